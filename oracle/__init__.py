@@ -1,0 +1,286 @@
+"""Oracle: plain, slow, FP64 CPU reference of the SLLBM time step (arXiv 2412.09051).
+
+TEST INFRASTRUCTURE.  Only tests/, the smoke check and the benchmark's CPU
+baseline may import this package.  It shares no code with the HIP library:
+
+* velocity set: 1D Gauss-Hermite rule from numpy (Sec. 3.2; 5 points give
+  quadrature degree 9), tensor product over dimensions;
+* support points: GLL from numpy's Legendre roots, GLC, equidistant (eq:intf);
+* nodal volumes: integrals of the nodal Lagrange functions by Gauss-Legendre;
+* the step itself: oracle/sllbm_oracle.c (tensor-product meshes),
+  full tensor Lagrange product formula, explicit Hermite-tensor equilibrium.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+from numpy.polynomial import hermite_e, legendre
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        _LIB = ctypes.CDLL(path)
+    return _LIB
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def _ptr(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+# --------------------------------------------------------------------------
+# Velocity space (Sec. 3.2)
+# --------------------------------------------------------------------------
+
+def gauss_hermite_1d(n: int = 5):
+    """Abscissae and weights of the n-point Gauss-Hermite rule for the weight
+    exp(-x^2/2)/sqrt(2 pi) (roots of the n-th Hermite polynomial), ascending."""
+    x, w = hermite_e.hermegauss(n)
+    w = w / math.sqrt(2.0 * math.pi)
+    o = np.argsort(x)
+    return x[o].copy(), w[o].copy()
+
+
+def velocity_set(dim: int, n: int = 5, T0: float = 1.0):
+    """Product-rule velocity set D{dim}V{n^dim}: zeta_i = sqrt(T0) x_a, index
+    i = a_x + n a_y + n^2 a_z over ascending abscissae; opposite reverses each a."""
+    x, w = gauss_hermite_1d(n)
+    Q = n ** dim
+    zeta = np.zeros((Q, dim))
+    wq = np.ones(Q)
+    opp = np.zeros(Q, dtype=np.int32)
+    for i in range(Q):
+        r = i
+        a = []
+        for _ in range(dim):
+            a.append(r % n)
+            r //= n
+        for d in range(dim):
+            zeta[i, d] = math.sqrt(T0) * x[a[d]]
+            wq[i] *= w[a[d]]
+        j = 0
+        for d in reversed(range(dim)):
+            j = j * n + (n - 1 - a[d])
+        opp[i] = j
+    return zeta, wq, opp
+
+
+def stroud_bound(degree: int, dim: int) -> int:
+    """Stroud's lower bound on the number of cubature points (Sec. 3.2 display)."""
+    k = degree // 2
+    return math.comb(k + dim, k)
+
+
+# --------------------------------------------------------------------------
+# Support points and nodal quadrature (eq:intf)
+# --------------------------------------------------------------------------
+
+def support_points(p: int, family: str = "gll") -> np.ndarray:
+    if family == "gll":
+        inner = legendre.Legendre.basis(p).deriv().roots() if p > 1 else np.array([])
+        x = np.concatenate([[-1.0], np.sort(np.real(inner)), [1.0]])
+        return x
+    if family == "glc":
+        return -np.cos(np.pi * np.arange(p + 1) / p)
+    if family == "equi":
+        return -1.0 + 2.0 * np.arange(p + 1) / p
+    raise ValueError(family)
+
+
+def lagrange_integrals(xref: np.ndarray) -> np.ndarray:
+    """int_{-1}^{1} l_j(xi) d xi by Gauss-Legendre with enough points to be exact."""
+    p = len(xref) - 1
+    xq, wq = legendre.leggauss(p + 1)
+    out = np.zeros(p + 1)
+    for j in range(p + 1):
+        v = np.ones_like(xq)
+        for m in range(p + 1):
+            if m != j:
+                v *= (xq - xref[m]) / (xref[j] - xref[m])
+        out[j] = np.sum(wq * v)
+    return out
+
+
+BC_CODES = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3}
+
+
+class OrTensor(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("p", ctypes.c_int), ("Q", ctypes.c_int),
+        ("zeta", _dp), ("w", _dp), ("opp", _ip), ("T0", ctypes.c_double),
+        ("xref", _dp),
+        ("ncell", ctypes.c_int * 3), ("edges", _dp * 3), ("periodic", ctypes.c_int * 3),
+        ("face_bc", (ctypes.c_int * 2) * 3),
+        ("n_bc", ctypes.c_int), ("bc_kind", _ip), ("bc_val", _dp),
+        ("gamma", ctypes.c_double), ("dt", ctypes.c_double),
+        ("relax_mode", ctypes.c_int), ("tau_bar", ctypes.c_double), ("mu_ref", ctypes.c_double),
+        ("T_ref", ctypes.c_double), ("mu_exp", ctypes.c_double),
+        ("force", ctypes.c_double * 3),
+        ("mass_fix", ctypes.c_int), ("mass_ref", ctypes.c_double),
+        ("node_vol", _dp),
+    ]
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class TensorOracle:
+    """FP64 reference of the SLLBM on a tensor-product (uniform or rectilinear) mesh.
+
+    mesh / phys are workloads.TensorMesh / workloads.Physics instances."""
+
+    def __init__(self, mesh, phys, n_gh: int = 5, vel=None):
+        self.mesh, self.phys = mesh, phys
+        self.dim = mesh.dim
+        if vel is None:
+            self.zeta, self.w, self.opp = velocity_set(mesh.dim, n_gh, phys.T0)
+        else:  # explicit (zeta, w, opp), e.g. the integer set of the classic-LBM limit
+            self.zeta = np.ascontiguousarray(vel[0], dtype=np.float64)
+            self.w = np.ascontiguousarray(vel[1], dtype=np.float64)
+            self.opp = np.ascontiguousarray(vel[2], dtype=np.int32)
+        self.Q = self.zeta.shape[0]
+        self.xref = support_points(mesh.p, mesh.nodes)
+        self.N = mesh.num_nodes
+        self._edges = [np.ascontiguousarray(e, dtype=np.float64) for e in mesh.edges]
+        nb = max(len(mesh.bcs), 1)
+        self._bc_kind = np.zeros(nb, dtype=np.int32)
+        self._bc_val = np.zeros((nb, 6))
+        for b, bc in enumerate(mesh.bcs):
+            self._bc_kind[b] = bc.kind
+            u = list(bc.u) + [0.0] * 3
+            self._bc_val[b] = [bc.rho, u[0], u[1], u[2], bc.T, bc.T_wall]
+        self.node_vol = self._node_volumes()
+        s = OrTensor()
+        s.dim, s.p, s.Q = mesh.dim, mesh.p, self.Q
+        s.zeta, s.w, s.opp = _ptr(self.zeta), _ptr(self.w), _ptr(self.opp, _ip)
+        s.T0 = phys.T0
+        s.xref = _ptr(self.xref)
+        for a in range(3):
+            if a < mesh.dim:
+                s.ncell[a] = mesh.ncell[a]
+                s.edges[a] = _ptr(self._edges[a])
+                s.periodic[a] = 1 if mesh.periodic(a) else 0
+                s.face_bc[a][0], s.face_bc[a][1] = mesh.face_bc[a]
+            else:
+                s.ncell[a] = 1
+                s.periodic[a] = 1
+                s.face_bc[a][0] = s.face_bc[a][1] = -1
+        s.n_bc = len(mesh.bcs)
+        s.bc_kind, s.bc_val = _ptr(self._bc_kind, _ip), _ptr(self._bc_val)
+        s.gamma, s.dt = phys.gamma, phys.dt
+        s.relax_mode, s.tau_bar = phys.relax_mode, phys.tau_bar
+        s.mu_ref, s.T_ref, s.mu_exp = phys.mu_ref, phys.T_ref, phys.mu_exp
+        f = list(phys.force) + [0.0] * 3
+        for a in range(3):
+            s.force[a] = f[a] if a < mesh.dim else 0.0
+        s.mass_fix, s.mass_ref = 0, 0.0
+        s.node_vol = _ptr(self.node_vol)
+        self._s = s
+        L = lib()
+        L.or_tensor_num_nodes.restype = ctypes.c_size_t
+        assert L.or_tensor_num_nodes(ctypes.byref(s)) == self.N
+
+    # ---- geometry -------------------------------------------------------
+    def _node_volumes(self):
+        m = self.mesh
+        li = lagrange_integrals(self.xref)
+        vols = []
+        for a in range(m.dim):
+            Na = m.axis_nodes(a)
+            v = np.zeros(Na)
+            e = m.edges[a]
+            for c in range(m.ncell[a]):
+                h = e[c + 1] - e[c]
+                for j in range(m.p + 1):
+                    n = c * m.p + j
+                    if m.periodic(a):
+                        n %= Na
+                    v[n] += 0.5 * h * li[j]
+            vols.append(v)
+        V = vols[0]
+        for a in range(1, m.dim):
+            V = np.multiply.outer(vols[a], V).reshape(-1)  # x fastest
+        return np.ascontiguousarray(V.reshape(-1))
+
+    def coords(self) -> np.ndarray:
+        xyz = np.zeros((self.N, self.dim))
+        lib().or_tensor_coords(ctypes.byref(self._s), _ptr(xyz))
+        return xyz
+
+    # ---- state ----------------------------------------------------------
+    def init(self, rho, u, T) -> np.ndarray:
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(self.N, self.dim)
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        pop = np.zeros(2 * self.Q * self.N)
+        lib().or_tensor_init(ctypes.byref(self._s), _ptr(rho), _ptr(u), _ptr(T), _ptr(pop))
+        return pop
+
+    def step(self, pop: np.ndarray, mass_ref: float | None = None) -> np.ndarray:
+        out = np.empty_like(pop)
+        s = self._s
+        s.mass_fix = 1 if mass_ref is not None else 0
+        s.mass_ref = float(mass_ref) if mass_ref is not None else 0.0
+        err = np.zeros(2, dtype=np.int64)
+        rc = lib().or_tensor_step(ctypes.byref(s), _ptr(np.ascontiguousarray(pop)), _ptr(out),
+                                  err.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        s.mass_fix = 0
+        if rc != 0:
+            raise OracleError(f"oracle step failed rc={rc} at node {err[0]} velocity {err[1]}")
+        return out
+
+    def run(self, pop: np.ndarray, nsteps: int, mass_fix_every: int = 0, mass_ref: float | None = None):
+        for n in range(nsteps):
+            fix = mass_fix_every > 0 and n > 0 and n % mass_fix_every == 0
+            pop = self.step(pop, mass_ref if fix else None)
+        return pop
+
+    def moments(self, pop: np.ndarray):
+        rho = np.zeros(self.N)
+        u = np.zeros((self.N, self.dim))
+        T = np.zeros(self.N)
+        lib().or_moments(ctypes.c_int(self.dim), ctypes.c_int(self.Q), _ptr(self.zeta),
+                         ctypes.c_double(self.phys.gamma), ctypes.c_size_t(self.N),
+                         _ptr(np.ascontiguousarray(pop)), _ptr(rho), _ptr(u), _ptr(T))
+        return rho, u, T
+
+    def totals(self, pop: np.ndarray):
+        """Nodal-quadrature totals: mass, momentum[dim], total energy."""
+        Q, N = self.Q, self.N
+        f = pop[: Q * N].reshape(Q, N)
+        g = pop[Q * N:].reshape(Q, N)
+        V = self.node_vol
+        mass = float(np.sum(V * f.sum(0)))
+        mom = [float(np.sum(V * (self.zeta[:, a:a + 1] * f).sum(0))) for a in range(self.dim)]
+        z2 = np.sum(self.zeta ** 2, axis=1)[:, None]
+        energy = float(np.sum(V * ((z2 * f).sum(0) + g.sum(0))))
+        return mass, mom, energy
+
+
+def equilibrium(dim: int, rho: float, u, T: float, gamma: float = 1.4, T0: float = 1.0, n_gh: int = 5):
+    """f^eq and g^eq of one state for every velocity of the D{dim}V{n^dim} set."""
+    zeta, w, _ = velocity_set(dim, n_gh, T0)
+    Q = zeta.shape[0]
+    feq = np.zeros(Q)
+    geq = np.zeros(Q)
+    uu = np.zeros(3)
+    uu[:dim] = u
+    lib().or_equilibrium(ctypes.c_int(dim), ctypes.c_int(Q), _ptr(zeta), _ptr(w), ctypes.c_double(T0),
+                         ctypes.c_double(gamma), ctypes.c_double(rho), _ptr(uu), ctypes.c_double(T),
+                         _ptr(feq), _ptr(geq))
+    return feq, geq

@@ -1,0 +1,220 @@
+"""Seeded synthetic inputs shared by the oracle and the HIP path.
+
+This module holds no arithmetic of the method: it only describes meshes
+(cell edges, boundary tags), physical parameters and initial nodal fields
+(density, velocity, temperature) as plain numbers and numpy arrays.  Both the
+oracle (tests) and the library (bench, smoke) receive exactly these arrays.
+
+Random numbers come from numpy's PCG64 with fixed seeds.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+# Largest Gauss-Hermite abscissa of the 5-point rule, sqrt(5 + sqrt(10)); used
+# only to pick time steps from a CFL number on the cell size.
+ZETA_MAX_GH5 = 2.8569700138728056
+
+BC_PERIODIC, BC_WALL, BC_INLET, BC_OUTLET = 0, 1, 2, 3
+NODES = {"gll": 0, "glc": 1, "equi": 2}
+
+
+@dataclass
+class BC:
+    kind: int
+    rho: float = 1.0
+    u: Sequence[float] = (0.0, 0.0, 0.0)
+    T: float = 1.0
+    T_wall: float = float("nan")   # NaN: plain bounce-back, no thermal condition
+
+
+@dataclass
+class TensorMesh:
+    dim: int
+    p: int
+    nodes: str                     # "gll" | "glc" | "equi"
+    ncell: Sequence[int]
+    edges: List[np.ndarray]        # per axis, ncell+1 monotone coordinates
+    face_bc: List[List[int]]       # per axis [low, high]: index into bcs or -1 (periodic)
+    bcs: List[BC] = field(default_factory=list)
+
+    def periodic(self, a: int) -> bool:
+        return self.face_bc[a][0] < 0
+
+    def axis_nodes(self, a: int) -> int:
+        return self.ncell[a] * self.p + (0 if self.periodic(a) else 1)
+
+    @property
+    def num_nodes(self) -> int:
+        n = 1
+        for a in range(self.dim):
+            n *= self.axis_nodes(a)
+        return n
+
+
+@dataclass
+class Physics:
+    gamma: float = 1.4
+    dt: float = 0.01
+    relax_mode: int = 0            # 0 constant tau_bar, 1 mu(T) law, 2 streaming only
+    tau_bar: float = 1.0
+    mu_ref: float = 0.0
+    T_ref: float = 1.0
+    mu_exp: float = 0.0
+    force: Sequence[float] = (0.0, 0.0, 0.0)
+    T0: float = 1.0
+
+
+def uniform_edges(n: int, lo: float, hi: float) -> np.ndarray:
+    return lo + (hi - lo) * np.arange(n + 1, dtype=np.float64) / n
+
+
+def tanh_edges(n: int, beta: float = 2.0) -> np.ndarray:
+    """Wall-normal channel edges on [0, 2]: y = 1 + tanh(beta (2 eta - 1)) / tanh(beta)."""
+    eta = np.arange(n + 1, dtype=np.float64) / n
+    y = 1.0 + np.tanh(beta * (2.0 * eta - 1.0)) / np.tanh(beta)
+    y[0], y[-1] = 0.0, 2.0
+    return y
+
+
+# --------------------------------------------------------------------------
+# C1: 2D periodic shear wave (and isentropic vortex), D2V25, p=4 GLL
+# --------------------------------------------------------------------------
+
+def shear_wave_case(ncell: int = 16, p: int = 4, nodes: str = "gll", tau_bar: float = 1.3,
+                    cfl: float = 0.5):
+    L = 2.0 * math.pi
+    mesh = TensorMesh(dim=2, p=p, nodes=nodes, ncell=(ncell, ncell),
+                      edges=[uniform_edges(ncell, 0.0, L), uniform_edges(ncell, 0.0, L)],
+                      face_bc=[[-1, -1], [-1, -1]])
+    h = L / ncell
+    phys = Physics(gamma=1.4, dt=cfl * h / ZETA_MAX_GH5, relax_mode=0, tau_bar=tau_bar)
+    return mesh, phys
+
+
+def shear_wave_fields(xyz: np.ndarray, amp: float = 0.01, U: Optional[float] = None,
+                      noise: float = 1e-3, seed: int = 1):
+    """u = (U, A sin x), rho = 1 + noise*U(-1,1), T = 1.  U defaults to Ma 0.5."""
+    if U is None:
+        U = 0.5 * math.sqrt(1.4)
+    n = xyz.shape[0]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rho = np.ones(n) + (noise * rng.uniform(-1.0, 1.0, n) if noise > 0 else 0.0)
+    u = np.zeros((n, 2))
+    u[:, 0] = U
+    u[:, 1] = amp * np.sin(xyz[:, 0])
+    T = np.ones(n)
+    return rho, u, T
+
+
+def vortex_case(ncell: int = 16, p: int = 4, nodes: str = "gll", tau_bar: float = 1.3, cfl: float = 0.5):
+    L = 10.0
+    mesh = TensorMesh(dim=2, p=p, nodes=nodes, ncell=(ncell, ncell),
+                      edges=[uniform_edges(ncell, 0.0, L), uniform_edges(ncell, 0.0, L)],
+                      face_bc=[[-1, -1], [-1, -1]])
+    phys = Physics(gamma=1.4, dt=cfl * (L / ncell) / ZETA_MAX_GH5, relax_mode=0, tau_bar=tau_bar)
+    return mesh, phys
+
+
+def vortex_fields(xyz: np.ndarray, eps: float = 2.0, gamma: float = 1.4, noise: float = 1e-3, seed: int = 1):
+    """Isentropic vortex of strength eps centred at (5, 5) on a Ma 0.5 stream in x."""
+    U = 0.5 * math.sqrt(gamma)
+    x = xyz[:, 0] - 5.0
+    y = xyz[:, 1] - 5.0
+    r2 = x * x + y * y
+    f = np.exp(0.5 * (1.0 - r2))
+    du = eps / (2.0 * math.pi) * f
+    u = np.stack([U - du * y, du * x], axis=1)
+    T = 1.0 - (gamma - 1.0) * eps ** 2 / (8.0 * gamma * math.pi ** 2) * np.exp(1.0 - r2)
+    rho = T ** (1.0 / (gamma - 1.0))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if noise > 0:
+        rho = rho + noise * rng.uniform(-1.0, 1.0, rho.shape[0])
+    return rho, u, T
+
+
+# --------------------------------------------------------------------------
+# C2: 3D periodic compressible Taylor-Green vortex, Ma 0.8, Re 400, p=3
+# --------------------------------------------------------------------------
+
+def tgv_case(ncell: int = 32, p: int = 3, nodes: str = "gll", cfl: float = 0.5, Re: float = 400.0,
+             Ma: float = 0.8):
+    L = 2.0 * math.pi
+    mesh = TensorMesh(dim=3, p=p, nodes=nodes, ncell=(ncell, ncell, ncell),
+                      edges=[uniform_edges(ncell, 0.0, L)] * 3,
+                      face_bc=[[-1, -1], [-1, -1], [-1, -1]])
+    U0 = Ma * math.sqrt(1.4)
+    phys = Physics(gamma=1.4, dt=cfl * (L / ncell) / ZETA_MAX_GH5, relax_mode=1,
+                   mu_ref=U0 / Re, T_ref=1.0, mu_exp=0.0)
+    return mesh, phys
+
+
+def tgv_fields(xyz: np.ndarray, Ma: float = 0.8):
+    U0 = Ma * math.sqrt(1.4)
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    u = np.stack([U0 * np.sin(x) * np.cos(y) * np.cos(z),
+                  -U0 * np.cos(x) * np.sin(y) * np.cos(z),
+                  np.zeros_like(x)], axis=1)
+    p = 1.0 + (U0 ** 2 / 16.0) * (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0)
+    T = np.ones_like(x)
+    rho = p / T
+    return rho, u, T
+
+
+# --------------------------------------------------------------------------
+# C4: 3D supersonic channel, isothermal walls at y = 0 and y = 2, tanh y-stretching
+# --------------------------------------------------------------------------
+
+def channel_case(ncell=(128, 96, 64), p: int = 2, nodes: str = "gll", Ma_b: float = 1.5, Re_b: float = 3000.0,
+                 Re_tau: float = 220.6, cfl: float = 0.9, beta: float = 2.0, T_wall: float = 1.0,
+                 box=(4.0 * math.pi, 2.0, 2.0 * math.pi)):
+    ex = uniform_edges(ncell[0], 0.0, box[0])
+    ey = tanh_edges(ncell[1], beta) * (box[1] / 2.0)
+    ez = uniform_edges(ncell[2], 0.0, box[2])
+    bcs = [BC(kind=BC_WALL, T_wall=T_wall)]
+    mesh = TensorMesh(dim=3, p=p, nodes=nodes, ncell=tuple(ncell), edges=[ex, ey, ez],
+                      face_bc=[[-1, -1], [0, 0], [-1, -1]], bcs=bcs)
+    hmin = float(np.min(np.diff(ey)))
+    u_b = Ma_b * math.sqrt(1.4 * T_wall)
+    mu_w = 1.0 * u_b * 1.0 / Re_b
+    F = 1.0 * Re_tau ** 2 * mu_w ** 2
+    phys = Physics(gamma=1.4, dt=cfl * hmin / ZETA_MAX_GH5, relax_mode=1, mu_ref=mu_w, T_ref=T_wall,
+                   mu_exp=0.7, force=(F, 0.0, 0.0))
+    return mesh, phys
+
+
+def channel_fields(xyz: np.ndarray, Ma_b: float = 1.5, T_wall: float = 1.0, amp: float = 0.05,
+                   kmax: int = 4, seed: int = 4, box=(4.0 * math.pi, 2.0, 2.0 * math.pi)):
+    """Poiseuille profile 1.5 u_b (1 - (y-1)^2) plus random-phase modes scaled by a parabola."""
+    u_b = Ma_b * math.sqrt(1.4 * T_wall)
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    par = 1.0 - (y - 1.0) ** 2
+    u = np.zeros((xyz.shape[0], 3))
+    u[:, 0] = 1.5 * u_b * par
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for comp in range(3):
+        pert = np.zeros_like(x)
+        for kx in range(1, kmax + 1):
+            for kz in range(1, kmax + 1):
+                ph = rng.uniform(0.0, 2.0 * math.pi, 2)
+                pert += np.sin(2 * math.pi * kx * x / box[0] + ph[0]) * np.sin(2 * math.pi * kz * z / box[2] + ph[1])
+        pert /= max(np.max(np.abs(pert)), 1e-30)
+        u[:, comp] += amp * u_b * par * pert
+    rho = np.ones(xyz.shape[0])
+    T = np.full(xyz.shape[0], T_wall)
+    return rho, u, T
+
+
+def random_fields(n: int, dim: int, seed: int, rho_amp=0.05, u_amp=0.2, T_amp=0.05, u_mean=None):
+    """Smooth-free random nodal state near rest: used by interpolation/BC unit tests."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rho = 1.0 + rho_amp * rng.uniform(-1.0, 1.0, n)
+    u = u_amp * rng.uniform(-1.0, 1.0, (n, dim))
+    if u_mean is not None:
+        u = u + np.asarray(u_mean)[None, :dim]
+    T = 1.0 + T_amp * rng.uniform(-1.0, 1.0, n)
+    return rho, u, T
