@@ -1,0 +1,185 @@
+/*
+ * sllbm.h - C ABI of the MI355X semi-Lagrangian lattice Boltzmann (SLLBM) library.
+ *
+ * The library advances the compressible SLLBM of Spelten, Wilde, Bedrunka, Reith and
+ * Foysi (arXiv 2412.09051) by one time step per call:
+ *   - streaming: every node x_k and velocity zeta_i takes the value of the order-p
+ *     Lagrange interpolant at the departure point x_k - dt zeta_i
+ *     (Sec. 3.1, SLLBM update display, eq:intf and the display after it);
+ *   - collision: BGK relaxation of the two population sets f and g towards the
+ *     4th-order Hermite equilibrium (Sec. 3.1, f^eq and g^eq displays);
+ *   - boundaries: equilibrium inlet (Sec. 3.3.1), bounce-back and isothermal wall
+ *     (Sec. 3.3.2, eq:thermalBC), zero-gradient outlet (Sec. 3.3.3), periodic.
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns 0 (SLLBM_OK) or a negative code; sllbm_last_error() returns a
+ *     thread-local message for the last failing call of the calling thread.
+ *   - Arguments are validated before anything is enqueued: on an error no work was
+ *     launched and no caller buffer was touched.
+ *   - Handles (sllbm_mesh, sllbm_plan) are owned by the library and must be released
+ *     with the matching *_destroy call.  A handle is not thread-safe: calls that use
+ *     one plan must be serialised (one host thread, one stream at a time), because the
+ *     plan owns a small device scratch area (reductions, mass-rescale factor).
+ *   - Population buffers are caller-owned device memory (e.g. torch tensors) holding
+ *     2*Q*N elements of the plan precision, laid out as pop[(s*Q + i)*N + k] with
+ *     s = 0 for f, s = 1 for g, i the velocity index, k the node index in library
+ *     order.  They must be 16-byte aligned.  pop_in and pop_out of a step must not
+ *     overlap.
+ *   - Library node order on tensor meshes: k = n_x + N_x (n_y + N_y n_z), x fastest,
+ *     where along a periodic axis N_a = ncell_a * p and along a bounded axis
+ *     N_a = ncell_a * p + 1 (the last node sits on the high face).
+ *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.  All
+ *     device work is asynchronous on that stream unless stated otherwise.
+ *   - Units: gas constant R = 1, c_v = 1/(gamma - 1); velocities are zeta = sqrt(T0) x
+ *     with x the Gauss-Hermite abscissae.
+ */
+#ifndef SLLBM_H
+#define SLLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SLLBM_OK = 0,
+  SLLBM_EINVAL = -1,       /* invalid argument, size or enum */
+  SLLBM_ENOMEM = -2,       /* host or device allocation failed */
+  SLLBM_EGEOM = -3,        /* a departure point cannot be placed (left the mesh untagged,
+                              reflected path leaves again, Newton inverse map failed) */
+  SLLBM_EHIP = -4,         /* a HIP runtime call failed, or no GPU is present */
+  SLLBM_EUNSUPPORTED = -5, /* valid input outside what the GPU path implements (e.g. Pr != 1) */
+  SLLBM_EUNSTABLE = -6     /* non-finite value, rho <= 0 or T <= 0 seen by sllbm_moments */
+};
+
+typedef struct sllbm_mesh_s *sllbm_mesh;
+typedef struct sllbm_plan_s *sllbm_plan;
+
+typedef enum { SLLBM_NODES_GLL = 0, SLLBM_NODES_GLC = 1, SLLBM_NODES_EQUI = 2 } sllbm_nodes;
+typedef enum { SLLBM_MESH_TENSOR = 0, SLLBM_MESH_CURVILINEAR = 1 } sllbm_mesh_kind;
+typedef enum { SLLBM_BC_PERIODIC = 0, SLLBM_BC_WALL = 1, SLLBM_BC_INLET = 2, SLLBM_BC_OUTLET = 3 } sllbm_bc_kind;
+typedef enum { SLLBM_F64 = 0, SLLBM_F32 = 1 } sllbm_prec;
+
+/* One boundary condition (Sec. 3.3).
+ *   WALL  : bounce-back (Sec. 3.3.2); T_wall finite adds the isothermal correction
+ *           of eq:thermalBC at every node where a trajectory hit this wall; NaN = none.
+ *   INLET : equilibrium inlet with state (rho, u, T) (Sec. 3.3.1).
+ *   OUTLET: zero-gradient outlet, mirrored departure point (Sec. 3.3.3). */
+typedef struct {
+  int kind;          /* sllbm_bc_kind */
+  double rho;
+  double u[3];
+  double T;
+  double T_wall;
+} sllbm_bc;
+
+/* Mesh description (eq:intf: cells with (p+1)^dim support points).  All pointers are
+ * host memory and are copied by sllbm_mesh_build.
+ *   TENSOR      : tensor product of 1D meshes; edges[a] holds ncell[a]+1 strictly
+ *                 increasing coordinates (uniform or stretched).  face_bc[a][0/1] is -1
+ *                 on both faces of a periodic axis, otherwise an index into bcs.  At
+ *                 most one axis may be bounded.
+ *   CURVILINEAR : dim = 2 isoparametric quads of order p: n_nodes unique nodes with
+ *                 node_xyz[k*2 + a]; cell_nodes[c*(p+1)^2 + j_x + (p+1) j_y] lists each
+ *                 cell's support points in reference order (xi fastest);
+ *                 cell_face_bc[c*4 + f] tags the faces xi=-1, xi=+1, eta=-1, eta=+1
+ *                 with -1 (interior) or an index into bcs.  Library node order is
+ *                 the caller's node order. */
+typedef struct {
+  int dim;        /* 2 or 3 */
+  int order_p;    /* 1..8 (GPU kernels: 2..4) */
+  int nodes;      /* sllbm_nodes: support-point family inside each cell */
+  int kind;       /* sllbm_mesh_kind */
+  int ncell[3];
+  const double *edges[3];
+  int face_bc[3][2];
+  int64_t n_nodes;
+  const double *node_xyz;
+  int64_t n_cells;
+  const int64_t *cell_nodes;
+  const int32_t *cell_face_bc;
+  int n_bc;
+  const sllbm_bc *bcs;
+} sllbm_mesh_desc;
+
+/* Build a mesh (host only, no GPU needed).  Returns EINVAL for malformed input. */
+int sllbm_mesh_build(const sllbm_mesh_desc *d, sllbm_mesh *out);
+/* Number of unique nodes; if xyz != NULL writes n_nodes*dim host doubles, library order. */
+int sllbm_mesh_nodes(sllbm_mesh m, int64_t *n_nodes, double *xyz);
+/* Integral of every nodal Lagrange function (the nodal quadrature weight V_k used for
+ * the totals and the mass rescaling); host output of n_nodes doubles. */
+int sllbm_mesh_volumes(sllbm_mesh m, double *vol);
+void sllbm_mesh_destroy(sllbm_mesh m);
+
+/* Discrete velocity set (Sec. 3.2). */
+typedef struct {
+  int dim, Q;
+  const double *zeta;        /* [Q][dim] */
+  const double *w;           /* [Q] */
+  const int32_t *opposite;   /* [Q] index of -zeta_i (bounce-back, Sec. 3.3.2) */
+  double T0;                 /* reference temperature of the Hermite expansion */
+} sllbm_velset;
+
+/* Product-rule Gauss-Hermite set D{dim}V{n^dim} (Sec. 3.2: n points give quadrature
+ * degree 2n-1; n = 5 gives degree 9).  Index i = a_x + n a_y + n^2 a_z over ascending
+ * abscissae.  Host outputs: zeta [Q*dim], w [Q], opp [Q] with Q = n^dim. */
+int sllbm_velset_gauss_hermite(int dim, int n_per_dim, double T0, double *zeta, double *w, int32_t *opp);
+
+/* Interpolation plan for (mesh, velocity set, dt, precision): for every node and
+ * velocity the departure point x_k - dt zeta_i, the boundary case that the backward
+ * path meets first, the source population and the interpolation weights
+ * (Sec. 3.1 interpolation display, Sec. 3.3).  Built on the host and uploaded to the
+ * GPU once; SLLBM_EGEOM names the offending node and velocity in the error message.
+ * Without a GPU the host part is still built (sllbm_plan_info works) and every launch
+ * returns SLLBM_EHIP.  GPU kernels exist for dim 2 and 3, p = 2..4, Q <= 128. */
+int sllbm_interp_plan(sllbm_mesh m, const sllbm_velset *v, double dt, int prec, sllbm_plan *out);
+
+typedef struct {
+  int64_t n_nodes;
+  int Q;
+  int dim, order_p, prec;
+  int64_t n_exceptions;      /* (node, velocity) pairs decided by a boundary */
+  int64_t n_thermal_nodes;   /* nodes that receive the isothermal correction */
+  int64_t table_bytes;       /* device bytes of the interpolation tables */
+  int has_device;            /* 1 if the tables are on a GPU */
+  int kernel;                /* 0 tensor-product, 1 CSR (curvilinear) */
+} sllbm_plan_info_t;
+int sllbm_plan_info(sllbm_plan p, sllbm_plan_info_t *info);
+void sllbm_plan_destroy(sllbm_plan p);
+
+/* Physical parameters of a step. */
+typedef struct {
+  double gamma;        /* c_v = 1/(gamma-1), R = 1 */
+  int relax_mode;      /* 0: constant tau_bar; 1: tau_bar = mu(T)/(rho T dt) + 1/2 with
+                          mu = mu_ref (T/T_ref)^mu_exp (tau = mu/p, Sec. 3.1; power law of
+                          Sec. 4.3); 2: streaming and boundary schemes only, no collision */
+  double tau_bar, mu_ref, T_ref, mu_exp;
+  double Pr;           /* must be 1 (the quasi-equilibrium term then vanishes): else EUNSUPPORTED */
+  double force[3];     /* body force per unit volume, Kupershtokh exact difference (Sec. 4.3) */
+  int mass_fix;        /* 1: scale all populations by mass_ref/M before streaming (Sec. 4.3) */
+  double mass_ref;
+} sllbm_params;
+
+/* Populations in equilibrium with nodal fields: f = f^eq(rho,u,T), g = g^eq.
+ * rho, T: device double [N]; u: device double [dim][N] (component-major). */
+int sllbm_init_equilibrium(sllbm_plan p, const sllbm_params *prm, const double *rho, const double *u,
+                           const double *T, void *pop, void *stream);
+
+/* One time step: pop_out <- collide(stream(pop_in)).  Both hold post-collision states. */
+int sllbm_step(sllbm_plan p, const sllbm_params *prm, const void *pop_in, void *pop_out, void *stream);
+
+/* Nodal rho, u ([dim][N]), T of a population set (eq:density, eq:momentum, energy display
+ * read as total energy), each output optional (NULL), device doubles.  If totals_host
+ * != NULL the call also reduces the nodal-quadrature totals [mass, momentum[dim], energy]
+ * (deterministic order), synchronises the stream and writes them to host memory; it
+ * returns SLLBM_EUNSTABLE if any node has a non-finite value, rho <= 0 or T <= 0. */
+int sllbm_moments(sllbm_plan p, const sllbm_params *prm, const void *pop, double *rho, double *u, double *T,
+                  double *totals_host, void *stream);
+
+const char *sllbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SLLBM_H */

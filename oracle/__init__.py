@@ -244,6 +244,23 @@ class TensorOracle:
             raise OracleError(f"oracle step failed rc={rc} at node {err[0]} velocity {err[1]}")
         return out
 
+    def step_nodes(self, pop: np.ndarray, nodes, mass_ref: float | None = None) -> np.ndarray:
+        """Post-collision populations at the listed nodes only: array [len(nodes)][2Q]."""
+        nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+        out = np.zeros((nodes.shape[0], 2 * self.Q))
+        s = self._s
+        s.mass_fix = 1 if mass_ref is not None else 0
+        s.mass_ref = float(mass_ref) if mass_ref is not None else 0.0
+        err = np.zeros(2, dtype=np.int64)
+        rc = lib().or_tensor_step_nodes(ctypes.byref(s), _ptr(np.ascontiguousarray(pop)),
+                                        nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        ctypes.c_int64(nodes.shape[0]), _ptr(out),
+                                        err.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        s.mass_fix = 0
+        if rc != 0:
+            raise OracleError(f"oracle step failed rc={rc} at node {err[0]} velocity {err[1]}")
+        return out
+
     def run(self, pop: np.ndarray, nsteps: int, mass_fix_every: int = 0, mass_ref: float | None = None):
         for n in range(nsteps):
             fix = mass_fix_every > 0 and n > 0 and n % mass_fix_every == 0

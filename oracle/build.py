@@ -13,7 +13,7 @@ def build(verbose=False):
     src = [os.path.join(HERE, f) for f in ("sllbm_oracle.c", "sllbm_oracle_curv.c", "sllbm_oracle_mlp.c")
            if os.path.exists(os.path.join(HERE, f))]
     out = os.path.join(HERE, "liboracle.so")
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-function", "-Wno-maybe-uninitialized",
            "-o", out + ".tmp"] + src + ["-lm"]
     if verbose:
         print(" ".join(cmd))

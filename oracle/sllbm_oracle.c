@@ -389,35 +389,99 @@ static void node_moments(int D, int Q, const double *zeta, double cv, const doub
   *T = (E - r * uu) / (2.0 * r * cv);
 }
 
-/* One SLLBM time step on a tensor-product mesh.  pop layout: [(s*Q + i)*N + k],
- * s = 0 for f, 1 for g.  On a geometry error the offending node and velocity are
- * written to err[0], err[1]. */
-int or_tensor_step(const or_tensor *m, const double *pin, double *pout, int64_t *err) {
+/* Post-collision populations of one node k (f into fo[Q], g into go[Q]) from the
+ * (already rescaled) input set src. */
+static int node_update(const or_tensor *m, const double *H, const int *Nax, const double *src,
+                       const double *inlet, size_t k, double *fo, double *go, int64_t *bad_i) {
   int D = m->dim, Q = m->Q;
-  int Nax[3] = {1, 1, 1};
-  for (int a = 0; a < D; a++) Nax[a] = axis_nodes(m, a);
   size_t N = or_tensor_num_nodes(m);
   double cv = 1.0 / (m->gamma - 1.0);
-  double *H = make_htab(D, Q, m->zeta, m->T0);
-
-  /* Global mass rescaling by mass_ref / M before streaming (Sec. 4.3, mass-loss
-   * remedy); M = sum_k V_k rho_k with V_k the integral of the nodal basis. */
-  const double *src = pin;
-  double *scaled = NULL;
-  if (m->mass_fix) {
-    double M = 0.0;
-    for (size_t k = 0; k < N; k++) {
-      double r = 0;
-      for (int i = 0; i < Q; i++) r += pin[(size_t)i * N + k];
-      M += m->node_vol[k] * r;
+  double xk[3];
+  node_xyz(m, Nax, k, xk);
+  double fs[OR_MAXQ], gs[OR_MAXQ], fe[OR_MAXQ], fe2[OR_MAXQ];
+  int thermal = 0;
+  double Tw = 0.0;
+  for (int i = 0; i < Q; i++) {
+    or_trace t;
+    int rc = trace(m, xk, i, &t);
+    if (rc != OR_OK) { *bad_i = i; return rc; }
+    if (t.kind == 1) {
+      fs[i] = inlet[(size_t)t.bc * 2 * Q + i];
+      gs[i] = inlet[(size_t)t.bc * 2 * Q + Q + i];
+    } else {
+      fs[i] = interp(m, src + (size_t)t.src * N, t.dp, Nax);
+      gs[i] = interp(m, src + ((size_t)Q + t.src) * N, t.dp, Nax);
     }
-    double c = m->mass_ref / M;
-    scaled = (double *)malloc(sizeof(double) * 2 * (size_t)Q * N);
-    for (size_t q = 0; q < 2 * (size_t)Q * N; q++) scaled[q] = c * pin[q];
-    src = scaled;
+    if (t.thermal) { thermal = 1; Tw = m->bc_val[t.bc * 6 + 5]; }
   }
+  double rho, u[3], T;
+  node_moments(D, Q, m->zeta, cv, fs, gs, &rho, u, &T);
+  if (thermal) {
+    /* eq:thermalBC: f_i += f^eq_i(rho,u,T_w) - f^eq_i(rho,u,T), same for g with
+     * g^eq; afterwards the node temperature is T_w. */
+    feq_all(D, Q, m->w, H, m->T0, rho, u, Tw, fe);
+    feq_all(D, Q, m->w, H, m->T0, rho, u, T, fe2);
+    for (int i = 0; i < Q; i++) {
+      fs[i] += fe[i] - fe2[i];
+      gs[i] += Tw * (2.0 * cv - D) * fe[i] - T * (2.0 * cv - D) * fe2[i];
+    }
+    T = Tw;
+  }
+  if (m->relax_mode == 2) {
+    for (int i = 0; i < Q; i++) { fo[i] = fs[i]; go[i] = gs[i]; }
+    return OR_OK;
+  }
+  /* Relaxation time: tau = mu/p with p = rho R T, R = 1, as a dimensionless
+   * tau_bar = tau/dt + 1/2 (Sec. 3.1; reading of the units). */
+  double tb = m->tau_bar;
+  if (m->relax_mode == 1) {
+    double mu = m->mu_ref * pow(T / m->T_ref, m->mu_exp);
+    tb = mu / (rho * T * m->dt) + 0.5;
+  }
+  feq_all(D, Q, m->w, H, m->T0, rho, u, T, fe);
+  double gfac = T * (2.0 * cv - D);
+  for (int i = 0; i < Q; i++) {
+    fo[i] = fs[i] - (fs[i] - fe[i]) / tb;
+    go[i] = gs[i] - (gs[i] - gfac * fe[i]) / tb;
+  }
+  int has_force = 0;
+  for (int a = 0; a < D; a++) if (m->force[a] != 0.0) has_force = 1;
+  if (has_force) {
+    /* Kupershtokh exact difference: delta h_i = h^eq(rho,u+du,T) - h^eq(rho,u,T),
+     * du = F dt / rho, added after the collision. */
+    double u2[3] = {u[0], u[1], u[2]};
+    for (int a = 0; a < D; a++) u2[a] += m->force[a] * m->dt / rho;
+    feq_all(D, Q, m->w, H, m->T0, rho, u2, T, fe2);
+    for (int i = 0; i < Q; i++) {
+      fo[i] += fe2[i] - fe[i];
+      go[i] += gfac * (fe2[i] - fe[i]);
+    }
+  }
+  return OR_OK;
+}
 
-  /* Equilibria of the inlet states (Sec. 3.3.1). */
+/* Input set for streaming: pin itself, or a copy rescaled by mass_ref / M (Sec. 4.3,
+ * mass-loss remedy) with M = sum_k V_k rho_k, V_k the integral of the nodal basis. */
+static double *prepare_source(const or_tensor *m, const double *pin) {
+  if (!m->mass_fix) return NULL;
+  size_t N = or_tensor_num_nodes(m);
+  int Q = m->Q;
+  double M = 0.0;
+  for (size_t k = 0; k < N; k++) {
+    double r = 0;
+    for (int i = 0; i < Q; i++) r += pin[(size_t)i * N + k];
+    M += m->node_vol[k] * r;
+  }
+  double c = m->mass_ref / M;
+  double *scaled = (double *)malloc(sizeof(double) * 2 * (size_t)Q * N);
+  for (size_t q = 0; q < 2 * (size_t)Q * N; q++) scaled[q] = c * pin[q];
+  return scaled;
+}
+
+/* Equilibria of the inlet states (Sec. 3.3.1). */
+static double *inlet_table(const or_tensor *m, const double *H) {
+  int D = m->dim, Q = m->Q;
+  double cv = 1.0 / (m->gamma - 1.0);
   double *inlet = (double *)calloc((size_t)(m->n_bc > 0 ? m->n_bc : 1) * 2 * Q, sizeof(double));
   for (int b = 0; b < m->n_bc; b++) {
     if (m->bc_kind[b] != OR_BC_INLET) continue;
@@ -426,85 +490,69 @@ int or_tensor_step(const or_tensor *m, const double *pin, double *pout, int64_t 
     for (int i = 0; i < Q; i++)
       inlet[(size_t)b * 2 * Q + Q + i] = v[4] * (2.0 * cv - D) * inlet[(size_t)b * 2 * Q + i];
   }
+  return inlet;
+}
 
+/* One SLLBM time step on a tensor-product mesh.  pop layout: [(s*Q + i)*N + k],
+ * s = 0 for f, 1 for g.  On a geometry error the offending node and velocity are
+ * written to err[0], err[1]. */
+int or_tensor_step(const or_tensor *m, const double *pin, double *pout, int64_t *err) {
+  int D = m->dim, Q = m->Q;
+  int Nax[3] = {1, 1, 1};
+  for (int a = 0; a < D; a++) Nax[a] = axis_nodes(m, a);
+  size_t N = or_tensor_num_nodes(m);
+  double *H = make_htab(D, Q, m->zeta, m->T0);
+  double *scaled = prepare_source(m, pin);
+  const double *src = scaled ? scaled : pin;
+  double *inlet = inlet_table(m, H);
   int status = OR_OK;
   int64_t ek = -1, ei = -1;
 #pragma omp parallel for schedule(dynamic, 64)
   for (size_t k = 0; k < N; k++) {
     if (status != OR_OK) continue;
-    double xk[3];
-    node_xyz(m, Nax, k, xk);
-    double fs[OR_MAXQ], gs[OR_MAXQ], fe[OR_MAXQ], fe2[OR_MAXQ];
-    int thermal = 0;
-    double Tw = 0.0;
-    for (int i = 0; i < Q; i++) {
-      or_trace t;
-      int rc = trace(m, xk, i, &t);
-      if (rc != OR_OK) {
+    double fo[OR_MAXQ], go[OR_MAXQ];
+    int64_t bi = -1;
+    int rc = node_update(m, H, Nax, src, inlet, k, fo, go, &bi);
+    if (rc != OR_OK) {
 #pragma omp critical
-        { status = rc; ek = (int64_t)k; ei = i; }
-        break;
-      }
-      if (t.kind == 1) {
-        fs[i] = inlet[(size_t)t.bc * 2 * Q + i];
-        gs[i] = inlet[(size_t)t.bc * 2 * Q + Q + i];
-      } else {
-        fs[i] = interp(m, src + (size_t)t.src * N, t.dp, Nax);
-        gs[i] = interp(m, src + ((size_t)Q + t.src) * N, t.dp, Nax);
-      }
-      if (t.thermal) { thermal = 1; Tw = m->bc_val[t.bc * 6 + 5]; }
-    }
-    if (status != OR_OK) continue;
-    double rho, u[3], T;
-    node_moments(D, Q, m->zeta, cv, fs, gs, &rho, u, &T);
-    if (thermal) {
-      /* eq:thermalBC: f_i += f^eq_i(rho,u,T_w) - f^eq_i(rho,u,T), same for g with
-       * g^eq; afterwards the node temperature is T_w. */
-      feq_all(D, Q, m->w, H, m->T0, rho, u, Tw, fe);
-      feq_all(D, Q, m->w, H, m->T0, rho, u, T, fe2);
-      for (int i = 0; i < Q; i++) {
-        fs[i] += fe[i] - fe2[i];
-        gs[i] += Tw * (2.0 * cv - D) * fe[i] - T * (2.0 * cv - D) * fe2[i];
-      }
-      T = Tw;
-    }
-    if (m->relax_mode == 2) {
-      for (int i = 0; i < Q; i++) {
-        pout[(size_t)i * N + k] = fs[i];
-        pout[((size_t)Q + i) * N + k] = gs[i];
-      }
+      { status = rc; ek = (int64_t)k; ei = bi; }
       continue;
     }
-    /* Relaxation time: tau = mu/p with p = rho R T, R = 1, as a dimensionless
-     * tau_bar = tau/dt + 1/2 (Sec. 3.1; reading of the units). */
-    double tb = m->tau_bar;
-    if (m->relax_mode == 1) {
-      double mu = m->mu_ref * pow(T / m->T_ref, m->mu_exp);
-      tb = mu / (rho * T * m->dt) + 0.5;
-    }
-    feq_all(D, Q, m->w, H, m->T0, rho, u, T, fe);
-    double gfac = T * (2.0 * cv - D);
     for (int i = 0; i < Q; i++) {
-      double fo = fs[i] - (fs[i] - fe[i]) / tb;
-      double go = gs[i] - (gs[i] - gfac * fe[i]) / tb;
-      pout[(size_t)i * N + k] = fo;
-      pout[((size_t)Q + i) * N + k] = go;
-    }
-    int has_force = 0;
-    for (int a = 0; a < D; a++) if (m->force[a] != 0.0) has_force = 1;
-    if (has_force) {
-      /* Kupershtokh exact difference: delta h_i = h^eq(rho,u+du,T) - h^eq(rho,u,T),
-       * du = F dt / rho, added after the collision. */
-      double u2[3] = {u[0], u[1], u[2]};
-      for (int a = 0; a < D; a++) u2[a] += m->force[a] * m->dt / rho;
-      feq_all(D, Q, m->w, H, m->T0, rho, u2, T, fe2);
-      for (int i = 0; i < Q; i++) {
-        pout[(size_t)i * N + k] += fe2[i] - fe[i];
-        pout[((size_t)Q + i) * N + k] += gfac * (fe2[i] - fe[i]);
-      }
+      pout[(size_t)i * N + k] = fo[i];
+      pout[((size_t)Q + i) * N + k] = go[i];
     }
   }
   if (err) { err[0] = ek; err[1] = ei; }
+  free(inlet);
+  free(scaled);
+  free(H);
+  return status;
+}
+
+/* The same step evaluated at a list of nodes only: out[j][2Q] (f then g) for node
+ * nodes[j].  Used to check large runs at sampled nodes. */
+int or_tensor_step_nodes(const or_tensor *m, const double *pin, const int64_t *nodes, int64_t n, double *out,
+                         int64_t *err) {
+  int D = m->dim, Q = m->Q;
+  int Nax[3] = {1, 1, 1};
+  for (int a = 0; a < D; a++) Nax[a] = axis_nodes(m, a);
+  double *H = make_htab(D, Q, m->zeta, m->T0);
+  double *scaled = prepare_source(m, pin);
+  const double *src = scaled ? scaled : pin;
+  double *inlet = inlet_table(m, H);
+  int status = OR_OK;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t j = 0; j < n; j++) {
+    if (status != OR_OK) continue;
+    int64_t bi = -1;
+    int rc = node_update(m, H, Nax, src, inlet, (size_t)nodes[j], out + (size_t)j * 2 * Q,
+                         out + (size_t)j * 2 * Q + Q, &bi);
+    if (rc != OR_OK) {
+#pragma omp critical
+      { status = rc; if (err) { err[0] = nodes[j]; err[1] = bi; } }
+    }
+  }
   free(inlet);
   free(scaled);
   free(H);

@@ -1,0 +1,315 @@
+// Device half of libsllbm (gfx950): plan upload, the fused stream + collide step,
+// equilibrium initialisation, moments and deterministic FP64 reductions.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+
+#include "sllbm_internal.h"
+#include "sllbm_kernels.h"
+
+using namespace sllbm;
+
+namespace {
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t _e = (expr);                                                               \
+    if (_e != hipSuccess) return fail(SLLBM_EHIP, "%s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+template <typename V>
+int upload(sllbm_plan_s *P, const std::vector<V> &h, const V **dptr) {
+  if (h.empty()) { *dptr = nullptr; return SLLBM_OK; }
+  void *d = nullptr;
+  size_t bytes = sizeof(V) * h.size();
+  hipError_t e = hipMalloc(&d, bytes);
+  if (e != hipSuccess) return fail(SLLBM_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  P->dev_allocs.push_back(d);
+  e = hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(SLLBM_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
+  P->table_bytes += (int64_t)bytes;
+  *dptr = (const V *)d;
+  return SLLBM_OK;
+}
+
+int check_params(const sllbm_plan_s *P, const sllbm_params *prm) {
+  if (!prm) return fail(SLLBM_EINVAL, "params is NULL");
+  if (!(prm->gamma > 1.0)) return fail(SLLBM_EINVAL, "gamma must be > 1");
+  if (prm->Pr != 1.0)
+    return fail(SLLBM_EUNSUPPORTED, "Pr = %g: only Pr = 1 (no quasi-equilibrium term) is implemented", prm->Pr);
+  if (prm->relax_mode < 0 || prm->relax_mode > 2) return fail(SLLBM_EINVAL, "relax_mode must be 0, 1 or 2");
+  if (prm->relax_mode == 0 && !(prm->tau_bar > 0.5))
+    return fail(SLLBM_EINVAL, "tau_bar must be > 1/2 (got %g)", prm->tau_bar);
+  if (prm->relax_mode == 1 && !(prm->mu_ref > 0 && prm->T_ref > 0))
+    return fail(SLLBM_EINVAL, "relax_mode 1 needs mu_ref > 0 and T_ref > 0");
+  if (prm->mass_fix && !(prm->mass_ref > 0)) return fail(SLLBM_EINVAL, "mass_fix needs mass_ref > 0");
+  for (int a = 0; a < 3; a++)
+    if (!std::isfinite(prm->force[a])) return fail(SLLBM_EINVAL, "force must be finite");
+  (void)P;
+  return SLLBM_OK;
+}
+
+StepArgs make_args(const sllbm_plan_s *P, const sllbm_params *prm) {
+  StepArgs a{};
+  int D = P->mesh.dim;
+  a.gamma = prm->gamma;
+  a.cv = 1.0 / (prm->gamma - 1.0);
+  a.gbase = 2.0 * a.cv - D;
+  a.dt = P->dt;
+  a.T0 = P->vel.T0;
+  a.inv_sqrtT0 = 1.0 / std::sqrt(P->vel.T0);
+  a.relax_mode = prm->relax_mode;
+  a.tau_bar = prm->tau_bar;
+  a.mu_ref = prm->mu_ref;
+  a.T_ref = prm->T_ref;
+  a.mu_exp = prm->mu_exp;
+  a.has_force = 0;
+  for (int d = 0; d < 3; d++) {
+    a.force[d] = d < D ? prm->force[d] : 0.0;
+    if (a.force[d] != 0.0) a.has_force = 1;
+  }
+  a.scale = nullptr;
+  a.inlet = P->inlet_dev;
+  return a;
+}
+
+size_t elem_size(const sllbm_plan_s *P) { return P->prec == SLLBM_F32 ? 4 : 8; }
+
+int check_pop(const sllbm_plan_s *P, const void *pop, const char *what) {
+  if (!pop) return fail(SLLBM_EINVAL, "%s is NULL", what);
+  if (((uintptr_t)pop) % 16) return fail(SLLBM_EINVAL, "%s must be 16-byte aligned", what);
+  return SLLBM_OK;
+}
+
+int require_device(const sllbm_plan_s *P) {
+  if (!P->has_device) return fail(SLLBM_EHIP, "plan has no GPU tables (no device was available when it was built)");
+  HIP_TRY(hipSetDevice(P->device));
+  return SLLBM_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan
+
+extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt, int prec, sllbm_plan *out) {
+  if (!ms || !v || !out) return fail(SLLBM_EINVAL, "interp_plan: NULL argument");
+  *out = nullptr;
+  const Mesh &m = ms->m;
+  if (v->dim != m.dim) return fail(SLLBM_EINVAL, "interp_plan: velocity set dim %d != mesh dim %d", v->dim, m.dim);
+  if (v->Q < 1 || v->Q > kMaxQ || !v->zeta || !v->w || !v->opposite || !(v->T0 > 0))
+    return fail(SLLBM_EINVAL, "interp_plan: velocity set needs 1 <= Q <= %d, T0 > 0, non-NULL arrays", kMaxQ);
+  for (int i = 0; i < v->Q; i++)
+    if (v->opposite[i] < 0 || v->opposite[i] >= v->Q)
+      return fail(SLLBM_EINVAL, "interp_plan: opposite[%d] out of range", i);
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(SLLBM_EINVAL, "interp_plan: dt must be > 0");
+  if (prec != SLLBM_F64 && prec != SLLBM_F32) return fail(SLLBM_EINVAL, "interp_plan: prec must be F64 or F32");
+
+  sllbm_plan_s *P = new (std::nothrow) sllbm_plan_s();
+  if (!P) return fail(SLLBM_ENOMEM, "interp_plan: out of host memory");
+  P->mesh = m;
+  P->dt = dt;
+  P->prec = prec;
+  VelSet &V = P->vel;
+  V.dim = v->dim;
+  V.Q = v->Q;
+  V.T0 = v->T0;
+  V.zeta.assign(v->zeta, v->zeta + v->Q * v->dim);
+  V.w.assign(v->w, v->w + v->Q);
+  V.opp.assign(v->opposite, v->opposite + v->Q);
+
+  HostTables t;
+  int rc;
+  if (m.kind == SLLBM_MESH_TENSOR) {
+    P->kernel = 0;
+    rc = build_tensor_tables(m, V, dt, t, &P->n_exceptions, &P->n_thermal);
+  } else {
+    P->kernel = 1;
+    rc = build_csr_tables(m, V, dt, t, &P->n_exceptions, &P->n_thermal);
+  }
+  if (rc != SLLBM_OK) { delete P; return rc; }
+  P->vol = node_volumes(m);
+
+  // velocity constants: zeta x,y,z, xi = zeta/sqrt(T0), |xi|^2, w
+  t.vel.assign(8 * (size_t)V.Q, 0.0);
+  for (int i = 0; i < V.Q; i++) {
+    double q = 0;
+    for (int d = 0; d < V.dim; d++) {
+      double z = V.zeta[i * V.dim + d];
+      t.vel[8 * i + d] = z;
+      t.vel[8 * i + 3 + d] = z / std::sqrt(V.T0);
+      q += (z / std::sqrt(V.T0)) * (z / std::sqrt(V.T0));
+    }
+    t.vel[8 * i + 6] = q;
+    t.vel[8 * i + 7] = V.w[i];
+  }
+  std::vector<double> inlet(5 * (size_t)std::max<size_t>(1, m.bcs.size()), 0.0);
+  for (size_t b = 0; b < m.bcs.size(); b++) {
+    inlet[5 * b + 0] = m.bcs[b].rho;
+    for (int d = 0; d < 3; d++) inlet[5 * b + 1 + d] = d < m.dim ? m.bcs[b].u[d] : 0.0;
+    inlet[5 * b + 4] = m.bcs[b].T;
+  }
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    P->has_device = 0;
+    *out = P;
+    return SLLBM_OK;
+  }
+  (void)hipGetDevice(&P->device);
+  P->has_device = 1;
+
+#define UP(vec, dst)                                  \
+  do {                                                \
+    int _rc = upload(P, vec, &(dst));                 \
+    if (_rc != SLLBM_OK) { sllbm_plan_destroy(P); return _rc; } \
+  } while (0)
+
+  const double *vel_d = nullptr, *inlet_d = nullptr, *vol_d = nullptr;
+  UP(t.vel, vel_d);
+  UP(inlet, inlet_d);
+  UP(P->vol, vol_d);
+  P->inlet_dev = inlet_d;
+  if (P->kernel == 0) {
+    DevTensorPlan &tp = P->tp;
+    tp.dim = m.dim;
+    tp.p = m.p;
+    tp.Q = V.Q;
+    tp.N = m.n_nodes;
+    for (int a = 0; a < 3; a++) {
+      DevAxis &ax = tp.ax[a];
+      ax.N = m.N[a];
+      ax.periodic = a < m.dim ? (m.periodic(a) ? 1 : 0) : 1;
+      std::vector<float> w32(t.w[a].size());
+      for (size_t r = 0; r < t.w[a].size(); r += m.p + 1) round_weights_f32(&t.w[a][r], m.p + 1, &w32[r]);
+      UP(t.start[a], ax.start);
+      UP(t.w[a], ax.w64);
+      UP(w32, ax.w32);
+      UP(t.ident[a], ax.ident);
+    }
+    UP(t.tab_reg, tp.tab_reg);
+    tp.nfaces = t.nfaces;
+    for (int f = 0; f < t.nfaces; f++) {
+      DevFace &F = tp.face[f];
+      F.axis = t.face_axis[f];
+      F.side = t.face_side[f];
+      F.depth = t.face_depth[f];
+      UP(t.face_e[f], F.e);
+      UP(t.face_Tw[f], F.Tw);
+    }
+    tp.vel = vel_d;
+    tp.vol = vol_d;
+  } else {
+    DevCsrPlan &cp = P->cp;
+    cp.dim = m.dim;
+    cp.p = m.p;
+    cp.Q = V.Q;
+    cp.N = m.n_nodes;
+    cp.npc = 1;
+    for (int d = 0; d < m.dim; d++) cp.npc *= (m.p + 1);
+    UP(m.cell_nodes, cp.cell_nodes);
+    UP(t.row_cell, cp.row_cell);
+    UP(t.row_src, cp.row_src);
+    std::vector<float> w32(t.row_w.size());
+    for (size_t r = 0; r < t.row_w.size(); r += cp.npc) round_weights_f32(&t.row_w[r], cp.npc, &w32[r]);
+    UP(t.row_w, cp.row_w64);
+    UP(w32, cp.row_w32);
+    UP(t.node_Tw, cp.node_Tw);
+    cp.vel = vel_d;
+    cp.vol = vol_d;
+  }
+#undef UP
+  int64_t nblk = (m.n_nodes + kBlock - 1) / kBlock;
+  P->scratch_len = kScratchHead + kRedWidth * nblk;
+  hipError_t e = hipMalloc((void **)&P->scratch, sizeof(double) * P->scratch_len);
+  if (e != hipSuccess) {
+    sllbm_plan_destroy(P);
+    return fail(SLLBM_ENOMEM, "hipMalloc scratch: %s", hipGetErrorString(e));
+  }
+  *out = P;
+  return SLLBM_OK;
+}
+
+extern "C" int sllbm_plan_info(sllbm_plan P, sllbm_plan_info_t *info) {
+  if (!P || !info) return fail(SLLBM_EINVAL, "plan_info: NULL argument");
+  info->n_nodes = P->mesh.n_nodes;
+  info->Q = P->vel.Q;
+  info->dim = P->mesh.dim;
+  info->order_p = P->mesh.p;
+  info->prec = P->prec;
+  info->n_exceptions = P->n_exceptions;
+  info->n_thermal_nodes = P->n_thermal;
+  info->table_bytes = P->table_bytes;
+  info->has_device = P->has_device;
+  info->kernel = P->kernel;
+  return SLLBM_OK;
+}
+
+extern "C" void sllbm_plan_destroy(sllbm_plan P) {
+  if (!P) return;
+  if (P->has_device) {
+    (void)hipSetDevice(P->device);
+    for (void *d : P->dev_allocs) (void)hipFree(d);
+    if (P->scratch) (void)hipFree(P->scratch);
+  }
+  delete P;
+}
+
+// ------------------------------------------------------------------ launches
+
+extern "C" int sllbm_init_equilibrium(sllbm_plan P, const sllbm_params *prm, const double *rho, const double *u,
+                                      const double *T, void *pop, void *stream) {
+  if (!P) return fail(SLLBM_EINVAL, "init_equilibrium: plan is NULL");
+  int rc = check_params(P, prm);
+  if (rc) return rc;
+  if (!rho || !u || !T) return fail(SLLBM_EINVAL, "init_equilibrium: rho, u and T are required");
+  if ((rc = check_pop(P, pop, "pop"))) return rc;
+  if ((rc = require_device(P))) return rc;
+  StepArgs a = make_args(P, prm);
+  return launch_init(P, a, rho, u, T, pop, (hipStream_t)stream);
+}
+
+extern "C" int sllbm_step(sllbm_plan P, const sllbm_params *prm, const void *pin, void *pout, void *stream) {
+  if (!P) return fail(SLLBM_EINVAL, "step: plan is NULL");
+  int rc = check_params(P, prm);
+  if (rc) return rc;
+  if ((rc = check_pop(P, pin, "pop_in")) || (rc = check_pop(P, pout, "pop_out"))) return rc;
+  size_t bytes = 2 * (size_t)P->vel.Q * (size_t)P->mesh.n_nodes * elem_size(P);
+  const char *a0 = (const char *)pin, *b0 = (const char *)pout;
+  if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(SLLBM_EINVAL, "step: pop_in and pop_out overlap");
+  if ((rc = require_device(P))) return rc;
+  StepArgs a = make_args(P, prm);
+  hipStream_t s = (hipStream_t)stream;
+  if (prm->mass_fix) {
+    rc = launch_mass_scale(P, pin, prm->mass_ref, s);
+    if (rc) return rc;
+    a.scale = P->scratch + kSlotScale;
+  }
+  return launch_step(P, a, pin, pout, s);
+}
+
+extern "C" int sllbm_moments(sllbm_plan P, const sllbm_params *prm, const void *pop, double *rho, double *u,
+                             double *T, double *totals_host, void *stream) {
+  if (!P) return fail(SLLBM_EINVAL, "moments: plan is NULL");
+  int rc = check_params(P, prm);
+  if (rc) return rc;
+  if ((rc = check_pop(P, pop, "pop"))) return rc;
+  if ((rc = require_device(P))) return rc;
+  StepArgs a = make_args(P, prm);
+  hipStream_t s = (hipStream_t)stream;
+  rc = launch_moments(P, a, pop, rho, u, T, totals_host != nullptr, s);
+  if (rc) return rc;
+  if (totals_host) {
+    double h[kRedWidth];
+    HIP_TRY(hipMemcpyAsync(h, P->scratch + kSlotTotals, sizeof(double) * kRedWidth, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int D = P->mesh.dim;
+    for (int q = 0; q < 2 + D; q++) totals_host[q] = h[q];
+    if (h[kRedWidth - 1] > 0)
+      return fail(SLLBM_EUNSTABLE, "moments: %.0f nodes with non-finite values, rho <= 0 or T <= 0", h[kRedWidth - 1]);
+  }
+  return SLLBM_OK;
+}

@@ -1,0 +1,168 @@
+// Internal structures of libsllbm shared by the host plan builder and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sllbm.h"
+
+namespace sllbm {
+
+constexpr int kMaxP = 8;      // host geometry supports p <= 8
+constexpr int kMaxQ = 128;    // device tables sized for Q <= 128
+constexpr int kMaxBC = 16;
+
+// Record an error for sllbm_last_error() and return the code.
+int fail(int code, const char *fmt, ...);
+
+// ---------------------------------------------------------------- velocity set
+struct VelSet {
+  int dim = 0, Q = 0;
+  double T0 = 1.0;
+  std::vector<double> zeta;   // [Q][dim]
+  std::vector<double> w;      // [Q]
+  std::vector<int32_t> opp;   // [Q]
+};
+
+// ---------------------------------------------------------------- mesh
+struct Mesh {
+  int dim = 0, p = 0, nodes = 0, kind = 0;
+  std::vector<double> xref;   // support points on [-1,1]
+  // tensor
+  int ncell[3] = {1, 1, 1};
+  std::vector<double> edges[3];
+  int face_bc[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
+  int N[3] = {1, 1, 1};       // nodes per axis
+  // curvilinear
+  std::vector<double> node_xyz;
+  std::vector<int64_t> cell_nodes;
+  std::vector<int32_t> cell_face_bc;
+  int64_t n_cells = 0;
+  // common
+  int64_t n_nodes = 0;
+  std::vector<sllbm_bc> bcs;
+  bool periodic(int a) const { return face_bc[a][0] < 0; }
+};
+
+// Support points of one cell on [-1,1] (GLL: ends plus roots of P_p'; GLC: -cos(pi j/p)).
+std::vector<double> support_points(int p, int family);
+// Barycentric Lagrange weights of the nodes xref at xi (exact 0/1 on a node).
+void lagrange_weights(const std::vector<double> &xref, double xi, double *w);
+// Integral over [-1,1] of each Lagrange basis function of xref.
+std::vector<double> lagrange_integrals(const std::vector<double> &xref);
+double tensor_node_coord(const Mesh &m, int a, int n);
+// Round one set of n interpolation weights to float so that their exact sum stays 1
+// (partition of unity) as closely as float allows: the residual of plain rounding is
+// moved into the weight that absorbs it with the smallest leftover.
+void round_weights_f32(const double *w, int n, float *out);
+
+// ---------------------------------------------------------------- plan
+enum ExcKind : int32_t { EXC_NONE = 0, EXC_WALL = 1, EXC_INLET = 2, EXC_OUTLET = 3 };
+
+// A (boundary layer, velocity) pair on a tensor mesh whose backward path leaves through
+// one face.  tab[a] selects the per-axis interpolation table for the axes parallel to
+// the face; along the face normal the stencil start and weights are explicit.
+struct ExcEntry {
+  int32_t kind;
+  int32_t src;        // source velocity (bounce-back: opposite), or bc index (inlet)
+  int32_t tab[3];     // per-axis table id (ignored along the face axis)
+  int32_t start;      // first stencil node along the face axis
+  double w[kMaxP + 1];
+  float w32[kMaxP + 1];  // the same weights rounded for FP32 plans (see round_weights_f32)
+};
+
+// Device view of a tensor-mesh plan; passed to kernels by value.
+struct DevAxis {
+  int N;
+  int periodic;
+  const int32_t *start;   // [ntab][N]
+  const double *w64;      // [ntab][N][p+1]
+  const float *w32;       // same, single precision
+  const int32_t *ident;   // [ntab] 1 = zero displacement (identity along this axis)
+};
+
+struct DevFace {
+  int axis, side;        // axis index and 0 = low, 1 = high
+  int depth;             // layers with entries (0 = face not bounded)
+  const ExcEntry *e;     // [depth][Q]
+  const double *Tw;      // [depth] wall temperature of a thermal layer, NaN otherwise
+};
+
+struct DevTensorPlan {
+  int dim, p, Q;
+  int64_t N;
+  DevAxis ax[3];
+  const int32_t *tab_reg;   // [3][Q] table id of the regular departure point
+  int nfaces;
+  DevFace face[2];
+  const double *vel;        // [Q][8]: zeta x,y,z, xi x,y,z (= zeta/sqrt(T0)), |xi|^2, w
+  const double *vol;        // [N] nodal volumes
+};
+
+// Device view of a CSR (curvilinear) plan.
+struct DevCsrPlan {
+  int dim, p, Q;
+  int64_t N;
+  int npc;                  // support points per cell, (p+1)^dim
+  const int64_t *cell_nodes;// [n_cells][npc]
+  const int32_t *row_cell;  // [Q][N] cell of the departure point, -1 inlet
+  const int32_t *row_src;   // [Q][N] source velocity, or bc index for inlet rows
+  const double *row_w64;    // [Q][N][npc]
+  const float *row_w32;
+  const double *node_Tw;    // [N] thermal-wall temperature, NaN = none
+  const double *vel;
+  const double *vol;
+};
+
+struct PlanHost;   // host-side tables (defined in sllbm_host.cpp)
+
+}  // namespace sllbm
+
+struct sllbm_mesh_s {
+  sllbm::Mesh m;
+};
+
+struct sllbm_plan_s {
+  sllbm::Mesh mesh;
+  sllbm::VelSet vel;
+  double dt = 0;
+  int prec = 0;
+  int kernel = 0;               // 0 tensor, 1 csr
+  int64_t n_exceptions = 0, n_thermal = 0, table_bytes = 0;
+  int has_device = 0;
+  int device = -1;
+  sllbm::DevTensorPlan tp{};
+  sllbm::DevCsrPlan cp{};
+  std::vector<void *> dev_allocs;
+  const double *inlet_dev = nullptr;  // [n_bc][5] inlet states (rho, u, T) on the device
+  double *scratch = nullptr;    // device scratch: reduction partials + scalars
+  int64_t scratch_len = 0;      // doubles
+  // host copies kept for the GPU-free info path
+  std::vector<double> vol;
+};
+
+namespace sllbm {
+// Host plan builders (fill the host vectors, then upload through the allocator callback).
+struct HostTables {
+  // tensor
+  std::vector<int32_t> start[3];
+  std::vector<double> w[3];
+  std::vector<int32_t> ident[3];
+  int ntab[3] = {0, 0, 0};
+  std::vector<int32_t> tab_reg;     // [3][Q]
+  int nfaces = 0;
+  int face_axis[2] = {0, 0}, face_side[2] = {0, 0}, face_depth[2] = {0, 0};
+  std::vector<ExcEntry> face_e[2];
+  std::vector<double> face_Tw[2];
+  // csr
+  std::vector<int32_t> row_cell, row_src;
+  std::vector<double> row_w;
+  std::vector<double> node_Tw;
+  // common
+  std::vector<double> vel;          // [Q][8]
+};
+int build_tensor_tables(const Mesh &m, const VelSet &v, double dt, HostTables &t, int64_t *n_exc, int64_t *n_th);
+int build_csr_tables(const Mesh &m, const VelSet &v, double dt, HostTables &t, int64_t *n_exc, int64_t *n_th);
+std::vector<double> node_volumes(const Mesh &m);
+}  // namespace sllbm

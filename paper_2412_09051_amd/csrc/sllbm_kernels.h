@@ -1,0 +1,36 @@
+// Launch interface between the C-ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sllbm_internal.h"
+
+namespace sllbm {
+
+constexpr int kBlock = 256;        // threads per block of the node-parallel kernels
+constexpr int kRedWidth = 8;       // doubles per block partial: mass, momentum[3], energy, -, -, bad
+constexpr int kScratchHead = 64;   // scratch doubles before the block partials
+constexpr int kSlotTotals = 0;     // [kRedWidth] final totals
+constexpr int kSlotScale = 16;     // mass-rescale factor mass_ref / M
+constexpr int kSlotMass = 24;      // final mass of the rescale reduction
+
+// Step parameters as the kernels see them (all derived on the host per call).
+struct StepArgs {
+  double gamma, cv, gbase;         // gbase = 2 c_v - D  (g^eq = T gbase f^eq)
+  double dt, T0, inv_sqrtT0;
+  int relax_mode;
+  double tau_bar, mu_ref, T_ref, mu_exp;
+  double force[3];
+  int has_force;
+  const double *scale;             // device mass-rescale factor, or nullptr
+  const double *inlet;             // device [n_bc][5] inlet states
+};
+
+int launch_init(sllbm_plan_s *P, const StepArgs &a, const double *rho, const double *u, const double *T, void *pop,
+                hipStream_t s);
+int launch_step(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout, hipStream_t s);
+int launch_moments(sllbm_plan_s *P, const StepArgs &a, const void *pop, double *rho, double *u, double *T,
+                   bool totals, hipStream_t s);
+int launch_mass_scale(sllbm_plan_s *P, const void *pop, double mass_ref, hipStream_t s);
+
+}  // namespace sllbm

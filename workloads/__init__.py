@@ -142,15 +142,19 @@ def vortex_fields(xyz: np.ndarray, eps: float = 2.0, gamma: float = 1.4, noise: 
 # --------------------------------------------------------------------------
 
 def tgv_case(ncell: int = 32, p: int = 3, nodes: str = "gll", cfl: float = 0.5, Re: float = 400.0,
-             Ma: float = 0.8):
+             Ma: float = 0.8, dt: Optional[float] = None):
     L = 2.0 * math.pi
     mesh = TensorMesh(dim=3, p=p, nodes=nodes, ncell=(ncell, ncell, ncell),
                       edges=[uniform_edges(ncell, 0.0, L)] * 3,
                       face_bc=[[-1, -1], [-1, -1], [-1, -1]])
     U0 = Ma * math.sqrt(1.4)
-    phys = Physics(gamma=1.4, dt=cfl * (L / ncell) / ZETA_MAX_GH5, relax_mode=1,
+    phys = Physics(gamma=1.4, dt=dt if dt is not None else cfl * (L / ncell) / ZETA_MAX_GH5, relax_mode=1,
                    mu_ref=U0 / Re, T_ref=1.0, mu_exp=0.0)
     return mesh, phys
+
+
+# time step of the 32^3-cell configuration (CFL 0.5 on its cell size)
+TGV_DT = 0.5 * (2.0 * math.pi / 32) / ZETA_MAX_GH5
 
 
 def tgv_fields(xyz: np.ndarray, Ma: float = 0.8):
