@@ -32,6 +32,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--kernel", choices=["auto", "gather", "tiled"], default="auto")
     return ap.parse_args()
 
 
@@ -63,7 +64,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def gpu_leg(prec, steps, warmup, ncell):
+KERNEL_NAMES = {0: "k_step_gather", 2: "k_step_tile"}
+
+
+def gpu_leg(prec, steps, warmup, ncell, kernel="auto"):
     import torch
     import numpy as np
     import paper_2412_09051_amd as S
@@ -72,6 +76,9 @@ def gpu_leg(prec, steps, warmup, ncell):
     m = S.sllbm_mesh_build(mesh)
     vs = S.sllbm_velset_gauss_hermite(3, 5, phys.T0)
     plan = S.sllbm_interp_plan(m, vs, phys.dt, S.SLLBM_F32 if prec == "f32" else S.SLLBM_F64)
+    if kernel != "auto":
+        S.sllbm_plan_select_kernel(plan, {"gather": 1, "tiled": 2}[kernel])
+    kname = KERNEL_NAMES[S.sllbm_plan_info(plan)["kernel"]]
     prm = S.Params.from_physics(phys)
     N, Q = plan.N, plan.Q
     xyz = S.sllbm_mesh_nodes(m)
@@ -114,7 +121,7 @@ def gpu_leg(prec, steps, warmup, ncell):
     return {
         "N": N, "Q": Q, "ms_per_step": total_ms / steps, "wall_s": wall, "gqups": gqups,
         "avg_launch_ms": avg_launch_ms, "achieved_GBs": achieved, "alg_bytes_per_launch": alg_bytes,
-        "finite": ok, "mass": float(tot[0]),
+        "finite": ok, "mass": float(tot[0]), "kernel": kname,
     }
 
 
@@ -143,8 +150,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    r64 = gpu_leg("f64", args.steps, args.warmup, args.ncell)
-    r32 = None if args.no_fp32 else gpu_leg("f32", args.steps, args.warmup, args.ncell)
+    r64 = gpu_leg("f64", args.steps, args.warmup, args.ncell, args.kernel)
+    r32 = None if args.no_fp32 else gpu_leg("f32", args.steps, args.warmup, args.ncell, args.kernel)
     cpu = None if args.no_cpu else cpu_leg(args.ncell, args.cpu_steps)
     traffic = traffic_from_profiles("f64")
     out = {
@@ -165,7 +172,7 @@ def main():
                    "nodes": r64["N"], "Q": r64["Q"], "order_p": 3, "velocity_set": "D3V125"},
         "roofline": {"bound": "hbm", "achieved": round(r64["achieved_GBs"], 2), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(r64["achieved_GBs"] / PEAK_HBM_GBS, 4),
-                     "traffic": traffic, "kernel": "k_step_gather<double,3,3>",
+                     "traffic": traffic, "kernel": r64["kernel"] + "<double,3,3>",
                      "alg_bytes_per_launch": r64["alg_bytes_per_launch"],
                      "avg_launch_ms": round(r64["avg_launch_ms"], 4)},
         "cpu_baseline": cpu,
@@ -175,7 +182,7 @@ def main():
         out["fp32"] = {"value": round(r32["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(r32["ms_per_step"], 4),
                        "roofline": {"bound": "hbm", "achieved": round(r32["achieved_GBs"], 2), "peak": PEAK_HBM_GBS,
                                     "unit": "GB/s", "frac": round(r32["achieved_GBs"] / PEAK_HBM_GBS, 4),
-                                    "kernel": "k_step_gather<float,3,3>",
+                                    "kernel": r32["kernel"] + "<float,3,3>",
                                     "avg_launch_ms": round(r32["avg_launch_ms"], 4)}}
     print(json.dumps(out), flush=True)
 

@@ -143,9 +143,15 @@ typedef struct {
   int64_t n_thermal_nodes;   /* nodes that receive the isothermal correction */
   int64_t table_bytes;       /* device bytes of the interpolation tables */
   int has_device;            /* 1 if the tables are on a GPU */
-  int kernel;                /* 0 tensor-product, 1 CSR (curvilinear) */
+  int kernel;                /* step kernel in use: 0 tensor-product per-node gather,
+                                1 CSR (curvilinear), 2 tensor-product LDS-tiled */
 } sllbm_plan_info_t;
 int sllbm_plan_info(sllbm_plan p, sllbm_plan_info_t *info);
+/* Choose the step kernel of a tensor-product plan: 0 automatic (tiled when it applies),
+ * 1 the per-node gather kernel, 2 the LDS-tiled kernel (SLLBM_EUNSUPPORTED when a
+ * departure stencil leaves the one-cell halo the tile stages, e.g. CFL > 1).  Both
+ * compute the same step; the choice exists for testing and measurement. */
+int sllbm_plan_select_kernel(sllbm_plan p, int kernel);
 void sllbm_plan_destroy(sllbm_plan p);
 
 /* Physical parameters of a step. */

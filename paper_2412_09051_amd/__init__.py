@@ -78,7 +78,8 @@ class sllbm_params(ctypes.Structure):
 
 _lib.sllbm_last_error.restype = ctypes.c_char_p
 for _name in ("sllbm_mesh_build", "sllbm_mesh_nodes", "sllbm_mesh_volumes", "sllbm_velset_gauss_hermite",
-              "sllbm_interp_plan", "sllbm_plan_info", "sllbm_init_equilibrium", "sllbm_step", "sllbm_moments"):
+              "sllbm_interp_plan", "sllbm_plan_info", "sllbm_plan_select_kernel", "sllbm_init_equilibrium",
+              "sllbm_step", "sllbm_moments"):
     getattr(_lib, _name).restype = ctypes.c_int
 _lib.sllbm_mesh_destroy.restype = None
 _lib.sllbm_plan_destroy.restype = None
@@ -247,6 +248,11 @@ def sllbm_interp_plan(m: Mesh, velset: dict, dt: float, prec: int = SLLBM_F64) -
     return Plan(h, m, velset, dt, prec)
 
 
+def sllbm_plan_select_kernel(plan: Plan, kernel: int) -> None:
+    """0 automatic, 1 per-node gather kernel, 2 LDS-tiled kernel."""
+    _check(_lib.sllbm_plan_select_kernel(plan.handle, ctypes.c_int(kernel)), "sllbm_plan_select_kernel")
+
+
 def sllbm_plan_info(plan: Plan) -> dict:
     info = sllbm_plan_info_t()
     _check(_lib.sllbm_plan_info(plan.handle, ctypes.byref(info)), "sllbm_plan_info")
@@ -311,5 +317,5 @@ def sllbm_moments(plan: Plan, params: Params, pop, rho=None, u=None, T=None, tot
 
 
 __all__ = ["sllbm_velset_gauss_hermite", "sllbm_mesh_build", "sllbm_mesh_nodes", "sllbm_mesh_volumes",
-           "sllbm_interp_plan", "sllbm_plan_info", "sllbm_init_equilibrium", "sllbm_step", "sllbm_moments",
+           "sllbm_interp_plan", "sllbm_plan_info", "sllbm_plan_select_kernel", "sllbm_init_equilibrium", "sllbm_step", "sllbm_moments",
            "Params", "Plan", "Mesh", "SllbmError", "SLLBM_F64", "SLLBM_F32", "LIB_PATH"]

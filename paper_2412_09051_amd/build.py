@@ -1,6 +1,7 @@
 """Build libsllbm.so (HIP for gfx950) in-tree.
 
-Usage: python -m paper_2412_09051_amd.build [-v]
+Usage: python paper_2412_09051_amd/build.py [-v]   (by path: importing the package
+loads the library this script builds)
 """
 import os
 import shutil
@@ -12,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsllbm.so")
 
-SOURCES = ["sllbm_host.cpp", "sllbm_csr.cpp", "sllbm_device.hip", "sllbm_kernels.hip"]
+SOURCES = ["sllbm_host.cpp", "sllbm_csr.cpp", "sllbm_device.hip", "sllbm_kernels.hip", "sllbm_tile.hip"]
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU ops.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
@@ -25,7 +26,7 @@ def hipcc():
     return h
 
 
-def build(verbose=False, jobs=4):
+def build(verbose=False, jobs=4, defines=()):
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
@@ -34,7 +35,7 @@ def build(verbose=False, jobs=4):
         s = os.path.join(CSRC, src)
         o = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc()] + HIPFLAGS + lang + ["-c", s, "-o", o]
+        cmd = [hipcc()] + HIPFLAGS + ["-D" + d for d in defines] + lang + ["-c", s, "-o", o]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT), src))
@@ -58,4 +59,4 @@ def build(verbose=False, jobs=4):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, defines=[a[2:] for a in sys.argv[1:] if a.startswith("-D")]))

@@ -131,6 +131,10 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
   }
   if (rc != SLLBM_OK) { delete P; return rc; }
   P->vol = node_volumes(m);
+  if (P->kernel == 0) {
+    int c[3];
+    P->tile_ok = tile_cells(m.dim, m.p, c) && tile_eligible(m, t, c) ? 1 : 0;
+  }
 
   // velocity constants: zeta x,y,z, xi = zeta/sqrt(T0), |xi|^2, w
   t.vel.assign(8 * (size_t)V.Q, 0.0);
@@ -229,6 +233,13 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
     sllbm_plan_destroy(P);
     return fail(SLLBM_ENOMEM, "hipMalloc scratch: %s", hipGetErrorString(e));
   }
+  if (P->tile_ok) {
+    e = hipMalloc((void **)&P->nstate, sizeof(double) * 6 * (size_t)m.n_nodes);
+    if (e != hipSuccess) {
+      sllbm_plan_destroy(P);
+      return fail(SLLBM_ENOMEM, "hipMalloc node state: %s", hipGetErrorString(e));
+    }
+  }
   *out = P;
   return SLLBM_OK;
 }
@@ -244,7 +255,16 @@ extern "C" int sllbm_plan_info(sllbm_plan P, sllbm_plan_info_t *info) {
   info->n_thermal_nodes = P->n_thermal;
   info->table_bytes = P->table_bytes;
   info->has_device = P->has_device;
-  info->kernel = P->kernel;
+  info->kernel = P->kernel == 1 ? 1 : ((P->tile_ok && P->kernel_choice != 1) ? 2 : 0);
+  return SLLBM_OK;
+}
+
+extern "C" int sllbm_plan_select_kernel(sllbm_plan P, int kernel) {
+  if (!P) return fail(SLLBM_EINVAL, "plan_select_kernel: plan is NULL");
+  if (kernel < 0 || kernel > 2) return fail(SLLBM_EINVAL, "plan_select_kernel: kernel must be 0, 1 or 2");
+  if (kernel == 2 && !P->tile_ok)
+    return fail(SLLBM_EUNSUPPORTED, "plan_select_kernel: the tiled kernel does not apply to this plan");
+  P->kernel_choice = kernel;
   return SLLBM_OK;
 }
 
@@ -254,6 +274,7 @@ extern "C" void sllbm_plan_destroy(sllbm_plan P) {
     (void)hipSetDevice(P->device);
     for (void *d : P->dev_allocs) (void)hipFree(d);
     if (P->scratch) (void)hipFree(P->scratch);
+    if (P->nstate) (void)hipFree(P->nstate);
   }
   delete P;
 }

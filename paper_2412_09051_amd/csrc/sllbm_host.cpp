@@ -295,7 +295,9 @@ struct AxisBuilder {
           out = true;
         }
         if (out) {
-          start = 0;
+          // nearest in-range cell, so that stencil starts stay non-decreasing along the
+          // axis and a tile's departure region stays local
+          start = (x < lo()) ? 0 : (m.ncell[a] - 1) * p;
           for (int j = 0; j <= p; j++) w[j] = 0.0;
         } else {
           int c;
@@ -640,3 +642,44 @@ extern "C" int sllbm_mesh_volumes(sllbm_mesh ms, double *vol) {
 }
 
 extern "C" void sllbm_mesh_destroy(sllbm_mesh m) { delete m; }
+
+namespace sllbm {
+
+bool tile_cells(int D, int P, int c[3]) {
+  // keep in step with TileShape<D, P> of the tiled kernel
+  static const int shape[2][3][3] = {{{8, 8, 1}, {8, 4, 1}, {8, 4, 1}}, {{4, 4, 4}, {4, 4, 2}, {2, 2, 2}}};
+  if (D < 2 || D > 3 || P < 2 || P > 4) return false;
+  for (int a = 0; a < 3; a++) c[a] = shape[D - 2][P - 2][a];
+  return true;
+}
+
+bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]) {
+  int P = m.p;
+  for (int a = 0; a < m.dim; a++) {
+    int T = c[a] * P, N = m.N[a];
+    if (m.periodic(a) && N <= T + P) return false;
+    std::vector<char> used(t.ntab[a], 0);
+    for (size_t q = 0; q < t.tab_reg.size() / 3; q++) used[t.tab_reg[a * (t.tab_reg.size() / 3) + q]] = 1;
+    for (int tb = 0; tb < t.ntab[a]; tb++) {
+      if (!used[tb] || t.ident[a][tb]) continue;
+      for (int n0 = 0; n0 < N; n0 += T) {
+        int v = std::min(T, N - n0);
+        int lo = 1 << 30, hi = -(1 << 30), first = 0, last = 0;
+        for (int k = 0; k < v; k++) {
+          int r = t.start[a][(size_t)tb * N + n0 + k] - n0;
+          if (r > T) r -= N;
+          else if (r < -P) r += N;
+          if (r < -P || r > T) return false;
+          lo = std::min(lo, r);
+          hi = std::max(hi, r);
+          if (k == 0) first = r;
+          last = r;
+        }
+        if (first != lo || last != hi || hi - lo > T) return false;
+      }
+    }
+  }
+  return true;
+}
+
+}  // namespace sllbm

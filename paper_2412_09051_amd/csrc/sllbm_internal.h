@@ -132,11 +132,14 @@ struct sllbm_plan_s {
   int64_t n_exceptions = 0, n_thermal = 0, table_bytes = 0;
   int has_device = 0;
   int device = -1;
+  int tile_ok = 0;              // the LDS-tiled kernel applies to this plan
+  int kernel_choice = 0;        // 0 auto, 1 baseline gather, 2 tiled
   sllbm::DevTensorPlan tp{};
   sllbm::DevCsrPlan cp{};
   std::vector<void *> dev_allocs;
   const double *inlet_dev = nullptr;  // [n_bc][5] inlet states (rho, u, T) on the device
   double *scratch = nullptr;    // device scratch: reduction partials + scalars
+  double *nstate = nullptr;     // tiled kernel: node state between its two launches, [6][N]
   int64_t scratch_len = 0;      // doubles
   // host copies kept for the GPU-free info path
   std::vector<double> vol;
@@ -165,4 +168,9 @@ struct HostTables {
 int build_tensor_tables(const Mesh &m, const VelSet &v, double dt, HostTables &t, int64_t *n_exc, int64_t *n_th);
 int build_csr_tables(const Mesh &m, const VelSet &v, double dt, HostTables &t, int64_t *n_exc, int64_t *n_th);
 std::vector<double> node_volumes(const Mesh &m);
+// Tile shape (cells per axis) of the LDS-tiled kernel for (dim, p), or false.
+bool tile_cells(int D, int P, int c[3]);
+// True if every regular departure stencil of a cell-aligned tile of c[] cells stays in
+// the one-cell halo that the tiled kernel stages.
+bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]);
 }  // namespace sllbm

@@ -26,6 +26,16 @@ struct StepArgs {
   const double *inlet;             // device [n_bc][5] inlet states
 };
 
+// Cell-aligned tile (cells per axis) of the LDS-tiled step kernel for (dim, order).
+template <int D, int P> struct TileShape;
+template <> struct TileShape<2, 2> { static constexpr int CX = 8, CY = 8, CZ = 1; };
+template <> struct TileShape<2, 3> { static constexpr int CX = 8, CY = 4, CZ = 1; };
+template <> struct TileShape<2, 4> { static constexpr int CX = 8, CY = 4, CZ = 1; };
+template <> struct TileShape<3, 2> { static constexpr int CX = 4, CY = 4, CZ = 4; };
+template <> struct TileShape<3, 3> { static constexpr int CX = 4, CY = 4, CZ = 2; };
+template <> struct TileShape<3, 4> { static constexpr int CX = 2, CY = 2, CZ = 2; };
+
+int launch_step_tile(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout, hipStream_t s);
 int launch_init(sllbm_plan_s *P, const StepArgs &a, const double *rho, const double *u, const double *T, void *pop,
                 hipStream_t s);
 int launch_step(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout, hipStream_t s);

@@ -15,6 +15,7 @@
 
 #include <cmath>
 
+#include "sllbm_device_common.h"
 #include "sllbm_kernels.h"
 
 namespace sllbm {
@@ -24,47 +25,6 @@ namespace sllbm {
     hipError_t _e = (expr);                                                               \
     if (_e != hipSuccess) return fail(SLLBM_EHIP, "%s: %s", #expr, hipGetErrorString(_e)); \
   } while (0)
-
-// ------------------------------------------------------------------ equilibrium
-// Closed form of the 4th-order Hermite expansion (f^eq display, N = 4) in the scaled
-// variables xi = zeta/sqrt(T0), ut = u/sqrt(T0), t = T/T0 - 1, s = xi.ut, q = |xi|^2:
-//   f^eq / (w rho) = c0 + c1 s + c2 s^2 + s^3/6 + s^4/24
-// with c0 = A0 + A1 q + A2 q^2, c1 = B0 + B1 q, c2 = C0 + C1 q (per-node constants).
-struct EqNode {
-  double rho, ux, uy, uz;
-  double A0, A1, A2, B0, B1, C0, C1;
-};
-
-__device__ __forceinline__ EqNode eq_prepare(double rho, double u0, double u1, double u2, double T,
-                                             const StepArgs &a, int D) {
-  EqNode e;
-  e.rho = rho;
-  e.ux = u0 * a.inv_sqrtT0;
-  e.uy = u1 * a.inv_sqrtT0;
-  e.uz = u2 * a.inv_sqrtT0;
-  double U = e.ux * e.ux + e.uy * e.uy + e.uz * e.uz;
-  double t = T / a.T0 - 1.0;
-  double Dd = (double)D;
-  e.A0 = 1.0 - 0.5 * U - 0.5 * t * Dd + 0.125 * U * U + 0.25 * t * U * (Dd + 2.0) + 0.125 * t * t * Dd * (Dd + 2.0);
-  e.A1 = 0.5 * t - 0.25 * t * U - 0.25 * t * t * (Dd + 2.0);
-  e.A2 = 0.125 * t * t;
-  e.B0 = 1.0 - 0.5 * U - 0.5 * t * (Dd + 2.0);
-  e.B1 = 0.5 * t;
-  e.C0 = 0.5 - 0.25 * U - 0.25 * t * (Dd + 4.0);
-  e.C1 = 0.25 * t;
-  return e;
-}
-
-// vel: [zeta x,y,z, xi x,y,z, |xi|^2, w] of one velocity
-__device__ __forceinline__ double eq_f(const EqNode &e, const double *vel) {
-  double s = vel[3] * e.ux + vel[4] * e.uy + vel[5] * e.uz;
-  double q = vel[6];
-  double c0 = e.A0 + q * (e.A1 + q * e.A2);
-  double c1 = e.B0 + e.B1 * q;
-  double c2 = e.C0 + e.C1 * q;
-  double poly = c0 + s * (c1 + s * (c2 + s * (1.0 / 6.0 + s * (1.0 / 24.0))));
-  return vel[7] * e.rho * poly;
-}
 
 // ------------------------------------------------------------------ reductions
 __device__ __forceinline__ double wave_sum(double v) {
@@ -118,119 +78,30 @@ __global__ void __launch_bounds__(kBlock) k_reduce_final(const double *__restric
   }
 }
 
-// ------------------------------------------------------------------ tensor streaming
-template <typename T> struct WeightSel;
-template <> struct WeightSel<double> {
-  __device__ static const double *get(const DevAxis &ax) { return ax.w64; }
-  __device__ static double exc(const ExcEntry &e, int j) { return e.w[j]; }
-};
-template <> struct WeightSel<float> {
-  __device__ static const float *get(const DevAxis &ax) { return ax.w32; }
-  __device__ static float exc(const ExcEntry &e, int j) { return e.w32[j]; }
+// Nodes with n[axis] in [lo, lo + cnt) (the whole mesh: axis 0, lo 0, cnt N_x).
+struct Slab {
+  int axis, lo, cnt;
+  int64_t total;   // nodes in the slab
 };
 
-// Streamed value of velocity i at node n (tensor mesh): the departure point's
-// interpolant (eq:intf) evaluated sum-factorised with per-axis 1D weights; boundary
-// layers use their face entries (bounce-back / outlet stencil, or inlet equilibrium).
 template <typename T, int D, int P>
-__device__ __forceinline__ void stream_tp(const DevTensorPlan &pl, const StepArgs &sa, const T *__restrict__ pin,
-                                          const int (&n)[3], int i, const ExcEntry *e0, const ExcEntry *e1,
-                                          int fax0, int fax1, double scale, double &fv, double &gv) {
-  const ExcEntry *ex = nullptr;
-  int fax = -1;
-  if (e0 && e0[i].kind != EXC_NONE) { ex = &e0[i]; fax = fax0; }
-  else if (e1 && e1[i].kind != EXC_NONE) { ex = &e1[i]; fax = fax1; }
-  const int Q = pl.Q;
-  if (ex && ex->kind == EXC_INLET) {
-    const double *st = sa.inlet + 5 * ex->src;
-    EqNode e = eq_prepare(st[0], st[1], st[2], st[3], st[4], sa, D);
-    fv = eq_f(e, pl.vel + 8 * i);
-    gv = st[4] * sa.gbase * fv;
-    return;
-  }
-  int src = ex ? ex->src : i;
-  int st[3];
-  int len[3];
-  T w[3][P + 1];
-#pragma unroll
-  for (int a = 0; a < 3; a++) {
-    len[a] = 1;
-    st[a] = 0;
-#pragma unroll
-    for (int j = 0; j <= P; j++) w[a][j] = (j == 0) ? T(1) : T(0);
-  }
-#pragma unroll
-  for (int a = 0; a < D; a++) {
-    const DevAxis &ax = pl.ax[a];
-    if (a == fax) {
-      st[a] = ex->start;
-      len[a] = P + 1;
-#pragma unroll
-      for (int j = 0; j <= P; j++) w[a][j] = WeightSel<T>::exc(*ex, j);
-    } else {
-      int tb = ex ? ex->tab[a] : pl.tab_reg[a * Q + i];
-      if (ax.ident[tb]) {
-        st[a] = n[a];
-        len[a] = 1;
-      } else {
-        size_t r = (size_t)tb * ax.N + n[a];
-        st[a] = ax.start[r];
-        len[a] = P + 1;
-        const T *wp = WeightSel<T>::get(ax) + r * (P + 1);
-#pragma unroll
-        for (int j = 0; j <= P; j++) w[a][j] = wp[j];
-      }
-    }
-  }
-  const int N0 = pl.ax[0].N, N1 = pl.ax[1].N, N2 = pl.ax[2].N;
-  const T *F = pin + (size_t)src * pl.N;
-  const T *G = pin + ((size_t)Q + src) * pl.N;
-  T fz = 0, gz = 0;
-#pragma unroll
-  for (int jz = 0; jz <= P; jz++) {
-    if (jz >= len[2]) break;
-    int mz = st[2] + jz;
-    if (mz >= N2) mz -= N2;
-    T fy = 0, gy = 0;
-#pragma unroll
-    for (int jy = 0; jy <= P; jy++) {
-      if (jy >= len[1]) break;
-      int my = st[1] + jy;
-      if (my >= N1) my -= N1;
-      size_t row = ((size_t)mz * N1 + my) * N0;
-      T fx = 0, gx = 0;
-#pragma unroll
-      for (int jx = 0; jx <= P; jx++) {
-        if (jx >= len[0]) break;
-        int mx = st[0] + jx;
-        if (mx >= N0) mx -= N0;
-        fx += w[0][jx] * F[row + mx];
-        gx += w[0][jx] * G[row + mx];
-      }
-      fy += w[1][jy] * fx;
-      gy += w[1][jy] * gx;
-    }
-    fz += w[2][jz] * fy;
-    gz += w[2][jz] * gy;
-  }
-  fv = scale * (double)fz;
-  gv = scale * (double)gz;
-}
-
-template <typename T, int D, int P>
-__global__ void __launch_bounds__(kBlock) k_step_gather(const DevTensorPlan pl, const StepArgs sa,
+__global__ void __launch_bounds__(kBlock) k_step_gather(const DevTensorPlan pl, const StepArgs sa, const Slab sl,
                                                          const T *__restrict__ pin, T *__restrict__ pout) {
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (k >= pl.N) return;
+  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= sl.total) return;
   const int Q = pl.Q;
   int n[3];
   {
-    int64_t r = k;
-    n[0] = (int)(r % pl.ax[0].N);
-    r /= pl.ax[0].N;
-    n[1] = (int)(r % pl.ax[1].N);
-    n[2] = (int)(r / pl.ax[1].N);
+    // slab axis fastest, then the remaining axes in x, y, z order
+    int64_t r = q / sl.cnt;
+    n[sl.axis] = sl.lo + (int)(q % sl.cnt);
+    for (int a = 0; a < 3; a++) {
+      if (a == sl.axis) continue;
+      n[a] = (int)(r % pl.ax[a].N);
+      r /= pl.ax[a].N;
+    }
   }
+  const int64_t k = (int64_t)n[0] + (int64_t)pl.ax[0].N * ((int64_t)n[1] + (int64_t)pl.ax[1].N * n[2]);
   const ExcEntry *er[2] = {nullptr, nullptr};
   int fax[2] = {-1, -1};
   double Tw = __builtin_nan("");
@@ -384,16 +255,18 @@ namespace {
 int64_t nblocks(int64_t N) { return (N + kBlock - 1) / kBlock; }
 
 template <typename T, int D, int P>
-void launch_gather_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
-  hipLaunchKernelGGL((k_step_gather<T, D, P>), dim3((unsigned)nblocks(Pl->tp.N)), dim3(kBlock), 0, s, Pl->tp, a,
+void launch_gather_t(sllbm_plan_s *Pl, const StepArgs &a, const Slab &sl, const void *pin, void *pout,
+                     hipStream_t s) {
+  if (sl.total <= 0) return;
+  hipLaunchKernelGGL((k_step_gather<T, D, P>), dim3((unsigned)nblocks(sl.total)), dim3(kBlock), 0, s, Pl->tp, a, sl,
                      (const T *)pin, (T *)pout);
 }
 
 template <typename T>
-int dispatch_gather(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
+int dispatch_gather(sllbm_plan_s *Pl, const StepArgs &a, const Slab &sl, const void *pin, void *pout, hipStream_t s) {
   int D = Pl->mesh.dim, p = Pl->mesh.p;
 #define CASE(DD, PP) \
-  if (D == DD && p == PP) { launch_gather_t<T, DD, PP>(Pl, a, pin, pout, s); return SLLBM_OK; }
+  if (D == DD && p == PP) { launch_gather_t<T, DD, PP>(Pl, a, sl, pin, pout, s); return SLLBM_OK; }
   CASE(2, 1) CASE(2, 2) CASE(2, 3) CASE(2, 4) CASE(3, 1) CASE(3, 2) CASE(3, 3) CASE(3, 4)
 #undef CASE
   return fail(SLLBM_EUNSUPPORTED, "no GPU kernel for dim %d order %d (p must be 1..4)", D, p);
@@ -402,8 +275,30 @@ int dispatch_gather(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *
 
 int launch_step(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
   if (Pl->kernel != 0) return fail(SLLBM_EUNSUPPORTED, "curvilinear step kernel not available");
-  int rc = Pl->prec == SLLBM_F32 ? dispatch_gather<float>(Pl, a, pin, pout, s)
-                                 : dispatch_gather<double>(Pl, a, pin, pout, s);
+  const DevTensorPlan &tp = Pl->tp;
+  auto gather = [&](const Slab &sl) {
+    return Pl->prec == SLLBM_F32 ? dispatch_gather<float>(Pl, a, sl, pin, pout, s)
+                                 : dispatch_gather<double>(Pl, a, sl, pin, pout, s);
+  };
+  int rc;
+  if (Pl->tile_ok && Pl->kernel_choice != 1) {
+    // interior nodes: LDS-tiled kernel; boundary-layer slabs: per-node gather
+    rc = launch_step_tile(Pl, a, pin, pout, s);
+    if (rc) return rc;
+    for (int f = 0; f < tp.nfaces; f++) {
+      const DevFace &F = tp.face[f];
+      if (F.depth <= 0) continue;
+      Slab sl;
+      sl.axis = F.axis;
+      sl.cnt = F.depth;
+      sl.lo = F.side == 0 ? 0 : tp.ax[F.axis].N - F.depth;
+      sl.total = (int64_t)F.depth * (tp.N / tp.ax[F.axis].N);
+      if ((rc = gather(sl))) return rc;
+    }
+  } else {
+    Slab sl{0, 0, tp.ax[0].N, tp.N};
+    rc = gather(sl);
+  }
   if (rc) return rc;
   HIP_TRY(hipGetLastError());
   return SLLBM_OK;

@@ -26,17 +26,22 @@ def say(*a):
     sys.stdout.flush()
 
 
-def _pair(mesh, phys, prec, fields):
+GATHER, TILED = 1, 2
+KERNELS = [pytest.param(GATHER, id="gather"), pytest.param(TILED, id="tiled")]
+
+
+def _pair(mesh, phys, prec, fields, kernel=0):
     o = oracle.TensorOracle(mesh, phys)
-    g = GpuRun(mesh, phys, prec)
+    g = GpuRun(mesh, phys, prec, kernel)
+    say("kernel in use", g.kernel)
     xyz = o.coords()
     assert np.max(np.abs(g.coords() - xyz)) < 1e-13
     rho, u, T = fields(xyz)
     return o, g, (rho, u, T)
 
 
-def _run_compare(mesh, phys, prec, fields, nsteps, tol, compare_pops=True, mass_fix_every=0):
-    o, g, (rho, u, T) = _pair(mesh, phys, prec, fields)
+def _run_compare(mesh, phys, prec, fields, nsteps, tol, compare_pops=True, mass_fix_every=0, kernel=0):
+    o, g, (rho, u, T) = _pair(mesh, phys, prec, fields, kernel)
     p0 = o.init(rho, u, T)
     g.init(rho, u, T)
     mref = o.totals(p0)[0] if mass_fix_every else None
@@ -80,23 +85,26 @@ def test_init_equilibrium_and_moments(dim):
 
 # ------------------------------------------------------------------ C1
 
-def test_shear_wave_fp64_100_steps():
-    say("case C1a shear wave fp64 16x16 p4 100 steps")
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_shear_wave_fp64_100_steps(kernel):
+    say("case C1a shear wave fp64 16x16 p4 100 steps", kernel)
     mesh, phys = W.shear_wave_case()
-    _run_compare(mesh, phys, "f64", lambda x: W.shear_wave_fields(x, noise=1e-3, seed=1), 100, TOL64)
+    _run_compare(mesh, phys, "f64", lambda x: W.shear_wave_fields(x, noise=1e-3, seed=1), 100, TOL64, kernel=kernel)
 
 
-def test_isentropic_vortex_fp64_100_steps():
-    say("case C1b vortex fp64 16x16 p4 100 steps")
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_isentropic_vortex_fp64_100_steps(kernel):
+    say("case C1b vortex fp64 16x16 p4 100 steps", kernel)
     mesh, phys = W.vortex_case()
-    _run_compare(mesh, phys, "f64", lambda x: W.vortex_fields(x, noise=1e-3, seed=1), 100, TOL64)
+    _run_compare(mesh, phys, "f64", lambda x: W.vortex_fields(x, noise=1e-3, seed=1), 100, TOL64, kernel=kernel)
 
 
-def test_shear_wave_fp32_100_steps():
-    say("case C1a shear wave fp32 100 steps")
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_shear_wave_fp32_100_steps(kernel):
+    say("case C1a shear wave fp32 100 steps", kernel)
     mesh, phys = W.shear_wave_case()
     _run_compare(mesh, phys, "f32", lambda x: W.shear_wave_fields(x, noise=1e-3, seed=1), 100, TOL32,
-                 compare_pops=False)
+                 compare_pops=False, kernel=kernel)
 
 
 @pytest.mark.parametrize("p,fam", [(1, "gll"), (2, "glc"), (3, "equi"), (4, "glc")])
@@ -114,19 +122,21 @@ def test_smallest_periodic_mesh():
 
 # ------------------------------------------------------------------ C2
 
-def test_tgv_fp64_small():
-    say("case C2 TGV fp64 6^3 p3 20 steps")
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_tgv_fp64_small(kernel):
+    say("case C2 TGV fp64 6^3 p3 20 steps", kernel)
     mesh, phys = W.tgv_case(ncell=6, p=3)
-    _run_compare(mesh, phys, "f64", lambda x: W.tgv_fields(x), 20, TOL64)
+    _run_compare(mesh, phys, "f64", lambda x: W.tgv_fields(x), 20, TOL64, kernel=kernel)
 
 
-def test_tgv_fp32_small_100_steps():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_tgv_fp32_small_100_steps(kernel):
     """100 steps at the time step of the 32^3 configuration (t = 3.4, before the
     vortex's transition).  A coarse mesh at its own CFL time step would reach t = 22,
     where the transitional flow amplifies any rounding ~15x per 50 steps."""
-    say("case C2 TGV fp32 5^3 p3 100 steps at the C2 time step")
-    mesh, phys = W.tgv_case(ncell=5, p=3, dt=W.TGV_DT)
-    _run_compare(mesh, phys, "f32", lambda x: W.tgv_fields(x), 100, TOL32, compare_pops=False)
+    say("case C2 TGV fp32 6^3 p3 100 steps at the C2 time step", kernel)
+    mesh, phys = W.tgv_case(ncell=6, p=3, dt=W.TGV_DT)
+    _run_compare(mesh, phys, "f32", lambda x: W.tgv_fields(x), 100, TOL32, compare_pops=False, kernel=kernel)
 
 
 # ------------------------------------------------------------------ walls, inlet, outlet
@@ -136,23 +146,25 @@ def _channel_small():
     T_w = 0.9 against a fluid at T = 1, power-law viscosity, Kupershtokh forcing) at bulk
     Ma 0.5: at Ma 1.5 with T = T0 the Gauss-Hermite set is unstable within 4 steps in the
     oracle as well."""
-    return W.channel_case(ncell=(6, 8, 4), p=2, box=(2.0, 2.0, 1.0), cfl=0.9, T_wall=0.9, Ma_b=0.5)
+    return W.channel_case(ncell=(6, 8, 6), p=2, box=(2.0, 2.0, 1.5), cfl=0.9, T_wall=0.9, Ma_b=0.5)
 
 
 def _channel_fields(x):
-    return W.channel_fields(x, box=(2.0, 2.0, 1.0), Ma_b=0.5, T_wall=1.0)
+    return W.channel_fields(x, box=(2.0, 2.0, 1.5), Ma_b=0.5, T_wall=1.0)
 
 
-def test_channel_thermal_walls_forcing_fp64():
-    say("case C4 sub-box fp64 6x8x4 p2 20 steps")
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_channel_thermal_walls_forcing_fp64(kernel):
+    say("case C4 sub-box fp64 6x8x6 p2 20 steps", kernel)
     mesh, phys = _channel_small()
-    _run_compare(mesh, phys, "f64", _channel_fields, 20, TOL64)
+    _run_compare(mesh, phys, "f64", _channel_fields, 20, TOL64, kernel=kernel)
 
 
-def test_channel_thermal_walls_forcing_fp32():
-    say("case C4 sub-box fp32 20 steps")
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_channel_thermal_walls_forcing_fp32(kernel):
+    say("case C4 sub-box fp32 20 steps", kernel)
     mesh, phys = _channel_small()
-    _run_compare(mesh, phys, "f32", _channel_fields, 20, TOL32, compare_pops=False)
+    _run_compare(mesh, phys, "f32", _channel_fields, 20, TOL32, compare_pops=False, kernel=kernel)
 
 
 def test_plain_bounce_back_2d_stretched():
@@ -194,10 +206,12 @@ def test_pure_streaming_mode():
     _run_compare(mesh, phys, "f64", lambda x: W.random_fields(x.shape[0], 2, seed=8), 5, TOL64)
 
 
-def test_mass_fix_every_3_steps():
-    say("case mass fix")
-    mesh, phys = W.shear_wave_case(ncell=6, p=3)
-    _run_compare(mesh, phys, "f64", lambda x: W.shear_wave_fields(x, noise=0.05, seed=9), 10, TOL64, mass_fix_every=3)
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_mass_fix_every_3_steps(kernel):
+    say("case mass fix", kernel)
+    mesh, phys = W.shear_wave_case(ncell=12, p=3)
+    _run_compare(mesh, phys, "f64", lambda x: W.shear_wave_fields(x, noise=0.05, seed=9), 10, TOL64, mass_fix_every=3,
+                 kernel=kernel)
 
 
 # ------------------------------------------------------------------ full size, sampled
@@ -209,21 +223,21 @@ def _sample_nodes(N, n, seed):
     return np.array(sorted(s), dtype=np.int64)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_tgv_full_size_one_step_sampled(prec):
+def test_tgv_full_size_one_step_sampled(prec, kernel):
     """The bench workload (32^3 cells p=3, 96^3 nodes, D3V125) one step from the TGV
     state, checked at sampled nodes against the oracle evaluated node by node."""
-    say("case C2 full size sampled", prec)
+    say("case C2 full size sampled", prec, kernel)
     mesh, phys = W.tgv_case()
     o = oracle.TensorOracle(mesh, phys)
-    g = GpuRun(mesh, phys, prec)
+    g = GpuRun(mesh, phys, prec, kernel)
     xyz = g.coords()
     rho, u, T = W.tgv_fields(xyz)
     p0 = o.init(rho, u, T)
     g.load(p0)
     g.run(1)
     got = g.pop()
-    src = g.a.new_empty(0)  # keep allocator quiet
     nodes = _sample_nodes(o.N, 150, 11)
     # FP32 path starts from the FP32-rounded state: give the oracle the same input
     pin = p0.astype(np.float32).astype(np.float64) if prec == "f32" else p0
@@ -232,3 +246,12 @@ def test_tgv_full_size_one_step_sampled(prec):
     e = rel_err(gq, ref)
     say("sampled pop error", e)
     assert e <= (TOL64 if prec == "f64" else 2e-6)
+
+
+def test_kernel_selection_reports_the_kernel_in_use():
+    say("case kernel selection")
+    mesh, phys = W.tgv_case(ncell=6, p=3)
+    assert GpuRun(mesh, phys, "f64").kernel == TILED
+    assert GpuRun(mesh, phys, "f64", GATHER).kernel == 0
+    mesh5, phys5 = W.tgv_case(ncell=5, p=3)   # 15 nodes per axis: too few for a tile + halo
+    assert GpuRun(mesh5, phys5, "f64").kernel == 0
