@@ -470,22 +470,23 @@ extern "C" int sllbm_velset_gauss_hermite(int dim, int n, double T0, double *zet
   std::vector<double> x;
   double R = 2.0 * std::sqrt((double)n) + 1.0;
   int steps = 20000;
-  double prev, dummy;
-  he(-R, &prev, &dummy);
-  for (int s = 1; s <= steps && (int)x.size() < n; s++) {
-    double xr = -R + 2.0 * R * s / steps, cur;
-    he(xr, &cur, &dummy);
-    if (cur == 0.0 || (prev < 0) != (cur < 0)) {
-      double a = xr - 2.0 * R / steps, b = xr;
-      double r = 0.5 * (a + b);
-      for (int it = 0; it < 60; it++) {
-        double Hn, Hn1;
-        he(r, &Hn, &Hn1);
-        double dr = Hn / (n * Hn1);
-        r -= dr;
-        if (std::fabs(dr) < 1e-16 * std::max(1.0, std::fabs(r))) break;
+  double dummy;
+  // grid offset by half a step, so that no grid point is a root (x = 0 for odd n)
+  auto grid = [&](int s) { return -R + 2.0 * R * (s + 0.5) / steps; };
+  double prev;
+  he(grid(0), &prev, &dummy);
+  for (int s = 1; s < steps && (int)x.size() < n; s++) {
+    double cur;
+    he(grid(s), &cur, &dummy);
+    if ((prev < 0) != (cur < 0)) {
+      double a = grid(s - 1), b = grid(s), fa = prev;
+      for (int it = 0; it < 200 && b - a > 0; it++) {  // bisection to the last bit
+        double mid = 0.5 * (a + b), fm;
+        if (mid == a || mid == b) break;
+        he(mid, &fm, &dummy);
+        if ((fm < 0) == (fa < 0)) { a = mid; fa = fm; } else { b = mid; }
       }
-      x.push_back(r);
+      x.push_back(0.5 * (a + b));
     }
     prev = cur;
   }
