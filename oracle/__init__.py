@@ -301,3 +301,189 @@ def equilibrium(dim: int, rho: float, u, T: float, gamma: float = 1.4, T0: float
                          ctypes.c_double(gamma), ctypes.c_double(rho), _ptr(uu), ctypes.c_double(T),
                          _ptr(feq), _ptr(geq))
     return feq, geq
+
+
+# --------------------------------------------------------------------------
+# Curvilinear (isoparametric quadrilateral) meshes
+# --------------------------------------------------------------------------
+
+class OrCurv(ctypes.Structure):
+    _fields_ = [
+        ("p", ctypes.c_int), ("Q", ctypes.c_int), ("zeta", _dp), ("w", _dp), ("opp", _ip), ("T0", ctypes.c_double),
+        ("xref", _dp), ("n_nodes", ctypes.c_int64), ("xyz", _dp), ("n_cells", ctypes.c_int64),
+        ("cell_nodes", ctypes.POINTER(ctypes.c_int64)), ("face_bc", _ip), ("n_bc", ctypes.c_int), ("bc_kind", _ip),
+        ("bc_val", _dp), ("gamma", ctypes.c_double), ("dt", ctypes.c_double), ("relax_mode", ctypes.c_int),
+        ("tau_bar", ctypes.c_double), ("mu_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
+        ("mu_exp", ctypes.c_double), ("force", ctypes.c_double * 2), ("mass_fix", ctypes.c_int),
+        ("mass_ref", ctypes.c_double), ("node_vol", _dp),
+        ("bx0", ctypes.c_double), ("by0", ctypes.c_double), ("bh", ctypes.c_double), ("bnx", ctypes.c_int),
+        ("bny", ctypes.c_int), ("bstart", ctypes.POINTER(ctypes.c_int64)), ("bcells", ctypes.POINTER(ctypes.c_int64)),
+    ]
+
+
+def _lagrange_table(xref, pts):
+    """l_j(pts) and l_j'(pts) by the product formula: arrays [len(pts), p+1]."""
+    p = len(xref) - 1
+    L = np.ones((len(pts), p + 1))
+    dL = np.zeros((len(pts), p + 1))
+    for j in range(p + 1):
+        for m in range(p + 1):
+            if m != j:
+                L[:, j] *= (pts - xref[m]) / (xref[j] - xref[m])
+        for k in range(p + 1):
+            if k == j:
+                continue
+            t = np.full(len(pts), 1.0 / (xref[j] - xref[k]))
+            for m in range(p + 1):
+                if m != j and m != k:
+                    t *= (pts - xref[m]) / (xref[j] - xref[m])
+            dL[:, j] += t
+    return L, dL
+
+
+class CurvOracle:
+    """FP64 reference of the SLLBM on a 2D curvilinear mesh (workloads.CurvMesh)."""
+
+    def __init__(self, mesh, phys, n_gh: int = 5, geometry: bool = True):
+        """geometry=False skips the departure-point table (for tests of locate/exit)."""
+        self.mesh, self.phys = mesh, phys
+        self.dim = 2
+        self.zeta, self.w, self.opp = velocity_set(2, n_gh, phys.T0)
+        self.Q = self.zeta.shape[0]
+        self.xref = support_points(mesh.p, mesh.nodes)
+        self.xyz = np.ascontiguousarray(mesh.node_xyz, dtype=np.float64)
+        self.N = self.xyz.shape[0]
+        self.cells = np.ascontiguousarray(mesh.cell_nodes, dtype=np.int64)
+        self.fb = np.ascontiguousarray(mesh.cell_face_bc, dtype=np.int32)
+        nb = max(len(mesh.bcs), 1)
+        self._bc_kind = np.zeros(nb, dtype=np.int32)
+        self._bc_val = np.zeros((nb, 6))
+        for b, bc in enumerate(mesh.bcs):
+            self._bc_kind[b] = bc.kind
+            u = list(bc.u) + [0.0] * 3
+            self._bc_val[b] = [bc.rho, u[0], u[1], u[2], bc.T, bc.T_wall]
+        self.node_vol = self._node_volumes()
+        s = OrCurv()
+        s.p, s.Q = mesh.p, self.Q
+        s.zeta, s.w, s.opp, s.T0 = _ptr(self.zeta), _ptr(self.w), _ptr(self.opp, _ip), phys.T0
+        s.xref = _ptr(self.xref)
+        s.n_nodes, s.xyz = self.N, _ptr(self.xyz)
+        s.n_cells, s.cell_nodes = self.cells.shape[0], self.cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        s.face_bc = _ptr(self.fb, _ip)
+        s.n_bc, s.bc_kind, s.bc_val = len(mesh.bcs), _ptr(self._bc_kind, _ip), _ptr(self._bc_val)
+        s.gamma, s.dt, s.relax_mode, s.tau_bar = phys.gamma, phys.dt, phys.relax_mode, phys.tau_bar
+        s.mu_ref, s.T_ref, s.mu_exp = phys.mu_ref, phys.T_ref, phys.mu_exp
+        f = list(phys.force) + [0.0, 0.0]
+        s.force[0], s.force[1] = f[0], f[1]
+        s.mass_fix, s.mass_ref, s.node_vol = 0, 0.0, _ptr(self.node_vol)
+        self._s = s
+        # bucket width: the median cell extent, capped at ~4M buckets
+        ext = np.ptp(self.xyz[self.cells], axis=1).max(axis=1)
+        span = np.ptp(self.xyz, axis=0).max()
+        h = max(float(np.median(ext)), span / 2000.0)
+        lib().or_curv_prepare(ctypes.byref(s), ctypes.c_double(h))
+        if geometry:
+            self._geometry()
+
+    def _geometry(self):
+        s = self._s
+        Qn = self.Q * self.N
+        self.g_cell = np.zeros(Qn, dtype=np.int64)
+        self.g_xi = np.zeros(2 * Qn)
+        self.g_src = np.zeros(Qn, dtype=np.int32)
+        self.g_kind = np.zeros(Qn, dtype=np.int32)
+        self.g_th = np.zeros(self.N, dtype=np.int32)
+        err = np.zeros(2, dtype=np.int64)
+        rc = lib().or_curv_geometry(ctypes.byref(s), self.g_cell.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    _ptr(self.g_xi), _ptr(self.g_src, _ip), _ptr(self.g_kind, _ip),
+                                    _ptr(self.g_th, _ip), err.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        if rc != 0:
+            raise OracleError(f"oracle geometry failed rc={rc} at node {err[0]} velocity {err[1]}")
+
+    def __del__(self):
+        if getattr(self, "_s", None) is not None:
+            lib().or_curv_release(ctypes.byref(self._s))
+            self._s = None
+
+    def _node_volumes(self):
+        """V_k = sum over cells of the integral of l_k |J| by a (p+2)^2 Gauss-Legendre rule."""
+        xg, wg = legendre.leggauss(self.mesh.p + 2)
+        L, dL = _lagrange_table(self.xref, xg)
+        n1 = self.mesh.p + 1
+        X = self.xyz[self.cells].reshape(-1, n1, n1, 2)           # [c, jy, jx, a]
+        # basis at (gy, gx): L[gy, jy] L[gx, jx]
+        dxi = np.einsum("cyxa,gy,hx->cgha", X, L, dL)
+        deta = np.einsum("cyxa,gy,hx->cgha", X, dL, L)
+        det = np.abs(dxi[..., 0] * deta[..., 1] - dxi[..., 1] * deta[..., 0])   # [c, gy, gx]
+        wts = np.einsum("g,h,cgh->cgh", wg, wg, det)
+        contrib = np.einsum("cgh,gy,hx->cyx", wts, L, L).reshape(len(self.cells), -1)
+        V = np.zeros(self.N)
+        np.add.at(V, self.cells.reshape(-1), contrib.reshape(-1))
+        return V
+
+    def coords(self):
+        return self.xyz.copy()
+
+    def init(self, rho, u, T):
+        pop = np.zeros(2 * self.Q * self.N)
+        lib().or_init_generic(ctypes.c_int(2), ctypes.c_int(self.Q), _ptr(self.zeta), _ptr(self.w),
+                              ctypes.c_double(self.phys.T0), ctypes.c_double(self.phys.gamma),
+                              ctypes.c_int64(self.N), _ptr(np.ascontiguousarray(rho, dtype=np.float64)),
+                              _ptr(np.ascontiguousarray(u, dtype=np.float64).reshape(self.N, 2)),
+                              _ptr(np.ascontiguousarray(T, dtype=np.float64)), _ptr(pop))
+        return pop
+
+    def step(self, pop, mass_ref=None):
+        out = np.empty_like(pop)
+        s = self._s
+        s.mass_fix = 1 if mass_ref is not None else 0
+        s.mass_ref = float(mass_ref) if mass_ref is not None else 0.0
+        lib().or_curv_step(ctypes.byref(s), self.g_cell.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                           _ptr(self.g_xi), _ptr(self.g_src, _ip), _ptr(self.g_kind, _ip), _ptr(self.g_th, _ip),
+                           _ptr(np.ascontiguousarray(pop)), _ptr(out))
+        s.mass_fix = 0
+        return out
+
+    def run(self, pop, nsteps, mass_fix_every=0, mass_ref=None):
+        for n in range(nsteps):
+            fix = mass_fix_every > 0 and n > 0 and n % mass_fix_every == 0
+            pop = self.step(pop, mass_ref if fix else None)
+        return pop
+
+    def step_nodes(self, pop, nodes, mass_ref=None):
+        """One step at the given nodes only (their geometry computed on the fly):
+        returns [len(nodes), 2Q] = (f_0..f_{Q-1}, g_0..g_{Q-1}) per node."""
+        nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+        out = np.zeros((nodes.size, 2 * self.Q))
+        err = np.zeros(2, dtype=np.int64)
+        s = self._s
+        s.mass_fix = 1 if mass_ref is not None else 0
+        s.mass_ref = float(mass_ref) if mass_ref is not None else 0.0
+        rc = lib().or_curv_step_nodes(ctypes.byref(s), _ptr(np.ascontiguousarray(pop)),
+                                      nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      ctypes.c_int64(nodes.size), _ptr(out),
+                                      err.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        s.mass_fix = 0
+        if rc != 0:
+            raise OracleError(f"oracle geometry failed rc={rc} at node {err[0]} velocity {err[1]}")
+        return out
+
+    def locate(self, x):
+        """(cell, reference coordinates) of point x, cell -1 outside the mesh."""
+        L = lib()
+        L.or_curv_locate.restype = ctypes.c_int64
+        xi = np.zeros(2)
+        c = L.or_curv_locate(ctypes.byref(self._s), _ptr(np.ascontiguousarray(x, dtype=np.float64)), _ptr(xi))
+        return int(c), xi
+
+    def exit(self, x0, v):
+        """(s, bc) where x0 + s v leaves the mesh, s in [0, 1], x0 inside."""
+        L = lib()
+        L.or_curv_exit.restype = ctypes.c_double
+        bc = ctypes.c_int(-1)
+        s = L.or_curv_exit(ctypes.byref(self._s), _ptr(np.ascontiguousarray(x0, dtype=np.float64)),
+                           _ptr(np.ascontiguousarray(v, dtype=np.float64)), ctypes.byref(bc))
+        return float(s), bc.value
+
+    moments = TensorOracle.moments
+    totals = TensorOracle.totals

@@ -238,14 +238,6 @@ static double wrap(double x, double lo, double hi) {
   return x;
 }
 
-static int inside_nonperiodic(const or_tensor *m, const double *x) {
-  for (int a = 0; a < m->dim; a++) {
-    if (m->periodic[a]) continue;
-    if (x[a] < m->edges[a][0] || x[a] > m->edges[a][m->ncell[a]]) return 0;
-  }
-  return 1;
-}
-
 /* Walk the backward segment x_k -> x_k - dt zeta_i; the first non-periodic face
  * crossed decides the boundary case (Sec. 3.3).  A departure point exactly on a
  * face counts as inside. */
@@ -286,31 +278,31 @@ static int trace(const or_tensor *m, const double *xk, int i, or_trace *t) {
         double iota = d[a] - (xk[a] - xw);
         t->dp[a] = xw + iota;
       }
-      /* the wall-normal coordinate is mathematically inside; absorb rounding */
+      /* a reflected point outside the box (rounding, a channel thinner than the path,
+       * a corner) is replaced by its nearest point of the box */
       for (int a = 0; a < D; a++) {
         if (m->periodic[a]) continue;
-        double lo = m->edges[a][0], hi = m->edges[a][m->ncell[a]], tol = 1e-12 * (hi - lo);
-        if (t->dp[a] < lo && t->dp[a] > lo - tol) t->dp[a] = lo;
-        if (t->dp[a] > hi && t->dp[a] < hi + tol) t->dp[a] = hi;
+        double lo = m->edges[a][0], hi = m->edges[a][m->ncell[a]];
+        if (t->dp[a] < lo) t->dp[a] = lo;
+        if (t->dp[a] > hi) t->dp[a] = hi;
       }
-      if (!inside_nonperiodic(m, t->dp)) return OR_EGEOM;
       if (!isnan(m->bc_val[bc * 6 + 5])) t->thermal = 1;
     } else if (kind == OR_BC_INLET) {
       t->kind = 1;
       t->src = i;
     } else if (kind == OR_BC_OUTLET) {
-      /* Sec. 3.3.3: restart from the arrival point in the opposite direction. */
+      /* Sec. 3.3.3: restart from the arrival point in the opposite direction, i.e.
+       * population i at x_k + dt zeta_i; should that point lie outside the box too,
+       * its nearest point of the box (each bounded coordinate clamped). */
       t->kind = 0;
       t->src = i;
-      double sf = 1.0;
       for (int a = 0; a < D; a++) {
-        if (m->periodic[a] || d[a] == 0.0) continue;
+        t->dp[a] = xk[a] + d[a];
+        if (m->periodic[a]) continue;
         double lo = m->edges[a][0], hi = m->edges[a][m->ncell[a]];
-        double end = xk[a] + d[a];
-        if (end > hi) { double f = (hi - xk[a]) / d[a]; if (f < sf) sf = f; }
-        if (end < lo) { double f = (lo - xk[a]) / d[a]; if (f < sf) sf = f; }
+        if (t->dp[a] < lo) t->dp[a] = lo;
+        if (t->dp[a] > hi) t->dp[a] = hi;
       }
-      for (int a = 0; a < D; a++) t->dp[a] = xk[a] + sf * d[a];
     } else {
       return OR_EINVAL;
     }
@@ -592,3 +584,646 @@ int or_moments(int D, int Q, const double *zeta, double gamma, size_t N, const d
   }
   return OR_OK;
 }
+
+/* ========================================================================= */
+/* Curvilinear (isoparametric quadrilateral) meshes, dim = 2                   */
+/* ========================================================================= */
+
+typedef struct {
+  int p, Q;
+  const double *zeta, *w;
+  const int *opp;
+  double T0;
+  const double *xref;
+  int64_t n_nodes;
+  const double *xyz;        /* [n_nodes][2] */
+  int64_t n_cells;
+  const int64_t *cell_nodes;/* [n_cells][(p+1)^2], xi fastest */
+  const int *face_bc;       /* [n_cells][4]: xi-, xi+, eta-, eta+ ; -1 interior */
+  int n_bc;
+  const int *bc_kind;
+  const double *bc_val;     /* [n_bc][6] */
+  double gamma, dt;
+  int relax_mode;
+  double tau_bar, mu_ref, T_ref, mu_exp;
+  double force[2];
+  int mass_fix;
+  double mass_ref;
+  const double *node_vol;
+  /* bucket grid over cell bounding boxes (built by or_curv_prepare) */
+  double bx0, by0, bh;
+  int bnx, bny;
+  int64_t *bstart, *bcells;
+} or_curv;
+
+/* derivative of the Lagrange basis, product rule */
+static void lagrange_d(int p, const double *xref, double xi, double *dl) {
+  for (int j = 0; j <= p; j++) {
+    double s = 0.0;
+    for (int k = 0; k <= p; k++) {
+      if (k == j) continue;
+      double t = 1.0 / (xref[j] - xref[k]);
+      for (int q = 0; q <= p; q++)
+        if (q != j && q != k) t *= (xi - xref[q]) / (xref[j] - xref[q]);
+      s += t;
+    }
+    dl[j] = s;
+  }
+}
+
+/* isoparametric map x(xi, eta) = sum_j X_j l_jx(xi) l_jy(eta) and its Jacobian */
+static void cell_map(const or_curv *m, int64_t c, double xi, double eta, double *x, double J[2][2]) {
+  int p = m->p, n1 = p + 1;
+  double lx[OR_MAXP + 1], ly[OR_MAXP + 1], dx[OR_MAXP + 1], dy[OR_MAXP + 1];
+  lagrange(p, m->xref, xi, lx);
+  lagrange(p, m->xref, eta, ly);
+  lagrange_d(p, m->xref, xi, dx);
+  lagrange_d(p, m->xref, eta, dy);
+  x[0] = x[1] = 0;
+  J[0][0] = J[0][1] = J[1][0] = J[1][1] = 0;
+  const int64_t *cn = m->cell_nodes + c * n1 * n1;
+  for (int jy = 0; jy <= p; jy++)
+    for (int jx = 0; jx <= p; jx++) {
+      const double *X = m->xyz + 2 * cn[jx + n1 * jy];
+      for (int a = 0; a < 2; a++) {
+        x[a] += X[a] * lx[jx] * ly[jy];
+        J[a][0] += X[a] * dx[jx] * ly[jy];
+        J[a][1] += X[a] * lx[jx] * dy[jy];
+      }
+    }
+}
+
+#define OR_CURV_TOL 1e-10
+
+/* Newton iteration for x(xi) = x in cell c from reference point r0 (steps damped to
+ * 0.5); returns 1 and the converged point if it converged. */
+static int cell_newton(const or_curv *m, int64_t c, const double *x, const double *r0, double *r) {
+  r[0] = r0[0];
+  r[1] = r0[1];
+  for (int it = 0; it < 60; it++) {
+    double X[2], J[2][2];
+    cell_map(m, c, r[0], r[1], X, J);
+    double e0 = x[0] - X[0], e1 = x[1] - X[1];
+    double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    if (det == 0.0) return 0;
+    double d0 = (J[1][1] * e0 - J[0][1] * e1) / det;
+    double d1 = (-J[1][0] * e0 + J[0][0] * e1) / det;
+    double sz = fabs(d0) > fabs(d1) ? fabs(d0) : fabs(d1);
+    if (sz > 0.5) { d0 *= 0.5 / sz; d1 *= 0.5 / sz; }
+    r[0] += d0;
+    r[1] += d1;
+    if (fabs(r[0]) > 4.0 || fabs(r[1]) > 4.0) return 0;
+    if (fabs(d0) + fabs(d1) < 1e-11) {
+      /* quadratic convergence: two more corrections reach the rounding level, which
+       * in a thin cell can itself be ~1e-13 in reference units */
+      for (int extra = 0; extra < 2; extra++) {
+        cell_map(m, c, r[0], r[1], X, J);
+        e0 = x[0] - X[0];
+        e1 = x[1] - X[1];
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        if (det == 0.0) return 0;
+        r[0] += (J[1][1] * e0 - J[0][1] * e1) / det;
+        r[1] += (-J[1][0] * e0 + J[0][0] * e1) / det;
+      }
+      return 1;
+    }
+  }
+  return 0; /* no convergence from this start */
+}
+
+static int in_ref_square(const double *r) {
+  return fabs(r[0]) <= 1.0 + OR_CURV_TOL && fabs(r[1]) <= 1.0 + OR_CURV_TOL;
+}
+
+/* Inverse of the isoparametric map of cell c; 1 if x lies in the cell (reference
+ * coordinates within 1e-10 of [-1,1]^2).  Starts from the support point nearest to x,
+ * then from a 3x3 grid of reference points. */
+static int cell_inverse(const or_curv *m, int64_t c, const double *x, double *xi) {
+  int n1 = m->p + 1;
+  const int64_t *cn = m->cell_nodes + c * n1 * n1;
+  double best = 1e300, r0[2] = {0, 0}, r[2];
+  for (int jy = 0; jy <= m->p; jy++)
+    for (int jx = 0; jx <= m->p; jx++) {
+      const double *X = m->xyz + 2 * cn[jx + n1 * jy];
+      double d = (X[0] - x[0]) * (X[0] - x[0]) + (X[1] - x[1]) * (X[1] - x[1]);
+      if (d < best) { best = d; r0[0] = m->xref[jx]; r0[1] = m->xref[jy]; }
+      if (d == 0.0) {  /* a support point: its exact reference coordinates */
+        xi[0] = m->xref[jx];
+        xi[1] = m->xref[jy];
+        return 1;
+      }
+    }
+  /* a start may converge to a root of the polynomial map outside the cell (or not
+   * at all, near a degenerate corner): then the next start is tried */
+  int ok = cell_newton(m, c, x, r0, r) && in_ref_square(r);
+  for (int t = 0; !ok && t < 9; t++) {
+    double s0[2] = {-0.6 + 0.6 * (t % 3), -0.6 + 0.6 * (t / 3)};
+    ok = cell_newton(m, c, x, s0, r) && in_ref_square(r);
+  }
+  if (!ok) return 0;
+  xi[0] = r[0] < -1.0 ? -1.0 : (r[0] > 1.0 ? 1.0 : r[0]);
+  xi[1] = r[1] < -1.0 ? -1.0 : (r[1] > 1.0 ? 1.0 : r[1]);
+  return 1;
+}
+
+int or_curv_prepare(or_curv *m, double cell_size) {
+  /* uniform bucket grid of width cell_size over all cell bounding boxes */
+  int n1 = m->p + 1;
+  double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+  for (int64_t k = 0; k < m->n_nodes; k++) {
+    double X = m->xyz[2 * k], Y = m->xyz[2 * k + 1];
+    if (X < x0) x0 = X;
+    if (X > x1) x1 = X;
+    if (Y < y0) y0 = Y;
+    if (Y > y1) y1 = Y;
+  }
+  m->bh = cell_size;
+  m->bx0 = x0 - cell_size;
+  m->by0 = y0 - cell_size;
+  m->bnx = (int)((x1 - m->bx0) / cell_size) + 2;
+  m->bny = (int)((y1 - m->by0) / cell_size) + 2;
+  int64_t nb = (int64_t)m->bnx * m->bny;
+  int64_t *cnt = (int64_t *)calloc(nb + 1, sizeof(int64_t));
+  /* a cell's box: its support points' box, widened by 5% for curved edges */
+  for (int pass = 0; pass < 2; pass++) {
+    for (int64_t c = 0; c < m->n_cells; c++) {
+      double cx0 = 1e300, cx1 = -1e300, cy0 = 1e300, cy1 = -1e300;
+      for (int j = 0; j < n1 * n1; j++) {
+        const double *X = m->xyz + 2 * m->cell_nodes[c * n1 * n1 + j];
+        if (X[0] < cx0) cx0 = X[0];
+        if (X[0] > cx1) cx1 = X[0];
+        if (X[1] < cy0) cy0 = X[1];
+        if (X[1] > cy1) cy1 = X[1];
+      }
+      double gx = 0.05 * (cx1 - cx0) + 1e-12, gy = 0.05 * (cy1 - cy0) + 1e-12;
+      int i0 = (int)((cx0 - gx - m->bx0) / cell_size), i1 = (int)((cx1 + gx - m->bx0) / cell_size);
+      int j0 = (int)((cy0 - gy - m->by0) / cell_size), j1 = (int)((cy1 + gy - m->by0) / cell_size);
+      for (int bj = j0; bj <= j1; bj++)
+        for (int bi = i0; bi <= i1; bi++) {
+          if (bi < 0 || bj < 0 || bi >= m->bnx || bj >= m->bny) continue;
+          int64_t b = (int64_t)bj * m->bnx + bi;
+          if (pass == 0) cnt[b + 1]++;
+          else m->bcells[m->bstart[b] + cnt[b]++] = c;
+        }
+    }
+    if (pass == 0) {
+      m->bstart = (int64_t *)malloc(sizeof(int64_t) * (nb + 1));
+      m->bstart[0] = 0;
+      for (int64_t b = 0; b < nb; b++) m->bstart[b + 1] = m->bstart[b] + cnt[b + 1];
+      m->bcells = (int64_t *)malloc(sizeof(int64_t) * (m->bstart[nb] + 1));
+      memset(cnt, 0, sizeof(int64_t) * (nb + 1));
+    }
+  }
+  free(cnt);
+  return OR_OK;
+}
+
+void or_curv_release(or_curv *m) {
+  free(m->bstart);
+  free(m->bcells);
+  m->bstart = m->bcells = NULL;
+}
+
+/* cell containing x (the largest cell index on shared faces), -1 if outside */
+static int64_t curv_locate(const or_curv *m, const double *x, double *xi) {
+  int bi = (int)((x[0] - m->bx0) / m->bh), bj = (int)((x[1] - m->by0) / m->bh);
+  if (bi < 0 || bj < 0 || bi >= m->bnx || bj >= m->bny) return -1;
+  int64_t b = (int64_t)bj * m->bnx + bi, best = -1;
+  double r[2];
+  int n1 = m->p + 1;
+  for (int64_t q = m->bstart[b]; q < m->bstart[b + 1]; q++) {
+    int64_t c = m->bcells[q];
+    if (c <= best) continue;
+    /* bounding box of the support points, widened by 5% for curved edges */
+    double cx0 = 1e300, cx1 = -1e300, cy0 = 1e300, cy1 = -1e300;
+    for (int j = 0; j < n1 * n1; j++) {
+      const double *X = m->xyz + 2 * m->cell_nodes[c * n1 * n1 + j];
+      if (X[0] < cx0) cx0 = X[0];
+      if (X[0] > cx1) cx1 = X[0];
+      if (X[1] < cy0) cy0 = X[1];
+      if (X[1] > cy1) cy1 = X[1];
+    }
+    double gx = 0.05 * (cx1 - cx0) + 1e-12, gy = 0.05 * (cy1 - cy0) + 1e-12;
+    if (x[0] < cx0 - gx || x[0] > cx1 + gx || x[1] < cy0 - gy || x[1] > cy1 + gy) continue;
+    if (cell_inverse(m, c, x, r)) { best = c; xi[0] = r[0]; xi[1] = r[1]; }
+  }
+  return best;
+}
+
+/* A point within this many reference units of a face counts as on it when the exit
+ * parameter is refined (a node on the face has +-1 only up to rounding). */
+#define OR_FACE_EPS 1e-13
+
+/* Point and tangent of face f of cell c at face parameter t. */
+static void face_curve(const or_curv *m, int64_t c, int f, double t, double *x, double *dx) {
+  int p = m->p, n1 = p + 1;
+  double l[OR_MAXP + 1], dl[OR_MAXP + 1];
+  lagrange(p, m->xref, t, l);
+  lagrange_d(p, m->xref, t, dl);
+  x[0] = x[1] = dx[0] = dx[1] = 0.0;
+  for (int j = 0; j <= p; j++) {
+    int jx = f == 0 ? 0 : (f == 1 ? p : j), jy = f == 2 ? 0 : (f == 3 ? p : j);
+    const double *X = m->xyz + 2 * m->cell_nodes[c * n1 * n1 + jx + n1 * jy];
+    for (int a = 0; a < 2; a++) {
+      x[a] += X[a] * l[j];
+      dx[a] += X[a] * dl[j];
+    }
+  }
+}
+
+/* Nearest point of the mesh boundary to y, over every tagged face: each face sampled at
+ * 65 parameters, then the sign change of d|face(t) - y|^2/dt next to the best sample
+ * bisected.  Returns the cell, with y's projection in its reference coordinates. */
+static int64_t curv_project(const or_curv *m, const double *y, double *xi) {
+  double best = 1e300;
+  int64_t cb = -1;
+  for (int64_t c = 0; c < m->n_cells; c++)
+    for (int f = 0; f < 4; f++) {
+      if (m->face_bc[c * 4 + f] < 0) continue;
+      int jb = 0;
+      double db = 1e300, x[2], dx[2];
+      for (int j = 0; j <= 64; j++) {
+        face_curve(m, c, f, -1.0 + j / 32.0, x, dx);
+        double dd = (x[0] - y[0]) * (x[0] - y[0]) + (x[1] - y[1]) * (x[1] - y[1]);
+        if (dd < db) { db = dd; jb = j; }
+      }
+      double t = -1.0 + jb / 32.0;
+      if (db < best * 4.0 + 1e-30) {
+        /* derivative of the squared distance, h(t) = (face(t) - y) . face'(t) */
+        double lo = t - 1.0 / 32.0, hi = t + 1.0 / 32.0, hl, hh;
+        if (lo < -1.0) lo = -1.0;
+        if (hi > 1.0) hi = 1.0;
+        face_curve(m, c, f, lo, x, dx);
+        hl = (x[0] - y[0]) * dx[0] + (x[1] - y[1]) * dx[1];
+        face_curve(m, c, f, hi, x, dx);
+        hh = (x[0] - y[0]) * dx[0] + (x[1] - y[1]) * dx[1];
+        if (hl < 0.0 && hh > 0.0) {
+          for (int it = 0; it < 100; it++) {
+            double mid = 0.5 * (lo + hi);
+            face_curve(m, c, f, mid, x, dx);
+            if ((x[0] - y[0]) * dx[0] + (x[1] - y[1]) * dx[1] < 0.0) lo = mid; else hi = mid;
+          }
+          t = 0.5 * (lo + hi);
+        } else {
+          t = hl >= 0.0 ? lo : hi;   /* the minimum sits at an end of the bracket */
+        }
+        face_curve(m, c, f, t, x, dx);
+        double dd = (x[0] - y[0]) * (x[0] - y[0]) + (x[1] - y[1]) * (x[1] - y[1]);
+        if (dd < best) {
+          best = dd;
+          cb = c;
+          xi[0] = f == 0 ? -1.0 : (f == 1 ? 1.0 : t);
+          xi[1] = f == 2 ? -1.0 : (f == 3 ? 1.0 : t);
+        }
+      }
+    }
+  return cb;
+}
+
+/* How far x0 + s v lies beyond face f of cell c, in the reference coordinate normal
+ * to that face (<= 0 on the cell's side); 0 if the inverse map does not converge. */
+static int face_excess(const or_curv *m, int64_t c, int f, const double *x0, const double *v, double s,
+                       const double *start, double *g) {
+  double x[2] = {x0[0] + s * v[0], x0[1] + s * v[1]}, r[2];
+  if (!cell_newton(m, c, x, start, r)) return 0;
+  double e = f == 0 ? -r[0] : (f == 1 ? r[0] : (f == 2 ? -r[1] : r[1]));
+  *g = e - 1.0;
+  return 1;
+}
+
+/* The crossing of x0 + s v with face f of cell c, given the bracket [lo, hi] of the
+ * exit from point location: bisection on the face-normal reference coordinate
+ * (face_excess <= OR_FACE_EPS on the cell's side), with the lower end stepped back from
+ * lo until it lies on the cell's side.  The crossing must lie on the face itself
+ * (tangential coordinate within 1e-9 of [-1,1]); -1 if there is none. */
+static double exit_through_face(const or_curv *m, int64_t c, int f, const double *x0, const double *v, double lo,
+                                double hi, const double *start) {
+  double ga = 1.0, gb, a = lo, bnd = hi;
+  for (double back = 1e-9; back < 2.0; back *= 10.0) {
+    a = lo - back > 0.0 ? lo - back : 0.0;
+    if (face_excess(m, c, f, x0, v, a, start, &ga) && ga <= OR_FACE_EPS) break;
+    ga = 1.0;
+    if (a == 0.0) break;
+  }
+  if (ga > OR_FACE_EPS) return -1.0;
+  /* the upper end: hi, or further along the path if hi is still on the cell's side */
+  for (double fwd = 0.0; fwd <= 1.0; fwd = fwd == 0.0 ? 1e-9 : fwd * 10.0) {
+    bnd = hi + fwd < 1.0 ? hi + fwd : 1.0;
+    if (face_excess(m, c, f, x0, v, bnd, start, &gb) && gb > OR_FACE_EPS) break;
+    gb = -1.0;
+    if (bnd == 1.0) break;
+  }
+  if (gb <= OR_FACE_EPS) return -1.0;
+  for (int it = 0; it < 100; it++) {
+    double mid = 0.5 * (a + bnd), g;
+    if (!face_excess(m, c, f, x0, v, mid, start, &g)) return -1.0;
+    if (g <= OR_FACE_EPS) a = mid; else bnd = mid;
+  }
+  /* tangential reference coordinate of the crossing */
+  double x[2] = {x0[0] + a * v[0], x0[1] + a * v[1]}, r[2];
+  if (!cell_newton(m, c, x, start, r)) return -1.0;
+  double tt = (f == 0 || f == 1) ? r[1] : r[0];
+  if (fabs(tt) > 1.0 + 1e-9) return -1.0;
+  return a;
+}
+
+/* Where x0 + s v (x0 inside, s in [0,1]) first leaves the mesh, and through which
+ * boundary tag.  Bisection on point location brackets the exit as lo; every tagged
+ * face passing within 1e-6 (reference units) of x0 + lo v is a candidate, and on each
+ * the crossing is refined without tolerance (face_excess).  The smallest crossing wins;
+ * crossings within 1e-10 of it are the same point (a junction of boundary segments),
+ * where the smallest tag wins. */
+static double curv_exit(const or_curv *m, const double *x0, const double *v, int *bc) {
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 80; it++) {
+    double mid = 0.5 * (lo + hi), x[2] = {x0[0] + mid * v[0], x0[1] + mid * v[1]}, xi[2];
+    if (curv_locate(m, x, xi) >= 0) lo = mid; else hi = mid;
+  }
+  double x[2] = {x0[0] + lo * v[0], x0[1] + lo * v[1]};
+  *bc = -1;
+  int bi = (int)((x[0] - m->bx0) / m->bh), bj = (int)((x[1] - m->by0) / m->bh);
+  if (bi < 0 || bj < 0 || bi >= m->bnx || bj >= m->bny) return lo;
+  int64_t b = (int64_t)bj * m->bnx + bi;
+  int n1 = m->p + 1;
+  double sbest = 1e300;
+  for (int64_t q = m->bstart[b]; q < m->bstart[b + 1]; q++) {
+    int64_t c = m->bcells[q];
+    /* unclamped reference coordinates of x in c, from the nearest support point or a
+     * 3x3 grid of starts */
+    const int64_t *cn = m->cell_nodes + c * n1 * n1;
+    double best = 1e300, r0[2] = {0, 0}, r[2];
+    for (int jy = 0; jy <= m->p; jy++)
+      for (int jx = 0; jx <= m->p; jx++) {
+        const double *X = m->xyz + 2 * cn[jx + n1 * jy];
+        double d = (X[0] - x[0]) * (X[0] - x[0]) + (X[1] - x[1]) * (X[1] - x[1]);
+        if (d < best) { best = d; r0[0] = m->xref[jx]; r0[1] = m->xref[jy]; }
+      }
+    int ok = cell_newton(m, c, x, r0, r) && fabs(r[0]) <= 1.0 + 1e-6 && fabs(r[1]) <= 1.0 + 1e-6;
+    for (int t = 0; !ok && t < 9; t++) {
+      double s0[2] = {-0.6 + 0.6 * (t % 3), -0.6 + 0.6 * (t / 3)};
+      ok = cell_newton(m, c, x, s0, r) && fabs(r[0]) <= 1.0 + 1e-6 && fabs(r[1]) <= 1.0 + 1e-6;
+    }
+    if (!ok) continue;
+    for (int f = 0; f < 4; f++) {
+      int tag = m->face_bc[c * 4 + f];
+      double dn = f == 0 ? fabs(r[0] + 1.0) : (f == 1 ? fabs(r[0] - 1.0) : (f == 2 ? fabs(r[1] + 1.0) : fabs(r[1] - 1.0)));
+      if (tag < 0 || dn > 1e-6) continue;
+      double s_f = exit_through_face(m, c, f, x0, v, lo, hi, r);
+      if (s_f < 0.0) continue;
+      if (s_f < sbest - 1e-10) {
+        sbest = s_f;
+        *bc = tag;
+      } else if (s_f <= sbest + 1e-10) {
+        if (s_f < sbest) sbest = s_f;
+        if (tag < *bc) *bc = tag;
+      }
+    }
+  }
+  return *bc < 0 ? lo : sbest;
+}
+
+/* Departure-point geometry of the Q (velocity, node k) pairs, row i stored at index
+ * i * stride: kind 0 interpolates population src in cell at xi; kind 1 takes the inlet
+ * state of boundary src.  *thermal = a thermal wall met by some path of node k, else -1.
+ * Returns OR_OK, or OR_EGEOM with the failing velocity in *bad_i. */
+static int curv_node_geometry(const or_curv *m, int64_t k, int64_t stride, int64_t *cell, double *xi, int *src,
+                              int *kind, int *thermal, int *bad_i) {
+  *thermal = -1;
+  const double *xk = m->xyz + 2 * k;
+  for (int i = 0; i < m->Q; i++) {
+    int64_t q = (int64_t)i * stride;
+    double d[2] = {m->dt * m->zeta[2 * i], m->dt * m->zeta[2 * i + 1]};
+    double dp[2] = {xk[0] - d[0], xk[1] - d[1]}, r[2];
+    int64_t c = curv_locate(m, dp, r);
+    src[q] = i;
+    kind[q] = 0;
+    if (c < 0) {
+      /* the backward path leaves the mesh: the first boundary crossed decides */
+      double v[2] = {-d[0], -d[1]};
+      int bc;
+      double s = curv_exit(m, xk, v, &bc);
+      if (bc < 0) { *bad_i = i; return OR_EGEOM; }
+      int bk = m->bc_kind[bc];
+      if (bk == OR_BC_WALL) {
+        /* Sec. 3.3.2: remaining path travelled back from the wall point x_k - s d */
+        double xw[2] = {xk[0] - s * d[0], xk[1] - s * d[1]};
+        for (int a = 0; a < 2; a++) dp[a] = xw[a] + (d[a] - (xk[a] - xw[a]));
+        c = curv_locate(m, dp, r);
+        /* reflected out of the mesh again (a corner, a thin gap): nearest boundary point */
+        if (c < 0) c = curv_project(m, dp, r);
+        if (c < 0) { *bad_i = i; return OR_EGEOM; }
+        src[q] = m->opp[i];
+        if (!isnan(m->bc_val[6 * bc + 5])) *thermal = bc;
+      } else if (bk == OR_BC_INLET) {
+        kind[q] = 1;
+        src[q] = bc;
+      } else if (bk == OR_BC_OUTLET) {
+        /* Sec. 3.3.3: population i at x_k + d; outside the mesh, at the nearest
+         * boundary point (orthogonal projection) */
+        dp[0] = xk[0] + d[0];
+        dp[1] = xk[1] + d[1];
+        c = curv_locate(m, dp, r);
+        if (c < 0) c = curv_project(m, dp, r);
+        if (c < 0) { *bad_i = i; return OR_EGEOM; }
+      } else {
+        *bad_i = i;
+        return OR_EGEOM;
+      }
+    }
+    cell[q] = c;
+    xi[2 * q] = r[0];
+    xi[2 * q + 1] = r[1];
+  }
+  return OR_OK;
+}
+
+/* Departure-point geometry of every (velocity, node) pair, rows [Q][N]. */
+int or_curv_geometry(const or_curv *m, int64_t *cell, double *xi, int *src, int *kind, int *thermal_bc,
+                     int64_t *err) {
+  int64_t N = m->n_nodes;
+  int status = OR_OK;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < N; k++) {
+    if (status != OR_OK) continue;
+    int bad = -1;
+    int rc = curv_node_geometry(m, k, N, cell + k, xi + 2 * k, src + k, kind + k, thermal_bc + k, &bad);
+    if (rc != OR_OK) {
+#pragma omp critical
+      { status = rc; err[0] = k; err[1] = bad; }
+    }
+  }
+  return status;
+}
+
+/* One node's new populations (Sec. 3.2-3.4): interpolate every row of its geometry
+ * (rows at index i * stride), the thermal-wall correction, then BGK relaxation and the
+ * force term.  out[i] = f_i, out[Q + i] = g_i, at index i * ostride. */
+static void curv_node_update(const or_curv *m, const double *H, const double *inlet, const double *in,
+                             const int64_t *cell, const double *xi, const int *src, const int *kind, int64_t stride,
+                             int thermal, double *out, int64_t ostride) {
+  int Q = m->Q, D = 2, p = m->p, n1 = p + 1;
+  int64_t N = m->n_nodes;
+  double cv = 1.0 / (m->gamma - 1.0);
+  double fs[OR_MAXQ], gs[OR_MAXQ], fe[OR_MAXQ], fe2[OR_MAXQ];
+  for (int i = 0; i < Q; i++) {
+    int64_t q = (int64_t)i * stride;
+    if (kind[q] == 1) {
+      fs[i] = inlet[(size_t)src[q] * 2 * Q + i];
+      gs[i] = inlet[(size_t)src[q] * 2 * Q + Q + i];
+      continue;
+    }
+    double lx[OR_MAXP + 1], ly[OR_MAXP + 1];
+    lagrange(p, m->xref, xi[2 * q], lx);
+    lagrange(p, m->xref, xi[2 * q + 1], ly);
+    const int64_t *cn = m->cell_nodes + cell[q] * n1 * n1;
+    const double *F = in + (size_t)src[q] * N, *G = in + ((size_t)Q + src[q]) * N;
+    double a = 0, b = 0;
+    for (int jy = 0; jy <= p; jy++)
+      for (int jx = 0; jx <= p; jx++) {
+        double wgt = lx[jx] * ly[jy];
+        a += wgt * F[cn[jx + n1 * jy]];
+        b += wgt * G[cn[jx + n1 * jy]];
+      }
+    fs[i] = a;
+    gs[i] = b;
+  }
+  double rho, u[3], T;
+  node_moments(D, Q, m->zeta, cv, fs, gs, &rho, u, &T);
+  if (thermal >= 0) {
+    double Tw = m->bc_val[6 * thermal + 5];
+    feq_all(D, Q, m->w, H, m->T0, rho, u, Tw, fe);
+    feq_all(D, Q, m->w, H, m->T0, rho, u, T, fe2);
+    for (int i = 0; i < Q; i++) {
+      fs[i] += fe[i] - fe2[i];
+      gs[i] += Tw * (2.0 * cv - D) * fe[i] - T * (2.0 * cv - D) * fe2[i];
+    }
+    T = Tw;
+  }
+  if (m->relax_mode == 2) {
+    for (int i = 0; i < Q; i++) {
+      out[(size_t)i * ostride] = fs[i];
+      out[((size_t)Q + i) * ostride] = gs[i];
+    }
+    return;
+  }
+  double tb = m->tau_bar;
+  if (m->relax_mode == 1) tb = m->mu_ref * pow(T / m->T_ref, m->mu_exp) / (rho * T * m->dt) + 0.5;
+  feq_all(D, Q, m->w, H, m->T0, rho, u, T, fe);
+  double gfac = T * (2.0 * cv - D);
+  int has_force = m->force[0] != 0.0 || m->force[1] != 0.0;
+  if (has_force) {
+    double u2[3] = {u[0] + m->force[0] * m->dt / rho, u[1] + m->force[1] * m->dt / rho, 0.0};
+    feq_all(D, Q, m->w, H, m->T0, rho, u2, T, fe2);
+  }
+  for (int i = 0; i < Q; i++) {
+    double fo = fs[i] - (fs[i] - fe[i]) / tb;
+    double go = gs[i] - (gs[i] - gfac * fe[i]) / tb;
+    if (has_force) {
+      fo += fe2[i] - fe[i];
+      go += gfac * (fe2[i] - fe[i]);
+    }
+    out[(size_t)i * ostride] = fo;
+    out[((size_t)Q + i) * ostride] = go;
+  }
+}
+
+/* The step's inputs shared by all nodes: the populations to stream (scaled by
+ * mass_ref / M first when the mass fix is on, M = sum_k V_k rho_k) and the inlet
+ * equilibria [n_bc][2Q].  *scaled is the buffer to free (or NULL). */
+static const double *curv_prepare(const or_curv *m, const double *pin, double **scaled, double **inlet) {
+  int Q = m->Q, D = 2;
+  int64_t N = m->n_nodes;
+  double cv = 1.0 / (m->gamma - 1.0);
+  double *H = make_htab(D, Q, m->zeta, m->T0);
+  const double *in = pin;
+  *scaled = NULL;
+  if (m->mass_fix) {
+    double M = 0.0;
+    for (int64_t k = 0; k < N; k++) {
+      double r = 0;
+      for (int i = 0; i < Q; i++) r += pin[(size_t)i * N + k];
+      M += m->node_vol[k] * r;
+    }
+    *scaled = (double *)malloc(sizeof(double) * 2 * (size_t)Q * N);
+    for (size_t q = 0; q < 2 * (size_t)Q * N; q++) (*scaled)[q] = (m->mass_ref / M) * pin[q];
+    in = *scaled;
+  }
+  *inlet = (double *)calloc((size_t)(m->n_bc > 0 ? m->n_bc : 1) * 2 * Q, sizeof(double));
+  for (int b = 0; b < m->n_bc; b++) {
+    if (m->bc_kind[b] != OR_BC_INLET) continue;
+    const double *v = m->bc_val + b * 6;
+    feq_all(D, Q, m->w, H, m->T0, v[0], v + 1, v[4], *inlet + (size_t)b * 2 * Q);
+    for (int i = 0; i < Q; i++)
+      (*inlet)[(size_t)b * 2 * Q + Q + i] = v[4] * (2.0 * cv - D) * (*inlet)[(size_t)b * 2 * Q + i];
+  }
+  free(H);
+  return in;
+}
+
+int or_curv_step(const or_curv *m, const int64_t *cell, const double *xi, const int *src, const int *kind,
+                 const int *thermal_bc, const double *pin, double *pout) {
+  int64_t N = m->n_nodes;
+  double *scaled, *inlet;
+  const double *in = curv_prepare(m, pin, &scaled, &inlet);
+  double *H = make_htab(2, m->Q, m->zeta, m->T0);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t k = 0; k < N; k++)
+    curv_node_update(m, H, inlet, in, cell + k, xi + 2 * k, src + k, kind + k, N, thermal_bc[k], pout + k, N);
+  free(inlet);
+  free(scaled);
+  free(H);
+  return OR_OK;
+}
+
+/* The step at a sample of nodes only (geometry computed for those nodes alone):
+ * out[n][2Q] = (f_0..f_Q-1, g_0..g_Q-1) of node nodes[n].  err = (node, velocity) of
+ * a geometry failure. */
+int or_curv_step_nodes(const or_curv *m, const double *pin, const int64_t *nodes, int64_t n, double *out,
+                       int64_t *err) {
+  int Q = m->Q;
+  double *scaled, *inlet;
+  const double *in = curv_prepare(m, pin, &scaled, &inlet);
+  double *H = make_htab(2, Q, m->zeta, m->T0);
+  int status = OR_OK;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t s = 0; s < n; s++) {
+    if (status != OR_OK) continue;
+    int64_t cell[OR_MAXQ];
+    double xi[2 * OR_MAXQ];
+    int src[OR_MAXQ], kind[OR_MAXQ], th, bad = -1;
+    int rc = curv_node_geometry(m, nodes[s], 1, cell, xi, src, kind, &th, &bad);
+    if (rc != OR_OK) {
+#pragma omp critical
+      { status = rc; err[0] = nodes[s]; err[1] = bad; }
+      continue;
+    }
+    curv_node_update(m, H, inlet, in, cell, xi, src, kind, 1, th, out + s * 2 * Q, 1);
+  }
+  free(inlet);
+  free(scaled);
+  free(H);
+  return status;
+}
+
+/* populations in equilibrium with nodal fields, any mesh (u is [N][D]) */
+int or_init_generic(int D, int Q, const double *zeta, const double *w, double T0, double gamma, int64_t N,
+                    const double *rho, const double *u, const double *T, double *pop) {
+  double cv = 1.0 / (gamma - 1.0);
+  double *H = make_htab(D, Q, zeta, T0);
+#pragma omp parallel for
+  for (int64_t k = 0; k < N; k++) {
+    double fe[OR_MAXQ], uk[3] = {0, 0, 0};
+    for (int a = 0; a < D; a++) uk[a] = u[k * D + a];
+    feq_all(D, Q, w, H, T0, rho[k], uk, T[k], fe);
+    for (int i = 0; i < Q; i++) {
+      pop[(size_t)i * N + k] = fe[i];
+      pop[((size_t)Q + i) * N + k] = T[k] * (2.0 * cv - D) * fe[i];
+    }
+  }
+  free(H);
+  return OR_OK;
+}
+
+/* point location of one point (test hook) */
+int64_t or_curv_locate(const or_curv *m, const double *x, double *xi) { return curv_locate(m, x, xi); }
+double or_curv_exit(const or_curv *m, const double *x0, const double *v, int *bc) { return curv_exit(m, x0, v, bc); }

@@ -1,0 +1,176 @@
+// CSR step kernel for curvilinear meshes (gfx950): one node per lane; every
+// (velocity, node) row names the cell holding the departure point, the source
+// population (bounce-back: the opposite one) and the (p+1)^2 interpolation weights
+// (eq:intf), or an inlet state (Sec. 3.3.1).  For Q = 25 (D2V25) the 50 streamed
+// values stay in registers between the moments and the relaxation, so every row's
+// weights are read once per step.
+#include <hip/hip_runtime.h>
+
+#include "sllbm_device_common.h"
+#include "sllbm_kernels.h"
+
+namespace sllbm {
+
+template <typename T> struct CsrW;
+template <> struct CsrW<double> {
+  __device__ static const double *get(const DevCsrPlan &p) { return p.row_w64; }
+};
+template <> struct CsrW<float> {
+  __device__ static const float *get(const DevCsrPlan &p) { return p.row_w32; }
+};
+
+template <typename T, int P>
+__device__ __forceinline__ void stream_csr(const DevCsrPlan &pl, const StepArgs &sa, const T *__restrict__ pin,
+                                           int64_t k, int i, double scale, double &fv, double &gv) {
+  constexpr int NPC = (P + 1) * (P + 1);
+  const int64_t N = pl.N;
+  const int c = pl.row_cell[(size_t)i * N + k];
+  const int src = pl.row_src[(size_t)i * N + k];
+  if (c < 0) {  // equilibrium inlet (Sec. 3.3.1)
+    const double *st = sa.inlet + 5 * src;
+    EqNode e = eq_prepare(st[0], st[1], st[2], st[3], st[4], sa, 2);
+    fv = eq_f(e, pl.vel + 8 * i);
+    gv = st[4] * sa.gbase * fv;
+    return;
+  }
+  const int32_t *cn = pl.cell_nodes + (size_t)c * NPC;
+  const T *F = pin + (size_t)src * N;
+  const T *G = pin + ((size_t)pl.Q + src) * N;
+  const T *W = CsrW<T>::get(pl) + (size_t)i * NPC * N + k;
+  T a = 0, b = 0;
+#pragma unroll
+  for (int j = 0; j < NPC; j++) {
+    const T w = W[(size_t)j * N];
+    const int n = cn[j];
+    a += w * F[n];
+    b += w * G[n];
+  }
+  fv = scale * (double)a;
+  gv = scale * (double)b;
+}
+
+// relaxation of one node given its streamed populations (thermal wall, BGK, force)
+struct NodeRelax {
+  EqNode eq, eqp, eqf;
+  bool thermal, force;
+  double Tpre, gT, itau;
+};
+
+__device__ __forceinline__ NodeRelax node_relax(const StepArgs &sa, double rho, double j0, double j1, double E,
+                                                double Tw) {
+  NodeRelax s;
+  double u0 = j0 / rho, u1 = j1 / rho;
+  s.Tpre = (E - rho * (u0 * u0 + u1 * u1)) / (2.0 * rho * sa.cv);
+  s.thermal = (Tw == Tw);
+  double Tn = s.thermal ? Tw : s.Tpre;
+  s.eq = eq_prepare(rho, u0, u1, 0.0, Tn, sa, 2);
+  if (s.thermal) s.eqp = eq_prepare(rho, u0, u1, 0.0, s.Tpre, sa, 2);
+  s.force = sa.has_force;
+  if (s.force) {
+    double r = sa.dt / rho;
+    s.eqf = eq_prepare(rho, u0 + sa.force[0] * r, u1 + sa.force[1] * r, 0.0, Tn, sa, 2);
+  }
+  s.itau = 0.0;
+  if (sa.relax_mode == 0) s.itau = 1.0 / sa.tau_bar;
+  if (sa.relax_mode == 1) s.itau = 1.0 / (sa.mu_ref * pow(Tn / sa.T_ref, sa.mu_exp) / (rho * Tn * sa.dt) + 0.5);
+  s.gT = Tn * sa.gbase;
+  return s;
+}
+
+__device__ __forceinline__ void relax_one(const NodeRelax &s, const StepArgs &sa, const double *vi, double f, double g,
+                                          double &fo, double &go) {
+  double fe = eq_f(s.eq, vi);
+  if (s.thermal) {  // eq:thermalBC
+    double fp = eq_f(s.eqp, vi);
+    f += fe - fp;
+    g += s.gT * fe - s.Tpre * sa.gbase * fp;
+  }
+  fo = f;
+  go = g;
+  if (sa.relax_mode != 2) {
+    fo = f - (f - fe) * s.itau;
+    go = g - (g - s.gT * fe) * s.itau;
+    if (s.force) {
+      double df = eq_f(s.eqf, vi) - fe;
+      fo += df;
+      go += s.gT * df;
+    }
+  }
+}
+
+template <typename T, int P, int QS>
+__global__ void __launch_bounds__(kBlock) k_step_csr(const DevCsrPlan pl, const StepArgs sa, const T *__restrict__ pin,
+                                                      T *__restrict__ pout) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= pl.N) return;
+  const int64_t N = pl.N;
+  const double scale = sa.scale ? *sa.scale : 1.0;
+  const double Tw = pl.node_Tw[k];
+  double rho = 0, j0 = 0, j1 = 0, E = 0;
+  if constexpr (QS > 0) {
+    double fs[QS], gs[QS];
+#pragma unroll
+    for (int i = 0; i < QS; i++) {
+      stream_csr<T, P>(pl, sa, pin, k, i, scale, fs[i], gs[i]);
+      const double *vi = pl.vel + 8 * i;
+      rho += fs[i];
+      j0 += vi[0] * fs[i];
+      j1 += vi[1] * fs[i];
+      E += (vi[0] * vi[0] + vi[1] * vi[1]) * fs[i] + gs[i];
+    }
+    NodeRelax s = node_relax(sa, rho, j0, j1, E, Tw);
+#pragma unroll
+    for (int i = 0; i < QS; i++) {
+      double fo, go;
+      relax_one(s, sa, pl.vel + 8 * i, fs[i], gs[i], fo, go);
+      pout[(size_t)i * N + k] = (T)fo;
+      pout[((size_t)QS + i) * N + k] = (T)go;
+    }
+  } else {
+    const int Q = pl.Q;
+    for (int i = 0; i < Q; i++) {
+      double f, g;
+      stream_csr<T, P>(pl, sa, pin, k, i, scale, f, g);
+      const double *vi = pl.vel + 8 * i;
+      rho += f;
+      j0 += vi[0] * f;
+      j1 += vi[1] * f;
+      E += (vi[0] * vi[0] + vi[1] * vi[1]) * f + g;
+    }
+    NodeRelax s = node_relax(sa, rho, j0, j1, E, Tw);
+    for (int i = 0; i < Q; i++) {
+      double f, g, fo, go;
+      stream_csr<T, P>(pl, sa, pin, k, i, scale, f, g);
+      relax_one(s, sa, pl.vel + 8 * i, f, g, fo, go);
+      pout[(size_t)i * N + k] = (T)fo;
+      pout[((size_t)Q + i) * N + k] = (T)go;
+    }
+  }
+}
+
+namespace {
+template <typename T, int P>
+void launch_csr_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
+  dim3 grid((unsigned)((Pl->cp.N + kBlock - 1) / kBlock));
+  if (Pl->cp.Q == 25)
+    hipLaunchKernelGGL((k_step_csr<T, P, 25>), grid, dim3(kBlock), 0, s, Pl->cp, a, (const T *)pin, (T *)pout);
+  else
+    hipLaunchKernelGGL((k_step_csr<T, P, 0>), grid, dim3(kBlock), 0, s, Pl->cp, a, (const T *)pin, (T *)pout);
+}
+}  // namespace
+
+int launch_step_csr(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
+  int p = Pl->mesh.p;
+  bool f32 = Pl->prec == SLLBM_F32;
+#define CCASE(PP)                                                         \
+  if (p == PP) {                                                          \
+    if (f32) launch_csr_t<float, PP>(Pl, a, pin, pout, s);                \
+    else launch_csr_t<double, PP>(Pl, a, pin, pout, s);                   \
+    return SLLBM_OK;                                                      \
+  }
+  CCASE(1) CCASE(2) CCASE(3) CCASE(4)
+#undef CCASE
+  return fail(SLLBM_EUNSUPPORTED, "no curvilinear GPU kernel for order %d (p must be 1..4)", p);
+}
+
+}  // namespace sllbm

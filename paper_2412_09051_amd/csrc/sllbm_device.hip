@@ -214,13 +214,26 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
     cp.N = m.n_nodes;
     cp.npc = 1;
     for (int d = 0; d < m.dim; d++) cp.npc *= (m.p + 1);
-    UP(m.cell_nodes, cp.cell_nodes);
+    std::vector<int32_t> cn32(m.cell_nodes.begin(), m.cell_nodes.end());
+    UP(cn32, cp.cell_nodes);
     UP(t.row_cell, cp.row_cell);
     UP(t.row_src, cp.row_src);
-    std::vector<float> w32(t.row_w.size());
-    for (size_t r = 0; r < t.row_w.size(); r += cp.npc) round_weights_f32(&t.row_w[r], cp.npc, &w32[r]);
-    UP(t.row_w, cp.row_w64);
-    UP(w32, cp.row_w32);
+    if (prec == SLLBM_F32) {
+      // float weights per row (strided by N in the SoA layout), sum kept at 1
+      std::vector<float> w32(t.row_w.size());
+      int64_t N = m.n_nodes;
+      double wr[kMaxP * kMaxP + 2 * kMaxP + 1];
+      float fr[kMaxP * kMaxP + 2 * kMaxP + 1];
+      for (int i = 0; i < V.Q; i++)
+        for (int64_t k = 0; k < N; k++) {
+          for (int j = 0; j < cp.npc; j++) wr[j] = t.row_w[((size_t)i * cp.npc + j) * N + k];
+          round_weights_f32(wr, cp.npc, fr);
+          for (int j = 0; j < cp.npc; j++) w32[((size_t)i * cp.npc + j) * N + k] = fr[j];
+        }
+      UP(w32, cp.row_w32);
+    } else {
+      UP(t.row_w, cp.row_w64);
+    }
     UP(t.node_Tw, cp.node_Tw);
     cp.vel = vel_d;
     cp.vol = vol_d;

@@ -344,7 +344,7 @@ int build_tensor_tables(const Mesh &m, const VelSet &v, double dt, HostTables &t
   t.nfaces = 0;
   if (bounded < 0) return SLLBM_OK;
   int a = bounded;
-  double lo = m.edges[a][0], hi = m.edges[a][m.ncell[a]], L = hi - lo;
+  double lo = m.edges[a][0], hi = m.edges[a][m.ncell[a]];
   double dmax = 0.0;
   for (int i = 0; i < Q; i++) dmax = std::max(dmax, std::fabs(dt * v.zeta[i * D + a]));
   for (int side = 0; side < 2; side++) {
@@ -378,13 +378,9 @@ int build_tensor_tables(const Mesh &m, const VelSet &v, double dt, HostTables &t
             // Sec. 3.3.2: wall at fraction s of the backward path; remaining path back
             // from the wall; opposite population at x_k + (1 - 2 s) dt zeta_i.
             double s = (x - (side == 0 ? lo : hi)) / d;
-            double y = x + (1.0 - 2.0 * s) * d;
-            double tol = 1e-12 * L;
-            if (y < lo && y > lo - tol) y = lo;
-            if (y > hi && y < hi + tol) y = hi;
-            if (y < lo || y > hi)
-              return fail(SLLBM_EGEOM, "bounce-back departure point leaves the domain again "
-                                       "(axis %d layer %d velocity %d)", a, l, i);
+            // a reflected point outside the domain (a channel thinner than the path,
+            // or rounding) is replaced by its nearest boundary point
+            double y = std::max(lo, std::min(hi, x + (1.0 - 2.0 * s) * d));
             e.kind = EXC_WALL;
             e.src = v.opp[i];
             int c;
@@ -397,13 +393,9 @@ int build_tensor_tables(const Mesh &m, const VelSet &v, double dt, HostTables &t
               if (b != a) e.tab[b] = ab[b].table(-(1.0 - 2.0 * s) * dt * v.zeta[i * D + b]);
             if (std::isfinite(B.T_wall)) thermal = true;
           } else if (B.kind == SLLBM_BC_OUTLET) {
-            // Sec. 3.3.3: population i at x_k + dt zeta_i, clamped to the domain.
-            double sf = 1.0;
-            double y = x + d;
-            if (y > hi) sf = std::min(sf, (hi - x) / d);
-            if (y < lo) sf = std::min(sf, (lo - x) / d);
-            y = x + sf * d;
-            y = std::max(lo, std::min(hi, y));
+            // Sec. 3.3.3: population i at x_k + dt zeta_i; outside the domain, its
+            // nearest boundary point (the bounded coordinate clamped)
+            double y = std::max(lo, std::min(hi, x + d));
             e.kind = EXC_OUTLET;
             e.src = i;
             int c;
@@ -413,7 +405,7 @@ int build_tensor_tables(const Mesh &m, const VelSet &v, double dt, HostTables &t
             lagrange_weights(m.xref, xi, e.w);
             round_weights_f32(e.w, p + 1, e.w32);
             for (int b = 0; b < D; b++)
-              if (b != a) e.tab[b] = ab[b].table(-sf * dt * v.zeta[i * D + b]);
+              if (b != a) e.tab[b] = ab[b].table(-dt * v.zeta[i * D + b]);
           } else {
             return fail(SLLBM_EINVAL, "bounded face with boundary kind %d", B.kind);
           }

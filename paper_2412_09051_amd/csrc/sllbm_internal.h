@@ -105,10 +105,10 @@ struct DevCsrPlan {
   int dim, p, Q;
   int64_t N;
   int npc;                  // support points per cell, (p+1)^dim
-  const int64_t *cell_nodes;// [n_cells][npc]
+  const int32_t *cell_nodes;// [n_cells][npc]
   const int32_t *row_cell;  // [Q][N] cell of the departure point, -1 inlet
   const int32_t *row_src;   // [Q][N] source velocity, or bc index for inlet rows
-  const double *row_w64;    // [Q][N][npc]
+  const double *row_w64;    // [Q][npc][N] (SoA over nodes: coalesced per weight)
   const float *row_w32;
   const double *node_Tw;    // [N] thermal-wall temperature, NaN = none
   const double *vel;

@@ -35,6 +35,7 @@ template <> struct TileShape<3, 2> { static constexpr int CX = 4, CY = 4, CZ = 4
 template <> struct TileShape<3, 3> { static constexpr int CX = 4, CY = 4, CZ = 2; };
 template <> struct TileShape<3, 4> { static constexpr int CX = 2, CY = 2, CZ = 2; };
 
+int launch_step_csr(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout, hipStream_t s);
 int launch_step_tile(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout, hipStream_t s);
 int launch_init(sllbm_plan_s *P, const StepArgs &a, const double *rho, const double *u, const double *T, void *pop,
                 hipStream_t s);

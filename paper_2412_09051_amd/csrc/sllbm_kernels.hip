@@ -274,7 +274,12 @@ int dispatch_gather(sllbm_plan_s *Pl, const StepArgs &a, const Slab &sl, const v
 }  // namespace
 
 int launch_step(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
-  if (Pl->kernel != 0) return fail(SLLBM_EUNSUPPORTED, "curvilinear step kernel not available");
+  if (Pl->kernel == 1) {
+    int rc = launch_step_csr(Pl, a, pin, pout, s);
+    if (rc) return rc;
+    HIP_TRY(hipGetLastError());
+    return SLLBM_OK;
+  }
   const DevTensorPlan &tp = Pl->tp;
   auto gather = [&](const Slab &sl) {
     return Pl->prec == SLLBM_F32 ? dispatch_gather<float>(Pl, a, sl, pin, pout, s)

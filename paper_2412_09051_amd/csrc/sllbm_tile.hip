@@ -106,8 +106,6 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
   constexpr int XS = RZ * RY * TX;           // one population's x-pass output
   constexpr int YS = RZ * TY * TX;           // one population's y-pass output (3D)
   constexpr int NST = (SS + BS - 1) / BS;      // staged elements per thread and population
-  constexpr int NXP = (XS + BS - 1) / BS;
-  constexpr int NYP = (YS + BS - 1) / BS;
   constexpr int NW = TX + TY + TZ;           // weight rows: one per tile position and axis
   static_assert(NW <= BS, "weight rows exceed the workgroup");
   __shared__ T S[2 * SS];

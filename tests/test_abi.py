@@ -94,13 +94,49 @@ def test_two_bounded_axes_are_unsupported_on_tensor_meshes():
     assert e.value.code == S.SLLBM_EUNSUPPORTED
 
 
-def test_reflected_departure_point_leaving_again_is_a_geometry_error():
+def test_reflected_departure_point_leaving_again_is_projected():
+    """A channel thinner than the path: the reflected point leaves through the other wall
+    and is taken at its nearest boundary point; the plan builds and counts every pair."""
     mesh = W.TensorMesh(dim=2, p=2, nodes="gll", ncell=(3, 1), edges=[W.uniform_edges(3, 0, 1), np.array([0.0, 0.05])],
                         face_bc=[[-1, -1], [0, 0]], bcs=[W.BC(kind=W.BC_WALL)])
     m = S.sllbm_mesh_build(mesh)
+    plan = S.sllbm_interp_plan(m, S.sllbm_velset_gauss_hermite(2), 0.1)
+    info = S.sllbm_plan_info(plan)
+    y = S.sllbm_mesh_nodes(m)[:, 1]
+    zy = S.sllbm_velset_gauss_hermite(2)["zeta"][:, 1]
+    leaves = sum(int(np.sum((y - 0.1 * z < 0) | (y - 0.1 * z > 0.05))) for z in zy)
+    assert info["n_exceptions"] == leaves
+
+
+def test_curvilinear_plan_on_the_airfoil_grid():
+    """The CSR plan of a small O-grid builds without a GPU; its thermal-wall nodes are
+    the oracle's."""
+    mesh, phys = W.naca_ogrid(n_around=48, n_radial=16, p=4, Ma=1.5)
+    m = S.sllbm_mesh_build(mesh)
+    assert np.max(np.abs(S.sllbm_mesh_nodes(m) - mesh.node_xyz)) == 0.0
+    plan = S.sllbm_interp_plan(m, S.sllbm_velset_gauss_hermite(2), phys.dt)
+    info = S.sllbm_plan_info(plan)
+    assert info["kernel"] == 1 and info["n_nodes"] == mesh.node_xyz.shape[0]
+    o = oracle.CurvOracle(mesh, phys)
+    assert info["n_thermal_nodes"] == int(np.sum(o.g_th >= 0))
+    assert np.max(np.abs(S.sllbm_mesh_volumes(m) - o.node_vol)) < 1e-13 * o.node_vol.max()
+
+
+def test_curvilinear_mesh_validation_errors():
+    mesh, _ = W.naca_ogrid(n_around=16, n_radial=4, p=2)
+    import copy
+    bad = copy.deepcopy(mesh)
+    bad.cell_nodes = bad.cell_nodes.copy()
+    bad.cell_nodes[3, 2] = mesh.node_xyz.shape[0] + 5
     with pytest.raises(S.SllbmError) as e:
-        S.sllbm_interp_plan(m, S.sllbm_velset_gauss_hermite(2), 0.1)
-    assert e.value.code == S.SLLBM_EGEOM and "velocity" in str(e.value)
+        S.sllbm_mesh_build(bad)
+    assert e.value.code == S.SLLBM_EINVAL
+    bad = copy.deepcopy(mesh)
+    bad.cell_face_bc = bad.cell_face_bc.copy()
+    bad.cell_face_bc[0, 2] = 7
+    with pytest.raises(S.SllbmError) as e:
+        S.sllbm_mesh_build(bad)
+    assert e.value.code == S.SLLBM_EINVAL
 
 
 def test_plan_info_without_gpu_counts_boundary_pairs():

@@ -222,3 +222,179 @@ def random_fields(n: int, dim: int, seed: int, rho_amp=0.05, u_amp=0.2, T_amp=0.
         u = u + np.asarray(u_mean)[None, :dim]
     T = 1.0 + T_amp * rng.uniform(-1.0, 1.0, n)
     return rho, u, T
+
+
+# --------------------------------------------------------------------------
+# Curvilinear meshes (2D isoparametric quads of order p)
+# --------------------------------------------------------------------------
+
+@dataclass
+class CurvMesh:
+    """Unique nodes, cell -> node lists (reference order, xi fastest) and per-face
+    boundary tags (xi-, xi+, eta-, eta+; -1 interior)."""
+    p: int
+    nodes: str
+    node_xyz: np.ndarray
+    cell_nodes: np.ndarray
+    cell_face_bc: np.ndarray
+    bcs: List[BC] = field(default_factory=list)
+    dim: int = 2
+
+    @property
+    def num_nodes(self) -> int:
+        return self.node_xyz.shape[0]
+
+
+def _gll_positions(p: int, nodes: str) -> np.ndarray:
+    """Where a mesh places the support points of a cell on [-1, 1] (mesh geometry)."""
+    if nodes == "glc":
+        return -np.cos(np.pi * np.arange(p + 1) / p)
+    if nodes == "equi":
+        return -1.0 + 2.0 * np.arange(p + 1) / p
+    from numpy.polynomial import legendre
+    inner = legendre.Legendre.basis(p).deriv().roots() if p > 1 else np.array([])
+    return np.concatenate([[-1.0], np.sort(np.real(inner)), [1.0]])
+
+
+def _structured_cells(na: int, nr: int, p: int, periodic_a: bool):
+    """Cell -> node lists of a structured (a, r) grid of na x nr cells; node index
+    ia + Na ir with Na = na p (periodic in a) or na p + 1."""
+    Na = na * p if periodic_a else na * p + 1
+    cells = np.zeros((na * nr, (p + 1) ** 2), dtype=np.int64)
+    for cr in range(nr):
+        for ca in range(na):
+            c = ca + na * cr
+            for jy in range(p + 1):
+                for jx in range(p + 1):
+                    ia = ca * p + jx
+                    if periodic_a:
+                        ia %= Na
+                    cells[c, jx + (p + 1) * jy] = ia + Na * (cr * p + jy)
+    return Na, cells
+
+
+def curv_box(mesh: TensorMesh, warp: float = 0.0) -> CurvMesh:
+    """A 2D tensor-product box as an explicit curvilinear mesh (bounded on every face:
+    face_bc of the tensor description gives the four sides' tags); warp > 0 bends the
+    interior with a smooth map that fixes the boundary."""
+    assert mesh.dim == 2
+    p = mesh.p
+    xr = _gll_positions(p, mesh.nodes)
+
+    def axis_coords(a):
+        e = mesh.edges[a]
+        c = [e[0]]
+        for k in range(mesh.ncell[a]):
+            for b in range(1, p + 1):
+                c.append(e[k] + 0.5 * (1 + xr[b]) * (e[k + 1] - e[k]))
+        return np.array(c)
+
+    cx, cy = axis_coords(0), axis_coords(1)
+    X, Y = np.meshgrid(cx, cy)
+    if warp > 0:
+        Lx, Ly = cx[-1] - cx[0], cy[-1] - cy[0]
+        sx = np.sin(np.pi * (X - cx[0]) / Lx) * np.sin(np.pi * (Y - cy[0]) / Ly)
+        X, Y = X + warp * Lx * sx * 0.05, Y + warp * Ly * sx * 0.03
+    xyz = np.stack([X.reshape(-1), Y.reshape(-1)], axis=1)
+    na, nr = mesh.ncell
+    _, cells = _structured_cells(na, nr, p, False)
+    fb = -np.ones((na * nr, 4), dtype=np.int32)
+    for cr in range(nr):
+        for ca in range(na):
+            c = ca + na * cr
+            if ca == 0:
+                fb[c, 0] = mesh.face_bc[0][0]
+            if ca == na - 1:
+                fb[c, 1] = mesh.face_bc[0][1]
+            if cr == 0:
+                fb[c, 2] = mesh.face_bc[1][0]
+            if cr == nr - 1:
+                fb[c, 3] = mesh.face_bc[1][1]
+    return CurvMesh(p=p, nodes=mesh.nodes, node_xyz=xyz, cell_nodes=cells, cell_face_bc=fb, bcs=list(mesh.bcs))
+
+
+def naca0012_surface(theta: np.ndarray) -> np.ndarray:
+    """Closed-trailing-edge NACA 0012 (4-digit thickness law with -0.1036 x^4), chord
+    [0, 1], parametrised by x = (1 + cos theta)/2: upper side for theta in [0, pi]."""
+    x = 0.5 * (1.0 + np.cos(theta))
+    yt = 0.6 * (0.2969 * np.sqrt(np.maximum(x, 0.0)) - 0.1260 * x - 0.3516 * x ** 2 + 0.2843 * x ** 3 - 0.1036 * x ** 4)
+    y = np.where(np.sin(theta) >= 0.0, yt, -yt)
+    return np.stack([x, y], axis=-1)
+
+
+def naca_ogrid(n_around: int = 256, n_radial: int = 128, p: int = 4, nodes: str = "gll", R_out: float = 10.0,
+               dr0: float = 2e-3, Ma: float = 2.0, Re: float = 1e4, T_inf: float = 1.0, gamma: float = 1.4,
+               dt: float = 1.5e-4, smooth: int = 20):
+    """Body-fitted O-grid around a NACA 0012 section: n_around cells around (cosine
+    clustering at the leading and trailing edges through the x = (1+cos)/2 law) and
+    n_radial cells out to a circle of radius R_out about mid-chord, geometric growth
+    from a first cell of dr0.  Node layers are marched along smoothed layer normals
+    (which spreads the trailing-edge fan) out to about one chord, then continued
+    straight to uniformly spaced points of the circle.  Isoparametric cells of order p.
+    Thermal wall on the airfoil at T_w = T_inf; equilibrium inlet on the upstream arc of
+    the outer circle (polar angle about mid-chord beyond +-100 deg), outlet on the rest."""
+    xr = _gll_positions(p, nodes)
+    Na, cells = _structured_cells(n_around, n_radial, p, True)
+    th_edges = 2.0 * np.pi * np.arange(n_around + 1) / n_around
+    th = np.concatenate([th_edges[c] + 0.5 * (1 + xr[:-1]) * (th_edges[c + 1] - th_edges[c]) for c in range(n_around)])
+    # geometric radial cell edges r_e (distance parameter from the wall), then node layers
+    L = R_out - 0.5
+    lo, hi = 1.0 + 1e-12, 10.0       # growth factor q: dr0 (q^n - 1)/(q - 1) = L, by bisection
+    for _ in range(200):
+        q = 0.5 * (lo + hi)
+        if dr0 * (q ** n_radial - 1.0) / (q - 1.0) > L:
+            hi = q
+        else:
+            lo = q
+    re = L * (q ** np.arange(n_radial + 1) - 1.0) / (q ** n_radial - 1.0)
+    rn = np.concatenate([re[c] + 0.5 * (1 + xr[:-1]) * (re[c + 1] - re[c]) for c in range(n_radial)] + [re[-1:]])
+    A = naca0012_surface(th)
+    # march node layers along smoothed normals out to about one chord (a cell edge) ...
+    ms = int(np.argmin(np.abs(re - 1.0))) * p
+    layers = [A]
+    X = A.copy()
+    for m in range(1, ms + 1):
+        t = np.roll(X, -1, axis=0) - np.roll(X, 1, axis=0)
+        n = np.stack([t[:, 1], -t[:, 0]], axis=1)
+        n /= np.linalg.norm(n, axis=1, keepdims=True)
+        for _ in range(smooth):
+            n = n + 0.5 * (np.roll(n, 1, axis=0) + np.roll(n, -1, axis=0))
+            n /= np.linalg.norm(n, axis=1, keepdims=True)
+        X = X + (rn[m] - rn[m - 1]) * n
+        layers.append(X.copy())
+    # ... then straight out to the circle of radius R_out about mid-chord, each grid line
+    # ending at its own (uniformly spaced) angle parameter, spaced by the same layer
+    # parameter
+    O = np.stack([0.5 + R_out * np.cos(th), R_out * np.sin(th)], axis=-1)
+    for m in range(ms + 1, len(rn)):
+        a = (rn[m] - rn[ms]) / (rn[-1] - rn[ms])
+        layers.append((1.0 - a) * X + a * O)
+    layers = np.array(layers)                                      # [Nr, Na, 2]
+    xyz = layers.reshape(-1, 2)
+    fb = -np.ones((n_around * n_radial, 4), dtype=np.int32)
+    u_inf = Ma * math.sqrt(gamma * T_inf)
+    bcs = [BC(kind=BC_WALL, T_wall=T_inf), BC(kind=BC_INLET, rho=1.0, u=(u_inf, 0.0, 0.0), T=T_inf),
+           BC(kind=BC_OUTLET)]
+    outer = layers[-1]
+    for ca in range(n_around):
+        fb[ca, 2] = 0
+        # inlet on the upstream arc, polar angle about mid-chord beyond +-100 deg: the
+        # junctions with the outlet then sit where the circle's tangent is not a lattice
+        # direction (at +-90 deg it is horizontal, and a horizontal velocity would graze
+        # the boundary right at the junction)
+        fm = outer[(ca * p + p // 2) % Na] - np.array([0.5, 0.0])
+        fb[ca + n_around * (n_radial - 1), 3] = 1 if fm[0] / np.hypot(fm[0], fm[1]) < math.cos(math.radians(100.0)) else 2
+    mesh = CurvMesh(p=p, nodes=nodes, node_xyz=np.ascontiguousarray(xyz), cell_nodes=cells, cell_face_bc=fb, bcs=bcs)
+    mu = 1.0 * u_inf * 1.0 / Re
+    phys = Physics(gamma=gamma, dt=dt, relax_mode=1, mu_ref=mu, T_ref=T_inf, mu_exp=0.0)
+    return mesh, phys
+
+
+def naca_fields(xyz: np.ndarray, Ma: float = 2.0, T_inf: float = 1.0, gamma: float = 1.4):
+    """Free stream plus the vortex-street trigger u_y = 0.1 u_x sin(1.3 y + 0.1) (Sec. 4.1)."""
+    u_inf = Ma * math.sqrt(gamma * T_inf)
+    n = xyz.shape[0]
+    u = np.zeros((n, 2))
+    u[:, 0] = u_inf
+    u[:, 1] = 0.1 * u_inf * np.sin(1.3 * xyz[:, 1] + 0.1)
+    return np.ones(n), u, np.full(n, T_inf)
