@@ -810,10 +810,6 @@ static int64_t curv_locate(const or_curv *m, const double *x, double *xi) {
   return best;
 }
 
-/* A point within this many reference units of a face counts as on it when the exit
- * parameter is refined (a node on the face has +-1 only up to rounding). */
-#define OR_FACE_EPS 1e-13
-
 /* Point and tangent of face f of cell c at face parameter t. */
 static void face_curve(const or_curv *m, int64_t c, int f, double t, double *x, double *dx) {
   int p = m->p, n1 = p + 1;
@@ -880,106 +876,141 @@ static int64_t curv_project(const or_curv *m, const double *y, double *xi) {
   return cb;
 }
 
-/* How far x0 + s v lies beyond face f of cell c, in the reference coordinate normal
- * to that face (<= 0 on the cell's side); 0 if the inverse map does not converge. */
-static int face_excess(const or_curv *m, int64_t c, int f, const double *x0, const double *v, double s,
-                       const double *start, double *g) {
-  double x[2] = {x0[0] + s * v[0], x0[1] + s * v[1]}, r[2];
-  if (!cell_newton(m, c, x, start, r)) return 0;
-  double e = f == 0 ? -r[0] : (f == 1 ? r[0] : (f == 2 ? -r[1] : r[1]));
-  *g = e - 1.0;
-  return 1;
+/* Outward unit normal of face f of cell c at face parameter t: perpendicular to the face
+ * curve, on the other side from the cell's point half a reference unit inward from the
+ * face (the normal component of that offset is positive in any unfolded cell, at a
+ * degenerate corner too). */
+static void face_normal(const or_curv *m, int64_t c, int f, double t, double *n) {
+  double x[2], dx[2], y[2], J[2][2];
+  face_curve(m, c, f, t, x, dx);
+  double xi = f == 0 ? -0.5 : (f == 1 ? 0.5 : t), eta = f == 2 ? -0.5 : (f == 3 ? 0.5 : t);
+  cell_map(m, c, xi, eta, y, J);
+  double len = sqrt(dx[0] * dx[0] + dx[1] * dx[1]);
+  n[0] = dx[1] / len;
+  n[1] = -dx[0] / len;
+  if (n[0] * (y[0] - x[0]) + n[1] * (y[1] - x[1]) > 0.0) {
+    n[0] = -n[0];
+    n[1] = -n[1];
+  }
 }
 
-/* The crossing of x0 + s v with face f of cell c, given the bracket [lo, hi] of the
- * exit from point location: bisection on the face-normal reference coordinate
- * (face_excess <= OR_FACE_EPS on the cell's side), with the lower end stepped back from
- * lo until it lies on the cell's side.  The crossing must lie on the face itself
- * (tangential coordinate within 1e-9 of [-1,1]); -1 if there is none. */
-static double exit_through_face(const or_curv *m, int64_t c, int f, const double *x0, const double *v, double lo,
-                                double hi, const double *start) {
-  double ga = 1.0, gb, a = lo, bnd = hi;
-  for (double back = 1e-9; back < 2.0; back *= 10.0) {
-    a = lo - back > 0.0 ? lo - back : 0.0;
-    if (face_excess(m, c, f, x0, v, a, start, &ga) && ga <= OR_FACE_EPS) break;
-    ga = 1.0;
-    if (a == 0.0) break;
-  }
-  if (ga > OR_FACE_EPS) return -1.0;
-  /* the upper end: hi, or further along the path if hi is still on the cell's side */
-  for (double fwd = 0.0; fwd <= 1.0; fwd = fwd == 0.0 ? 1e-9 : fwd * 10.0) {
-    bnd = hi + fwd < 1.0 ? hi + fwd : 1.0;
-    if (face_excess(m, c, f, x0, v, bnd, start, &gb) && gb > OR_FACE_EPS) break;
-    gb = -1.0;
-    if (bnd == 1.0) break;
-  }
-  if (gb <= OR_FACE_EPS) return -1.0;
+/* For a path x0 + s v tangent to face f of cell c at x0 = face(t0): whether its end x0 + v
+ * lies beyond the face curve (a convex boundary, which the path then leaves) rather than
+ * on it (a straight face, along which it stays).  The end is projected onto the face's
+ * polynomial curve (extended past its ends if need be) by bisection on the derivative
+ * of the squared distance, near t0; beyond = on the outward side by more than rounding. */
+static int beyond_face(const or_curv *m, int64_t c, int f, double t0, const double *x0, const double *v,
+                       double scale) {
+  double y[2] = {x0[0] + v[0], x0[1] + v[1]}, x[2], dx[2];
+  double lo = t0 - 0.5, hi = t0 + 0.5;
+  face_curve(m, c, f, lo, x, dx);
+  double hlo = (x[0] - y[0]) * dx[0] + (x[1] - y[1]) * dx[1];
   for (int it = 0; it < 100; it++) {
-    double mid = 0.5 * (a + bnd), g;
-    if (!face_excess(m, c, f, x0, v, mid, start, &g)) return -1.0;
-    if (g <= OR_FACE_EPS) a = mid; else bnd = mid;
+    double mid = 0.5 * (lo + hi);
+    face_curve(m, c, f, mid, x, dx);
+    double h = (x[0] - y[0]) * dx[0] + (x[1] - y[1]) * dx[1];
+    if ((h > 0.0) == (hlo > 0.0)) { lo = mid; hlo = h; } else hi = mid;
   }
-  /* tangential reference coordinate of the crossing */
-  double x[2] = {x0[0] + a * v[0], x0[1] + a * v[1]}, r[2];
-  if (!cell_newton(m, c, x, start, r)) return -1.0;
-  double tt = (f == 0 || f == 1) ? r[1] : r[0];
-  if (fabs(tt) > 1.0 + 1e-9) return -1.0;
-  return a;
+  double t = 0.5 * (lo + hi), n[2];
+  face_curve(m, c, f, t, x, dx);
+  face_normal(m, c, f, t, n);
+  return n[0] * (y[0] - x[0]) + n[1] * (y[1] - x[1]) > 1e-12 * scale;
 }
 
-/* Where x0 + s v (x0 inside, s in [0,1]) first leaves the mesh, and through which
- * boundary tag.  Bisection on point location brackets the exit as lo; every tagged
- * face passing within 1e-6 (reference units) of x0 + lo v is a candidate, and on each
- * the crossing is refined without tolerance (face_excess).  The smallest crossing wins;
- * crossings within 1e-10 of it are the same point (a junction of boundary segments),
- * where the smallest tag wins. */
+/* Where x0 + s v (x0 inside the mesh or on its boundary, s in [0,1]) first meets the
+ * boundary, and that boundary's tag; *bc = -1 if it never does.  Every tagged face is
+ * intersected with the line: h(t) = (face(t) - x0) x v is sampled at 65 even parameters
+ * and at the face's support points, every sign change is bisected in t, and a root gives
+ * s = (face(t) - x0).v / |v|^2.  A root at x0 itself (x0 a boundary node) counts only if
+ * the path leaves the mesh there: v . n_out > 0, or a tangent path whose end lies beyond
+ * the face curve (beyond_face).  Crossing points closer than 1e-9 max(1, |x0|) are one point (a
+ * junction of boundary segments): the smaller tag wins. */
 static double curv_exit(const or_curv *m, const double *x0, const double *v, int *bc) {
-  double lo = 0.0, hi = 1.0;
-  for (int it = 0; it < 80; it++) {
-    double mid = 0.5 * (lo + hi), x[2] = {x0[0] + mid * v[0], x0[1] + mid * v[1]}, xi[2];
-    if (curv_locate(m, x, xi) >= 0) lo = mid; else hi = mid;
-  }
-  double x[2] = {x0[0] + lo * v[0], x0[1] + lo * v[1]};
-  *bc = -1;
-  int bi = (int)((x[0] - m->bx0) / m->bh), bj = (int)((x[1] - m->by0) / m->bh);
-  if (bi < 0 || bj < 0 || bi >= m->bnx || bj >= m->bny) return lo;
-  int64_t b = (int64_t)bj * m->bnx + bi;
-  int n1 = m->p + 1;
+  int p = m->p, n1 = p + 1;
+  double vv = v[0] * v[0] + v[1] * v[1], vlen = sqrt(vv);
+  double scale = fmax(1.0, fmax(fabs(x0[0]), fabs(x0[1])));
+  double tie = 1e-9 * scale / fmax(fabs(v[0]), fabs(v[1]));
+  double sx0 = fmin(x0[0], x0[0] + v[0]), sx1 = fmax(x0[0], x0[0] + v[0]);
+  double sy0 = fmin(x0[1], x0[1] + v[1]), sy1 = fmax(x0[1], x0[1] + v[1]);
   double sbest = 1e300;
-  for (int64_t q = m->bstart[b]; q < m->bstart[b + 1]; q++) {
-    int64_t c = m->bcells[q];
-    /* unclamped reference coordinates of x in c, from the nearest support point or a
-     * 3x3 grid of starts */
-    const int64_t *cn = m->cell_nodes + c * n1 * n1;
-    double best = 1e300, r0[2] = {0, 0}, r[2];
-    for (int jy = 0; jy <= m->p; jy++)
-      for (int jx = 0; jx <= m->p; jx++) {
-        const double *X = m->xyz + 2 * cn[jx + n1 * jy];
-        double d = (X[0] - x[0]) * (X[0] - x[0]) + (X[1] - x[1]) * (X[1] - x[1]);
-        if (d < best) { best = d; r0[0] = m->xref[jx]; r0[1] = m->xref[jy]; }
-      }
-    int ok = cell_newton(m, c, x, r0, r) && fabs(r[0]) <= 1.0 + 1e-6 && fabs(r[1]) <= 1.0 + 1e-6;
-    for (int t = 0; !ok && t < 9; t++) {
-      double s0[2] = {-0.6 + 0.6 * (t % 3), -0.6 + 0.6 * (t / 3)};
-      ok = cell_newton(m, c, x, s0, r) && fabs(r[0]) <= 1.0 + 1e-6 && fabs(r[1]) <= 1.0 + 1e-6;
+  *bc = -1;
+  double ts[65 + OR_MAXP + 1];
+  int nt = 0;
+  for (int j = 0; j <= 64; j++) ts[nt++] = -1.0 + j / 32.0;
+  for (int j = 1; j < p; j++) ts[nt++] = m->xref[j];
+  for (int a = 1; a < nt; a++)             /* insertion sort: the samples in order */
+    for (int b = a; b > 0 && ts[b] < ts[b - 1]; b--) {
+      double tmp = ts[b];
+      ts[b] = ts[b - 1];
+      ts[b - 1] = tmp;
     }
-    if (!ok) continue;
+  for (int64_t c = 0; c < m->n_cells; c++)
     for (int f = 0; f < 4; f++) {
       int tag = m->face_bc[c * 4 + f];
-      double dn = f == 0 ? fabs(r[0] + 1.0) : (f == 1 ? fabs(r[0] - 1.0) : (f == 2 ? fabs(r[1] + 1.0) : fabs(r[1] - 1.0)));
-      if (tag < 0 || dn > 1e-6) continue;
-      double s_f = exit_through_face(m, c, f, x0, v, lo, hi, r);
-      if (s_f < 0.0) continue;
-      if (s_f < sbest - 1e-10) {
-        sbest = s_f;
-        *bc = tag;
-      } else if (s_f <= sbest + 1e-10) {
-        if (s_f < sbest) sbest = s_f;
-        if (tag < *bc) *bc = tag;
+      if (tag < 0) continue;
+      /* the face's box (its support points, widened by 10% for the curve) against the
+       * segment's */
+      double fx0 = 1e300, fx1 = -1e300, fy0 = 1e300, fy1 = -1e300;
+      for (int j = 0; j <= p; j++) {
+        int jx = f == 0 ? 0 : (f == 1 ? p : j), jy = f == 2 ? 0 : (f == 3 ? p : j);
+        const double *X = m->xyz + 2 * m->cell_nodes[c * n1 * n1 + jx + n1 * jy];
+        fx0 = fmin(fx0, X[0]);
+        fx1 = fmax(fx1, X[0]);
+        fy0 = fmin(fy0, X[1]);
+        fy1 = fmax(fy1, X[1]);
+      }
+      double w = 0.1 * fmax(fx1 - fx0, fy1 - fy0) + 1e-12;
+      if (sx1 < fx0 - w || sx0 > fx1 + w || sy1 < fy0 - w || sy0 > fy1 + w) continue;
+      double hprev = 0.0, tprev = -1.0;
+      for (int j = 0; j < nt; j++) {
+        double x[2], dx[2];
+        face_curve(m, c, f, ts[j], x, dx);
+        double h = (x[0] - x0[0]) * v[1] - (x[1] - x0[1]) * v[0];
+        double troot;
+        int have = 0;
+        if (h == 0.0) {
+          troot = ts[j];
+          have = 1;
+        } else if (j > 0 && hprev != 0.0 && (h > 0.0) != (hprev > 0.0)) {
+          double lo = tprev, hi = ts[j], hlo = hprev;
+          for (int it = 0; it < 100; it++) {
+            double mid = 0.5 * (lo + hi), xm[2], dm[2];
+            face_curve(m, c, f, mid, xm, dm);
+            double hm = (xm[0] - x0[0]) * v[1] - (xm[1] - x0[1]) * v[0];
+            if (hm == 0.0) { lo = hi = mid; break; }
+            if ((hm > 0.0) == (hlo > 0.0)) { lo = mid; hlo = hm; } else hi = mid;
+          }
+          troot = 0.5 * (lo + hi);
+          have = 1;
+        }
+        hprev = h;
+        tprev = ts[j];
+        if (!have) continue;
+        double xr[2], dr[2];
+        face_curve(m, c, f, troot, xr, dr);
+        double sr = ((xr[0] - x0[0]) * v[0] + (xr[1] - x0[1]) * v[1]) / vv;
+        if (sr < -1e-9 || sr > 1.0 + 1e-9) continue;
+        double dist = fabs(xr[0] - x0[0]) + fabs(xr[1] - x0[1]);
+        if (dist <= 1e-12 * scale) {
+          /* the root is x0: only a path that leaves the mesh here counts */
+          double n[2];
+          face_normal(m, c, f, troot, n);
+          double nv = n[0] * v[0] + n[1] * v[1];
+          if (nv < -1e-12 * vlen) continue;
+          if (nv <= 1e-12 * vlen && !beyond_face(m, c, f, troot, x0, v, scale)) continue;
+          sr = 0.0;
+        }
+        if (sr < 0.0) sr = 0.0;
+        if (sr < sbest - tie) {
+          sbest = sr;
+          *bc = tag;
+        } else if (sr <= sbest + tie) {
+          if (sr < sbest) sbest = sr;
+          if (tag < *bc) *bc = tag;
+        }
       }
     }
-  }
-  return *bc < 0 ? lo : sbest;
+  return *bc < 0 ? 0.0 : sbest;
 }
 
 /* Departure-point geometry of the Q (velocity, node k) pairs, row i stored at index

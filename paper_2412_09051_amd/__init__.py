@@ -16,6 +16,10 @@ from dataclasses import dataclass, field
 from typing import Optional, Sequence
 
 import numpy as np
+# torch first: its bundled HIP runtime is then the one libsllbm.so binds to.  Loaded the
+# other way round, the process would hold two HIP runtimes, and whichever initialises
+# first keeps the GPU (the other reports no device).
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsllbm.so")
@@ -28,7 +32,7 @@ SLLBM_MESH_TENSOR, SLLBM_MESH_CURVILINEAR = 0, 1
 SLLBM_F64, SLLBM_F32 = 0, 1
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2412_09051_amd.build` "
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2412_09051_amd/build.py` "
                       "(there is no CPU fallback)")
 _lib = ctypes.CDLL(LIB_PATH)
 

@@ -198,6 +198,38 @@ struct Geo {
     }
   }
 
+  // unit normal of face f of cell c at face parameter t (point x, tangent tc), pointing
+  // out of the cell: away from the point half a reference unit inward of the face
+  void outward_normal(int64_t c, int f, double t, const double *tc, const double *x, double *n) const {
+    double y[2], J[2][2];
+    cell_map(c, f == 0 ? -0.5 : (f == 1 ? 0.5 : t), f == 2 ? -0.5 : (f == 3 ? 0.5 : t), y, J);
+    double len = std::hypot(tc[0], tc[1]);
+    n[0] = tc[1] / len;
+    n[1] = -tc[0] / len;
+    if (n[0] * (y[0] - x[0]) + n[1] * (y[1] - x[1]) > 0.0) {
+      n[0] = -n[0];
+      n[1] = -n[1];
+    }
+  }
+
+  // a path x0 + s v tangent to face f of cell c at x0 = face(t0) leaves the mesh there
+  // only if the face curves away from it (a convex boundary): its end x0 + v, projected
+  // onto the face curve by Newton (extended past the face's ends if need be), lies on the
+  // outward side by more than rounding.  Along a straight face the path stays on it.
+  bool tangent_end_beyond(int64_t c, int f, double t0, const double *x0, const double *v, double xscale) const {
+    double y[2] = {x0[0] + v[0], x0[1] + v[1]}, x[2], dx[2];
+    double t = t0;
+    for (int it = 0; it < 8; it++) {
+      face_point(c, f, t, x, dx);
+      double g = (x[0] - y[0]) * dx[0] + (x[1] - y[1]) * dx[1];
+      t -= g / (dx[0] * dx[0] + dx[1] * dx[1]);   // Gauss-Newton on |face(t) - y|^2
+    }
+    face_point(c, f, t, x, dx);
+    double n[2];
+    outward_normal(c, f, t, dx, x, n);
+    return n[0] * (y[0] - x[0]) + n[1] * (y[1] - x[1]) > 1e-12 * xscale;
+  }
+
   // first boundary face crossed by x0 + s v, s in [0, 1]: returns s and the bc index
   bool first_crossing(const double *x0, const double *v, double *s_out, int *bc_out) const {
     double xs0 = std::min(x0[0], x0[0] + v[0]), xs1 = std::max(x0[0], x0[0] + v[0]);
@@ -211,6 +243,8 @@ struct Geo {
     j1 = std::min(bny - 1, j1 + 1);
     double best = std::numeric_limits<double>::infinity();
     double scale = std::fabs(x0[0]) + std::fabs(x0[1]) + std::fabs(v[0]) + std::fabs(v[1]);
+    double xscale = std::max(1.0, std::max(std::fabs(x0[0]), std::fabs(x0[1])));
+    double tie = 1e-9 * xscale / std::max(std::fabs(v[0]), std::fabs(v[1]));
     int bbc = -1;
     for (int bj = j0; bj <= j1; bj++)
       for (int bi = i0; bi <= i1; bi++) {
@@ -246,13 +280,26 @@ struct Geo {
             if (!ok) continue;
             if (std::fabs(t) <= 1.0 + 1e-9 && s >= -1e-9 && s <= 1.0 + 1e-9) {
               int tag = m.cell_face_bc[c * 4 + f];
+              double xc[2], tc[2];
+              face_point(c, f, t, xc, tc);
+              if (std::fabs(xc[0] - x0[0]) + std::fabs(xc[1] - x0[1]) <= 1e-12 * xscale) {
+                // the crossing is x0 itself (a boundary node): it counts only if the
+                // path leaves the mesh there, tangent paths included
+                double n[2];
+                outward_normal(c, f, t, tc, xc, n);
+                double nv = n[0] * v[0] + n[1] * v[1], vl = std::hypot(v[0], v[1]);
+                if (nv < -1e-12 * vl) continue;
+                if (nv <= 1e-12 * vl && !tangent_end_beyond(c, f, t, x0, v, xscale)) continue;
+                s = 0.0;
+              }
               s = std::max(0.0, s);
-              // where two boundary segments meet, the path crosses both at once: the
-              // segment with the smaller tag decides
-              if (s < best - 1e-10) {
+              // where two boundary segments meet, the path crosses both at once
+              // (crossing points closer than 1e-9 max(1, |x0|)): the segment with the
+              // smaller tag decides
+              if (s < best - tie) {
                 best = s;
                 bbc = tag;
-              } else if (s <= best + 1e-10) {
+              } else if (s <= best + tie) {
                 best = std::min(best, s);
                 bbc = std::min(bbc, tag);
               }
