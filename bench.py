@@ -1,13 +1,17 @@
 #!/usr/bin/env python3
 """Throughput of the SLLBM hot path on one MI355X.
 
-Workload (one "step" = one fused stream + collide pass over the whole mesh): the 3D
-periodic compressible Taylor-Green vortex at Ma 0.8, Re 400 on 32^3 cells of order
-p = 3 with GLL support points (96^3 = 884,736 nodes) and the D3V125 Gauss-Hermite
-velocity set; FP64 populations (headline) and FP32 storage side by side.
+Workload (one "step" = one stream + collide pass over the whole mesh): the 3D periodic
+compressible Taylor-Green vortex at Ma 0.8, Re 400 on 32^3 cells of order p = 3 with GLL
+support points (96^3 = 884,736 nodes) and the D3V125 Gauss-Hermite velocity set; FP64
+populations (headline) and FP32 storage side by side.  A second workload, the
+supersonic NACA 0012 O-grid at Ma 1.5 (256 x 128 cells, p = 4, 525,312 nodes, D2V25,
+curvilinear CSR plan), is reported in the "ogrid" object.
 
 Prints ONE JSON line.  value = GQUPS = nodes * Q * steps / s (one update = one
 (node, velocity) pair with both f and g).  Inputs are resident in HBM before timing.
+Per-kernel times come from HIP events the library records around each of its launches
+on the timing stream (sllbm_plan_profile).
 """
 import argparse
 import json
@@ -20,7 +24,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-BYTES_PER_UPDATE = {"f64": 32, "f32": 16}   # read + write of f_i and g_i
+# algorithmic bytes per update: read + write of f_i and g_i; the curvilinear plan adds
+# its (p+1)^2 weights and a cell id per row (f and g share the row)
+BYTES_PER_UPDATE = {"f64": 32, "f32": 16}
+
+
+def curv_bytes_per_update(prec, p):
+    return BYTES_PER_UPDATE[prec] + (p + 1) ** 2 * (8 if prec == "f64" else 4) + 4
 
 
 def parse():
@@ -31,21 +41,22 @@ def parse():
     ap.add_argument("--ncell", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-ogrid", action="store_true", help="skip the curvilinear O-grid workload")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--kernel", choices=["auto", "gather", "tiled"], default="auto")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (reference for byte counters)")
     return ap.parse_args()
 
 
 def traffic_from_profiles(prec):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel build (else None)."""
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
-        import paper_2412_09051_amd as S
-        stamp = os.path.getmtime(S.LIB_PATH)
         e = d.get(prec)
         if not e or e.get("kernel_source_hash") != kernel_source_hash():
             return None
@@ -64,7 +75,27 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-KERNEL_NAMES = {0: "k_step_gather", 2: "k_step_tile"}
+def timed_steps(S, plan, prm, a, b, steps, warmup, torch):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        S.sllbm_step(plan, prm, a, b, stream)
+        a, b = b, a
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    S.sllbm_plan_profile(plan, True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t0.record(stream)
+    for _ in range(steps):
+        S.sllbm_step(plan, prm, a, b, stream)
+        a, b = b, a
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    prof = S.sllbm_plan_profile_read(plan)
+    S.sllbm_plan_profile(plan, False)
+    return a, t0.elapsed_time(t1), wall, prof
 
 
 def gpu_leg(prec, steps, warmup, ncell, kernel="auto"):
@@ -78,7 +109,6 @@ def gpu_leg(prec, steps, warmup, ncell, kernel="auto"):
     plan = S.sllbm_interp_plan(m, vs, phys.dt, S.SLLBM_F32 if prec == "f32" else S.SLLBM_F64)
     if kernel != "auto":
         S.sllbm_plan_select_kernel(plan, {"gather": 1, "tiled": 2}[kernel])
-    kname = KERNEL_NAMES[S.sllbm_plan_info(plan)["kernel"]]
     prm = S.Params.from_physics(phys)
     N, Q = plan.N, plan.Q
     xyz = S.sllbm_mesh_nodes(m)
@@ -89,46 +119,74 @@ def gpu_leg(prec, steps, warmup, ncell, kernel="auto"):
     b = torch.empty_like(a)
     S.sllbm_init_equilibrium(plan, prm, torch.tensor(rho, device=dev), torch.tensor(np.ascontiguousarray(u.T), device=dev),
                              torch.tensor(T, device=dev), a)
-    stream = torch.cuda.current_stream()
-    for _ in range(warmup):
-        S.sllbm_step(plan, prm, a, b, stream)
-        a, b = b, a
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    t_all0 = torch.cuda.Event(enable_timing=True)
-    t_all1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    t_all0.record(stream)
-    for k in range(steps):
-        ev[k][0].record(stream)
-        S.sllbm_step(plan, prm, a, b, stream)      # one kernel launch per step on `stream`
-        ev[k][1].record(stream)
-        a, b = b, a
-    t_all1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    total_ms = t_all0.elapsed_time(t_all1)
-    per_launch = [s.elapsed_time(e) for s, e in ev]
-    avg_launch_ms = sum(per_launch) / len(per_launch)
+    a, total_ms, wall, prof = timed_steps(S, plan, prm, a, b, steps, warmup, torch)
     tot = S.sllbm_moments(plan, prm, a, totals=True)
     torch.cuda.synchronize()
-    ok = all(math.isfinite(x) for x in tot)
     updates = N * Q
-    gqups = updates * steps / (total_ms * 1e-3) / 1e9
-    alg_bytes = updates * BYTES_PER_UPDATE[prec]
-    achieved = alg_bytes / (avg_launch_ms * 1e-3) / 1e9
-    return {
-        "N": N, "Q": Q, "ms_per_step": total_ms / steps, "wall_s": wall, "gqups": gqups,
-        "avg_launch_ms": avg_launch_ms, "achieved_GBs": achieved, "alg_bytes_per_launch": alg_bytes,
-        "finite": ok, "mass": float(tot[0]), "kernel": kname,
+    return summarize(prof, total_ms, wall, steps, updates, BYTES_PER_UPDATE[prec],
+                     finite=all(math.isfinite(x) for x in tot), N=N, Q=Q, mass=float(tot[0]))
+
+
+def summarize(prof, total_ms, wall, steps, updates, bytes_per_update, **extra):
+    dom = max(prof.items(), key=lambda kv: kv[1][0])
+    name, (kms, launches) = dom
+    avg_ms = kms / max(launches, 1)
+    alg = updates * bytes_per_update
+    out = {
+        "ms_per_step": total_ms / steps, "wall_s": wall,
+        "gqups": updates * steps / (total_ms * 1e-3) / 1e9,
+        "kernels": {k: {"avg_ms": round(v[0] / max(v[1], 1), 4), "launches": v[1]} for k, v in prof.items()},
+        "dominant": name, "avg_launch_ms": avg_ms, "alg_bytes_per_launch": alg,
+        "achieved_GBs": alg / (avg_ms * 1e-3) / 1e9,
+        "step_GBs": alg * steps / (total_ms * 1e-3) / 1e9,
     }
+    out.update(extra)
+    return out
+
+
+def ogrid_leg(prec, steps, warmup):
+    import torch
+    import paper_2412_09051_amd as S
+    import workloads as W
+    mesh, phys = W.naca_ogrid()
+    m = S.sllbm_mesh_build(mesh)
+    vs = S.sllbm_velset_gauss_hermite(2, 5, phys.T0)
+    t0 = time.perf_counter()
+    plan = S.sllbm_interp_plan(m, vs, phys.dt, S.SLLBM_F32 if prec == "f32" else S.SLLBM_F64)
+    plan_s = time.perf_counter() - t0
+    prm = S.Params.from_physics(phys)
+    N, Q = plan.N, plan.Q
+    rho, u, T = W.naca_fields(S.sllbm_mesh_nodes(m))
+    dev = torch.device("cuda")
+    dt = torch.float32 if prec == "f32" else torch.float64
+    a = torch.empty(2 * Q * N, dtype=dt, device=dev)
+    b = torch.empty_like(a)
+    S.sllbm_init_equilibrium(plan, prm, torch.tensor(rho, device=dev), torch.tensor(u.T.copy(), device=dev),
+                             torch.tensor(T, device=dev), a)
+    a, total_ms, wall, prof = timed_steps(S, plan, prm, a, b, steps, warmup, torch)
+    tot = S.sllbm_moments(plan, prm, a, totals=True)
+    torch.cuda.synchronize()
+    return summarize(prof, total_ms, wall, steps, N * Q, curv_bytes_per_update(prec, mesh.p),
+                     finite=all(math.isfinite(x) for x in tot), N=N, Q=Q, plan_build_s=plan_s,
+                     bpu=curv_bytes_per_update(prec, mesh.p))
+
+
+def copy_calibration():
+    """A plain device copy of 1 GiB, three times: the reference for the FETCH_SIZE and
+    WRITE_SIZE counters of the profiled runs."""
+    import torch
+    n = 1 << 27                       # 2^27 doubles = 1 GiB
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"bytes_read": 8 * n, "bytes_written": 8 * n, "launches": 3}
 
 
 def cpu_leg(ncell, steps):
     """The oracle, as it stands, on the host cores: one (or more) full step(s) of the
     same workload in FP64."""
-    import numpy as np
     import oracle
     import workloads as W
     mesh, phys = W.tgv_case(ncell=ncell)
@@ -144,6 +202,14 @@ def cpu_leg(ncell, steps):
             "sample": f"{steps} full step(s) of the {o.N}-node mesh, FP64, {el:.1f} s"}
 
 
+def roofline(r, traffic=None):
+    return {"bound": "hbm", "achieved": round(r["achieved_GBs"], 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(r["achieved_GBs"] / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "kernel": r["dominant"], "avg_launch_ms": round(r["avg_launch_ms"], 4),
+            "alg_bytes_per_launch": r["alg_bytes_per_launch"],
+            "step_achieved": round(r["step_GBs"], 2), "step_frac": round(r["step_GBs"] / PEAK_HBM_GBS, 4)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -151,9 +217,15 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     r64 = gpu_leg("f64", args.steps, args.warmup, args.ncell, args.kernel)
+    print(f"# tgv f64 done: {r64['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
     r32 = None if args.no_fp32 else gpu_leg("f32", args.steps, args.warmup, args.ncell, args.kernel)
+    og = {}
+    if not args.no_ogrid:
+        for prec in ("f32", "f64"):
+            og[prec] = ogrid_leg(prec, args.steps, args.warmup)
+            print(f"# ogrid {prec} done: {og[prec]['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
+    cal = copy_calibration() if args.copy_calibration else None
     cpu = None if args.no_cpu else cpu_leg(args.ncell, args.cpu_steps)
-    traffic = traffic_from_profiles("f64")
     out = {
         "metric": "GQUPS (node x velocity updates/s, f and g together)",
         "value": round(r64["gqups"], 4),
@@ -170,20 +242,22 @@ def main():
         "config": {"workload": f"3D periodic compressible Taylor-Green vortex Ma 0.8 Re 400, "
                                f"{args.ncell}^3 cells p=3 GLL ({r64['N']} nodes), D3V125 Gauss-Hermite, FP64",
                    "nodes": r64["N"], "Q": r64["Q"], "order_p": 3, "velocity_set": "D3V125"},
-        "roofline": {"bound": "hbm", "achieved": round(r64["achieved_GBs"], 2), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(r64["achieved_GBs"] / PEAK_HBM_GBS, 4),
-                     "traffic": traffic, "kernel": r64["kernel"] + "<double,3,3>",
-                     "alg_bytes_per_launch": r64["alg_bytes_per_launch"],
-                     "avg_launch_ms": round(r64["avg_launch_ms"], 4)},
+        "roofline": roofline(r64, traffic_from_profiles("f64")),
         "cpu_baseline": cpu,
-        "hbm_pct_algorithmic": round(100.0 * r64["gqups"] * 32 / PEAK_HBM_GBS, 2),
+        "kernels": r64["kernels"],
     }
     if r32:
         out["fp32"] = {"value": round(r32["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(r32["ms_per_step"], 4),
-                       "roofline": {"bound": "hbm", "achieved": round(r32["achieved_GBs"], 2), "peak": PEAK_HBM_GBS,
-                                    "unit": "GB/s", "frac": round(r32["achieved_GBs"] / PEAK_HBM_GBS, 4),
-                                    "kernel": r32["kernel"] + "<float,3,3>",
-                                    "avg_launch_ms": round(r32["avg_launch_ms"], 4)}}
+                       "roofline": roofline(r32, traffic_from_profiles("f32")), "kernels": r32["kernels"]}
+    if og:
+        out["ogrid"] = {
+            "workload": "supersonic NACA 0012 O-grid Ma 1.5 Re 1e4, 256x128 cells p=4 GLL (525312 nodes), D2V25, "
+                        "curvilinear CSR plan",
+            **{prec: {"value": round(v["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(v["ms_per_step"], 4),
+                      "bytes_per_update": v["bpu"], "plan_build_s": round(v["plan_build_s"], 2),
+                      "roofline": roofline(v), "finite": v["finite"]} for prec, v in og.items()}}
+    if cal:
+        out["copy_calibration"] = cal
     print(json.dumps(out), flush=True)
 
 

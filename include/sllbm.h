@@ -152,6 +152,17 @@ int sllbm_plan_info(sllbm_plan p, sllbm_plan_info_t *info);
  * departure stencil leaves the one-cell halo the tile stages, e.g. CFL > 1).  Both
  * compute the same step; the choice exists for testing and measurement. */
 int sllbm_plan_select_kernel(sllbm_plan p, int kernel);
+/* Per-kernel timing of a plan's launches (for measurement, not part of the method).
+ * enable = 1 clears the counters and starts recording a HIP event pair around every
+ * launch this plan makes, on the stream the launch uses; enable = 0 stops.  Recording
+ * adds two event records per launch and no synchronisation (events are waited for only
+ * when read, or every 8192 launches).  Returns SLLBM_EHIP for a plan without a device. */
+int sllbm_plan_profile(sllbm_plan p, int enable);
+/* Times since the last enable: waits for the recorded events, then writes up to `max`
+ * entries (kernel name, NUL-terminated in 32 chars; total milliseconds; launch count)
+ * into caller-owned host arrays.  Returns the number of distinct kernels (which may
+ * exceed max), or a negative error code. */
+int sllbm_plan_profile_read(sllbm_plan p, int max, char (*names)[32], double *total_ms, int64_t *launches);
 void sllbm_plan_destroy(sllbm_plan p);
 
 /* Physical parameters of a step. */

@@ -22,7 +22,8 @@ import numpy as np
 import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsllbm.so")
+# SLLBM_LIB names another build of the library (e.g. a variant for an A/B timing)
+LIB_PATH = os.environ.get("SLLBM_LIB") or os.path.join(HERE, "libsllbm.so")
 
 SLLBM_OK, SLLBM_EINVAL, SLLBM_ENOMEM, SLLBM_EGEOM, SLLBM_EHIP, SLLBM_EUNSUPPORTED, SLLBM_EUNSTABLE = \
     0, -1, -2, -3, -4, -5, -6
@@ -83,7 +84,7 @@ class sllbm_params(ctypes.Structure):
 _lib.sllbm_last_error.restype = ctypes.c_char_p
 for _name in ("sllbm_mesh_build", "sllbm_mesh_nodes", "sllbm_mesh_volumes", "sllbm_velset_gauss_hermite",
               "sllbm_interp_plan", "sllbm_plan_info", "sllbm_plan_select_kernel", "sllbm_init_equilibrium",
-              "sllbm_step", "sllbm_moments"):
+              "sllbm_step", "sllbm_moments", "sllbm_plan_profile", "sllbm_plan_profile_read"):
     getattr(_lib, _name).restype = ctypes.c_int
 _lib.sllbm_mesh_destroy.restype = None
 _lib.sllbm_plan_destroy.restype = None
@@ -104,12 +105,16 @@ class Mesh:
     """Owner of an sllbm_mesh handle."""
 
     def __init__(self, handle, dim):
+        self._lib = _lib
         self.handle = handle
         self.dim = dim
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            _lib.sllbm_mesh_destroy(self.handle)
+        # the instance keeps the library alive: module globals may already be gone
+        # when the interpreter shuts down
+        lib = getattr(self, "_lib", None)
+        if getattr(self, "handle", None) and lib is not None:
+            lib.sllbm_mesh_destroy(self.handle)
             self.handle = None
 
 
@@ -117,6 +122,7 @@ class Plan:
     """Owner of an sllbm_plan handle (keeps its mesh alive)."""
 
     def __init__(self, handle, mesh, velset, dt, prec):
+        self._lib = _lib
         self.handle = handle
         self.mesh = mesh
         self.velset = velset
@@ -128,8 +134,9 @@ class Plan:
         self.dim = info["dim"]
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            _lib.sllbm_plan_destroy(self.handle)
+        lib = getattr(self, "_lib", None)
+        if getattr(self, "handle", None) and lib is not None:
+            lib.sllbm_plan_destroy(self.handle)
             self.handle = None
 
 
@@ -255,6 +262,23 @@ def sllbm_interp_plan(m: Mesh, velset: dict, dt: float, prec: int = SLLBM_F64) -
 def sllbm_plan_select_kernel(plan: Plan, kernel: int) -> None:
     """0 automatic, 1 per-node gather kernel, 2 LDS-tiled kernel."""
     _check(_lib.sllbm_plan_select_kernel(plan.handle, ctypes.c_int(kernel)), "sllbm_plan_select_kernel")
+
+
+def sllbm_plan_profile(plan: Plan, enable: bool) -> None:
+    """Start (clearing the counters) or stop per-kernel event timing of this plan."""
+    _check(_lib.sllbm_plan_profile(plan.handle, ctypes.c_int(1 if enable else 0)), "sllbm_plan_profile")
+
+
+def sllbm_plan_profile_read(plan: Plan) -> dict:
+    """{kernel name: (total milliseconds, launches)} since profiling was enabled."""
+    cap = 32
+    names = (ctypes.c_char * 32 * cap)()
+    ms = (ctypes.c_double * cap)()
+    cnt = (ctypes.c_int64 * cap)()
+    n = _lib.sllbm_plan_profile_read(plan.handle, ctypes.c_int(cap), names, ms, cnt)
+    if n < 0:
+        raise SllbmError(n, "sllbm_plan_profile_read")
+    return {bytes(names[k]).split(b"\0", 1)[0].decode(): (ms[k], cnt[k]) for k in range(min(n, cap))}
 
 
 def sllbm_plan_info(plan: Plan) -> dict:

@@ -152,6 +152,7 @@ namespace {
 template <typename T, int P>
 void launch_csr_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
   dim3 grid((unsigned)((Pl->cp.N + kBlock - 1) / kBlock));
+  ProfScope ps(Pl, "k_step_csr", s);
   if (Pl->cp.Q == 25)
     hipLaunchKernelGGL((k_step_csr<T, P, 25>), grid, dim3(kBlock), 0, s, Pl->cp, a, (const T *)pin, (T *)pout);
   else

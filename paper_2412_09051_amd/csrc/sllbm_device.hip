@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <limits>
 #include <new>
@@ -281,10 +282,101 @@ extern "C" int sllbm_plan_select_kernel(sllbm_plan P, int kernel) {
   return SLLBM_OK;
 }
 
+// ------------------------------------------------------------------ per-kernel timing
+
+namespace sllbm {
+namespace {
+hipEvent_t prof_event(Profiler &pr) {
+  if (!pr.pool.empty()) {
+    hipEvent_t e = pr.pool.back();
+    pr.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// wait for the recorded launches, add their times, recycle the events
+void prof_flush(Profiler &pr) {
+  for (const auto &r : pr.pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      pr.total_ms[r.id] += ms;
+      pr.launches[r.id] += 1;
+    }
+    pr.pool.push_back(r.a);
+    pr.pool.push_back(r.b);
+  }
+  pr.pending.clear();
+}
+}  // namespace
+
+void prof_begin(sllbm_plan_s *P, const char *name, hipStream_t s, int *id, hipEvent_t *a) {
+  *id = -1;
+  *a = nullptr;
+  Profiler &pr = P->prof;
+  if (!pr.on) return;
+  int k = 0;
+  while (k < (int)pr.names.size() && pr.names[k] != name) k++;
+  if (k == (int)pr.names.size()) {
+    pr.names.push_back(name);
+    pr.total_ms.push_back(0.0);
+    pr.launches.push_back(0);
+  }
+  hipEvent_t e = prof_event(pr);
+  if (!e || hipEventRecord(e, s) != hipSuccess) return;
+  *id = k;
+  *a = e;
+}
+
+void prof_end(sllbm_plan_s *P, int id, hipEvent_t a, hipStream_t s) {
+  if (id < 0) return;
+  Profiler &pr = P->prof;
+  hipEvent_t b = prof_event(pr);
+  if (!b || hipEventRecord(b, s) != hipSuccess) return;
+  pr.pending.push_back({id, a, b});
+  if (pr.pending.size() > 8192) prof_flush(pr);
+}
+}  // namespace sllbm
+
+extern "C" int sllbm_plan_profile(sllbm_plan P, int enable) {
+  if (!P) return fail(SLLBM_EINVAL, "plan_profile: plan is NULL");
+  if (!P->has_device) return fail(SLLBM_EHIP, "plan_profile: the plan has no device");
+  HIP_TRY(hipSetDevice(P->device));
+  prof_flush(P->prof);
+  if (enable) {
+    P->prof.names.clear();
+    P->prof.total_ms.clear();
+    P->prof.launches.clear();
+  }
+  P->prof.on = enable != 0;
+  return SLLBM_OK;
+}
+
+extern "C" int sllbm_plan_profile_read(sllbm_plan P, int max, char (*names)[32], double *total_ms, int64_t *launches) {
+  if (!P) return fail(SLLBM_EINVAL, "plan_profile_read: plan is NULL");
+  if (max < 0 || (max > 0 && (!names || !total_ms || !launches)))
+    return fail(SLLBM_EINVAL, "plan_profile_read: NULL output with max > 0");
+  if (P->has_device) {
+    HIP_TRY(hipSetDevice(P->device));
+    prof_flush(P->prof);
+  }
+  int n = (int)P->prof.names.size();
+  for (int k = 0; k < n && k < max; k++) {
+    std::snprintf(names[k], 32, "%s", P->prof.names[k].c_str());
+    total_ms[k] = P->prof.total_ms[k];
+    launches[k] = P->prof.launches[k];
+  }
+  return n;
+}
+
 extern "C" void sllbm_plan_destroy(sllbm_plan P) {
   if (!P) return;
   if (P->has_device) {
     (void)hipSetDevice(P->device);
+    prof_flush(P->prof);
+    for (hipEvent_t e : P->prof.pool) (void)hipEventDestroy(e);
     for (void *d : P->dev_allocs) (void)hipFree(d);
     if (P->scratch) (void)hipFree(P->scratch);
     if (P->nstate) (void)hipFree(P->nstate);

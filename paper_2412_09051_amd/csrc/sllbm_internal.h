@@ -5,6 +5,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_runtime_api.h>
+
 #include "sllbm.h"
 
 namespace sllbm {
@@ -123,6 +125,24 @@ struct sllbm_mesh_s {
   sllbm::Mesh m;
 };
 
+namespace sllbm {
+// Per-kernel timing of one plan: HIP events recorded around each launch on the caller's
+// stream while enabled; read out (after synchronising on the events) as total time and
+// launch count per kernel name.
+struct Profiler {
+  bool on = false;
+  std::vector<std::string> names;
+  std::vector<double> total_ms;
+  std::vector<int64_t> launches;
+  struct Rec {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+};
+}  // namespace sllbm
+
 struct sllbm_plan_s {
   sllbm::Mesh mesh;
   sllbm::VelSet vel;
@@ -143,6 +163,7 @@ struct sllbm_plan_s {
   int64_t scratch_len = 0;      // doubles
   // host copies kept for the GPU-free info path
   std::vector<double> vol;
+  sllbm::Profiler prof;
 };
 
 namespace sllbm {

@@ -44,4 +44,17 @@ int launch_moments(sllbm_plan_s *P, const StepArgs &a, const void *pop, double *
                    bool totals, hipStream_t s);
 int launch_mass_scale(sllbm_plan_s *P, const void *pop, double mass_ref, hipStream_t s);
 
+// Per-kernel timing: while the plan's profiler is on, a ProfScope around a launch
+// records HIP events before and after it on the launch stream.
+void prof_begin(sllbm_plan_s *P, const char *name, hipStream_t s, int *id, hipEvent_t *a);
+void prof_end(sllbm_plan_s *P, int id, hipEvent_t a, hipStream_t s);
+struct ProfScope {
+  sllbm_plan_s *P;
+  hipStream_t s;
+  int id = -1;
+  hipEvent_t a = nullptr;
+  ProfScope(sllbm_plan_s *P_, const char *name, hipStream_t s_) : P(P_), s(s_) { prof_begin(P, name, s, &id, &a); }
+  ~ProfScope() { prof_end(P, id, a, s); }
+};
+
 }  // namespace sllbm

@@ -258,6 +258,7 @@ template <typename T, int D, int P>
 void launch_gather_t(sllbm_plan_s *Pl, const StepArgs &a, const Slab &sl, const void *pin, void *pout,
                      hipStream_t s) {
   if (sl.total <= 0) return;
+  ProfScope ps(Pl, "k_step_gather", s);
   hipLaunchKernelGGL((k_step_gather<T, D, P>), dim3((unsigned)nblocks(sl.total)), dim3(kBlock), 0, s, Pl->tp, a, sl,
                      (const T *)pin, (T *)pout);
 }
@@ -348,6 +349,7 @@ int launch_mass_scale(sllbm_plan_s *Pl, const void *pop, double mass_ref, hipStr
   int64_t N = Pl->mesh.n_nodes, nb = nblocks(N);
   const double *vol = Pl->kernel == 0 ? Pl->tp.vol : Pl->cp.vol;
   double *part = Pl->scratch + kScratchHead;
+  ProfScope ps(Pl, "k_mass_scale", s);
   if (Pl->prec == SLLBM_F32)
     hipLaunchKernelGGL(k_mass_partial<float>, dim3((unsigned)nb), dim3(kBlock), 0, s, N, Pl->vel.Q, vol,
                        (const float *)pop, part);

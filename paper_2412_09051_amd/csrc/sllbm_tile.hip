@@ -5,9 +5,11 @@
 // displacement, at most one cell of halo on one side per axis) from HBM into LDS, then
 // applies the separable interpolant of eq:intf as three 1D passes (x, y, z) in LDS:
 // the cost per streamed value is 3(p+1) multiply-adds instead of (p+1)^3 gathers.
-// Two launches per step over the velocities: the first reduces the conserved moments
-// of the streamed populations per node into a small node-state array (6 doubles per
-// node), the second re-streams, applies the BGK relaxation and forcing, and stores.  Nodes in the boundary layers of a bounded
+// Two launches per step: the first streams every velocity, stores the streamed f_i, g_i
+// and reduces their conserved moments per node into a small node-state array (6 doubles
+// per node); the second relaxes the stored populations in place, one node per lane.
+// (Built with TILE_STORE=0, the second launch re-streams instead of reading the stored
+// values: half the HBM writes, twice the interpolation.)  Nodes in the boundary layers of a bounded
 // face (where some departure point leaves the domain, and where the isothermal-wall
 // correction acts) are left to the per-node gather kernel, launched on those slabs.
 #include <hip/hip_runtime.h>
@@ -25,6 +27,11 @@ namespace sllbm {
 #endif
 #ifndef PASS_UNROLL
 #define PASS_UNROLL 1
+#endif
+// 1: the moments launch also stores the streamed populations and a per-node kernel
+// relaxes them in place; 0: the second launch re-streams them instead
+#ifndef TILE_STORE
+#define TILE_STORE 1
 #endif
 
 struct TileGrid {
@@ -92,7 +99,8 @@ __device__ __forceinline__ int wrap_idx(int g, int N) {
   return g;
 }
 
-// MODE 1: streamed moments -> node state (rho, u, T, 1/tau_bar as [6][N] doubles);
+// MODE 1: streamed moments -> node state (rho, u, T, 1/tau_bar as [6][N] doubles), and
+// with TILE_STORE the streamed populations -> pout;
 // MODE 2: re-stream, relax against the node state, store.
 template <typename T, int D, int P, int CX, int CY, int CZ, int BS, int WPE, int MODE>
 __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, const StepArgs sa, const TileGrid tg,
@@ -336,6 +344,15 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
       stream_velocity(i, i + 1 < Q ? i + 1 : -1, fv, gv);
       const double *vi = pl.vel + 8 * i;
       const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
+      if (TILE_STORE) {
+#pragma unroll
+        for (int m = 0; m < NPT; m++) {
+          if (!own[m]) continue;
+          const int64_t k = node_index(m);
+          pout[(size_t)i * N + k] = (T)fv[m];
+          pout[((size_t)Q + i) * N + k] = (T)gv[m];
+        }
+      }
 #pragma unroll
       for (int m = 0; m < NPT; m++) {
         rho[m] += fv[m];
@@ -416,6 +433,51 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
   }
 }
 
+// In-place BGK relaxation and forcing of the streamed populations the moments launch
+// stored, one node per lane (its equilibrium coefficients built once); nodes in the
+// boundary layers of a bounded face belong to the gather kernel and are skipped.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, const StepArgs sa,
+                                                        T *__restrict__ pop, const double *__restrict__ nstate) {
+  const int64_t N = pl.N;
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= N) return;
+  const int Nx = pl.ax[0].N, Ny = pl.ax[1].N;
+  for (int fc = 0; fc < pl.nfaces; fc++) {
+    const DevFace &F = pl.face[fc];
+    int64_t n3 = F.axis == 0 ? k % Nx : (F.axis == 1 ? (k / Nx) % Ny : k / ((int64_t)Nx * Ny));
+    int64_t l = F.side == 0 ? n3 : pl.ax[F.axis].N - 1 - n3;
+    if (l < F.depth) return;
+  }
+  if (sa.relax_mode == 2) return;   // pure streaming: the stored values are final
+  const int Q = pl.Q;
+  const double rho = nstate[k], u0 = nstate[N + k], u1 = nstate[2 * N + k], u2 = nstate[3 * N + k];
+  const double Tn = nstate[4 * N + k], itau = nstate[5 * N + k];
+  const EqNode e = eq_prepare(rho, u0, u1, u2, Tn, sa, D);
+  EqNode ef = e;
+  if (sa.has_force) {
+    double r = sa.dt / rho;
+    ef = eq_prepare(rho, u0 + sa.force[0] * r, u1 + sa.force[1] * r, u2 + sa.force[2] * r, Tn, sa, D);
+  }
+  const double gT = Tn * sa.gbase;
+  for (int i = 0; i < Q; i++) {
+    const double *vi = pl.vel + 8 * i;
+    T *pf = pop + (size_t)i * N + k;
+    T *pg = pop + ((size_t)Q + i) * N + k;
+    double f = (double)*pf, g = (double)*pg;
+    double fe = eq_f(e, vi);
+    double fo = f - (f - fe) * itau;
+    double go = g - (g - gT * fe) * itau;
+    if (sa.has_force) {
+      double df = eq_f(ef, vi) - fe;
+      fo += df;
+      go += gT * df;
+    }
+    *pf = (T)fo;
+    *pg = (T)go;
+  }
+}
+
 // ------------------------------------------------------------------ launcher
 
 namespace {
@@ -433,10 +495,21 @@ int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *po
   int ntiles = tg.nt[0] * tg.nt[1] * tg.nt[2];
   tg.q = ntiles / 8;
   tg.r = ntiles % 8;
-  hipLaunchKernelGGL((k_step_tile<T, D, P, CX, CY, CZ, BS, WPE, 1>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
-                     (const T *)pin, (T *)pout, Pl->nstate);
-  hipLaunchKernelGGL((k_step_tile<T, D, P, CX, CY, CZ, BS, WPE2, 2>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
-                     (const T *)pin, (T *)pout, Pl->nstate);
+  {
+    ProfScope ps(Pl, "k_step_tile", s);
+    hipLaunchKernelGGL((k_step_tile<T, D, P, CX, CY, CZ, BS, WPE, 1>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
+                       (const T *)pin, (T *)pout, Pl->nstate);
+  }
+  if (TILE_STORE) {
+    (void)WPE2;
+    ProfScope ps(Pl, "k_relax_nodes", s);
+    hipLaunchKernelGGL((k_relax_nodes<T, D>), dim3((unsigned)((tp.N + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tp,
+                       a, (T *)pout, (const double *)Pl->nstate);
+  } else {
+    ProfScope ps(Pl, "k_step_tile_restream", s);
+    hipLaunchKernelGGL((k_step_tile<T, D, P, CX, CY, CZ, BS, WPE2, 2>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
+                       (const T *)pin, (T *)pout, Pl->nstate);
+  }
   return SLLBM_OK;
 }
 }  // namespace

@@ -201,3 +201,14 @@ def test_tiled_kernel_eligibility_follows_the_halo_rule():
     assert S.sllbm_plan_info(S.sllbm_interp_plan(m, vs, big))["kernel"] == 0
     small = W.tgv_case(ncell=5, p=3)[0]       # 15 nodes per axis < tile + halo
     assert S.sllbm_plan_info(S.sllbm_interp_plan(S.sllbm_mesh_build(small), vs, phys.dt))["kernel"] == 0
+
+
+def test_profiling_needs_a_device_plan():
+    mesh, phys = W.shear_wave_case(ncell=4, p=2)
+    plan = S.sllbm_interp_plan(S.sllbm_mesh_build(mesh), S.sllbm_velset_gauss_hermite(2), phys.dt)
+    if S.sllbm_plan_info(plan)["has_device"]:
+        pytest.skip("a GPU is present")
+    with pytest.raises(S.SllbmError) as e:
+        S.sllbm_plan_profile(plan, True)
+    assert e.value.code == S.SLLBM_EHIP
+    assert S.sllbm_plan_profile_read(plan) == {}

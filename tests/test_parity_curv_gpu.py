@@ -105,7 +105,7 @@ def test_warped_box_force_and_mass_fix_fp64():
 
 @pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
 def test_full_size_ogrid_one_step_sampled(prec, tol):
-    """The 256 x 128 cell, p = 4 O-grid (525,312 nodes) at Ma 2: one step from the
+    """The 256 x 128 cell, p = 4 O-grid (525,312 nodes) at Ma 1.5: one step from the
     initial field on the GPU, checked at 512 sampled nodes (all wall nodes' neighbours
     included) against the oracle's step at those nodes."""
     mesh, phys = W.naca_ogrid()

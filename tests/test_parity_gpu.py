@@ -255,3 +255,21 @@ def test_kernel_selection_reports_the_kernel_in_use():
     assert GpuRun(mesh, phys, "f64", GATHER).kernel == 0
     mesh5, phys5 = W.tgv_case(ncell=5, p=3)   # 15 nodes per axis: too few for a tile + halo
     assert GpuRun(mesh5, phys5, "f64").kernel == 0
+
+
+def test_plan_profile_counts_every_launch():
+    """Per-kernel event timing: one entry per launch of each kernel of the step."""
+    mesh, phys = W.tgv_case(ncell=8, p=3)
+    g = GpuRun(mesh, phys, "f64")
+    rho, u, T = W.tgv_fields(g.coords())
+    g.init(rho, u, T)
+    g.S.sllbm_plan_profile(g.plan, True)
+    g.run(7)
+    prof = g.S.sllbm_plan_profile_read(g.plan)
+    g.S.sllbm_plan_profile(g.plan, False)
+    say("profile", prof)
+    assert g.kernel == TILED
+    assert prof["k_step_tile"][1] == 7 and prof["k_relax_nodes"][1] == 7
+    assert all(ms > 0 for ms, _ in prof.values())
+    g.run(2)
+    assert g.S.sllbm_plan_profile_read(g.plan) == prof   # stopped: nothing more recorded

@@ -323,7 +323,7 @@ def naca0012_surface(theta: np.ndarray) -> np.ndarray:
 
 
 def naca_ogrid(n_around: int = 256, n_radial: int = 128, p: int = 4, nodes: str = "gll", R_out: float = 10.0,
-               dr0: float = 2e-3, Ma: float = 2.0, Re: float = 1e4, T_inf: float = 1.0, gamma: float = 1.4,
+               dr0: float = 2e-3, Ma: float = 1.5, Re: float = 1e4, T_inf: float = 1.0, gamma: float = 1.4,
                dt: float = 1.5e-4, smooth: int = 20):
     """Body-fitted O-grid around a NACA 0012 section: n_around cells around (cosine
     clustering at the leading and trailing edges through the x = (1+cos)/2 law) and
@@ -390,7 +390,7 @@ def naca_ogrid(n_around: int = 256, n_radial: int = 128, p: int = 4, nodes: str 
     return mesh, phys
 
 
-def naca_fields(xyz: np.ndarray, Ma: float = 2.0, T_inf: float = 1.0, gamma: float = 1.4):
+def naca_fields(xyz: np.ndarray, Ma: float = 1.5, T_inf: float = 1.0, gamma: float = 1.4):
     """Free stream plus the vortex-street trigger u_y = 0.1 u_x sin(1.3 y + 0.1) (Sec. 4.1)."""
     u_inf = Ma * math.sqrt(gamma * T_inf)
     n = xyz.shape[0]
