@@ -225,6 +225,60 @@ def random_fields(n: int, dim: int, seed: int, rho_amp=0.05, u_amp=0.2, T_amp=0.
 
 
 # --------------------------------------------------------------------------
+# C5: temporal compressible mixing layer (Sec. 4.4), coarse and nested fine meshes
+# --------------------------------------------------------------------------
+
+MIX_DTHETA0 = 0.093
+
+
+def mixing_layer_case(ncell=(64, 64, 64), p: int = 2, refine: int = 1, Ma_c: float = 0.7, box=None,
+                      Re_theta: float = 160.0, cfl: float = 0.5, T_inf: float = 1.0):
+    """Periodic in x and z, bounded in y by moving equilibrium walls u_x = +-du/2 (the
+    temporal mixing layer of Sec. 4.4; du = 2 Ma_c sqrt(gamma T)).  The box defaults to
+    160 x 176 x 98 initial momentum thicknesses (0.093).  refine = r gives the nested
+    fine mesh with r times the cells per axis and the time step divided by r, whose
+    every r-th node along each axis is a node of the coarse mesh (p = 2, GLL)."""
+    if box is None:
+        box = (160 * MIX_DTHETA0, 176 * MIX_DTHETA0, 98 * MIX_DTHETA0)
+    n = tuple(c * refine for c in ncell)
+    du = 2.0 * Ma_c * math.sqrt(1.4 * T_inf)
+    edges = [uniform_edges(n[0], 0.0, box[0]), uniform_edges(n[1], -0.5 * box[1], 0.5 * box[1]),
+             uniform_edges(n[2], 0.0, box[2])]
+    bcs = [BC(kind=BC_INLET, rho=1.0, u=(-0.5 * du, 0.0, 0.0), T=T_inf),
+           BC(kind=BC_INLET, rho=1.0, u=(0.5 * du, 0.0, 0.0), T=T_inf)]
+    mesh = TensorMesh(dim=3, p=p, nodes="gll", ncell=n, edges=edges,
+                      face_bc=[[-1, -1], [0, 1], [-1, -1]], bcs=bcs)
+    h_coarse = min(box[a] / ncell[a] for a in range(3))
+    dt = cfl * h_coarse / ZETA_MAX_GH5 / refine
+    mu = du * MIX_DTHETA0 / Re_theta
+    phys = Physics(gamma=1.4, dt=dt, relax_mode=1, mu_ref=mu, T_ref=T_inf, mu_exp=0.0)
+    return mesh, phys
+
+
+def mixing_layer_fields(xyz: np.ndarray, Ma_c: float = 0.7, amp: float = 0.05, seed: int = 5, T_inf: float = 1.0,
+                        box=None, kmax: int = 4):
+    """tanh profile u_x = du/2 tanh(y / (2 dtheta0)) plus broadband seeded perturbations
+    (random-phase Fourier modes up to kmax per periodic axis, amplitude amp du, confined
+    to the layer by a Gaussian in y); rho = 1, T = T_inf."""
+    if box is None:
+        box = (160 * MIX_DTHETA0, 176 * MIX_DTHETA0, 98 * MIX_DTHETA0)
+    du = 2.0 * Ma_c * math.sqrt(1.4 * T_inf)
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    env = np.exp(-(y / (4.0 * MIX_DTHETA0)) ** 2)
+    u = np.zeros((xyz.shape[0], 3))
+    u[:, 0] = 0.5 * du * np.tanh(y / (2.0 * MIX_DTHETA0))
+    for c in range(3):
+        for kx in range(1, kmax + 1):
+            for kz in range(0, kmax + 1):
+                ph = rng.uniform(0.0, 2.0 * math.pi, 2)
+                a = rng.uniform(-1.0, 1.0)
+                u[:, c] += (amp * du / kmax) * a * env * np.cos(2 * math.pi * kx * x / box[0] + ph[0]) * \
+                    np.cos(2 * math.pi * kz * z / box[2] + ph[1])
+    return np.ones(xyz.shape[0]), u, np.full(xyz.shape[0], T_inf)
+
+
+# --------------------------------------------------------------------------
 # Curvilinear meshes (2D isoparametric quads of order p)
 # --------------------------------------------------------------------------
 
