@@ -194,6 +194,66 @@ int sllbm_step(sllbm_plan p, const sllbm_params *prm, const void *pop_in, void *
 int sllbm_moments(sllbm_plan p, const sllbm_params *prm, const void *pop, double *rho, double *u, double *T,
                   double *totals_host, void *stream);
 
+/* ------------------------------------------------------------------------------------
+ * Learned post-collision correction (tensor-product plans)
+ *
+ * A small network maps the moments of a node and their gradients to a correction of the
+ * node's post-collision populations on a coarse mesh; it is trained on restricted runs
+ * of a finer mesh.  The plain step stays the method; the correction is a separate call
+ * after it, so leaving it out falls back to the plain method.
+ *
+ * Features of node k (n_feat = (D+2)(D+1): 12 in 2D, 20 in 3D), in this order:
+ *   rho - 1, u_a / sqrt(T0) (a < D), T / T0 - 1, then for each of those D+2 fields q and
+ *   each axis a: h_a dq/dx_a, the derivative of the cell interpolant (eq:intf) along a at
+ *   the node averaged over the cells that share the node on that axis, h_a the mean
+ *   length of those cells.  Stored as BF16 (round to nearest even), row-major [N][n_feat].
+ * Network: three tanh layers of width 64 and a linear output y of n_out = 2Q values;
+ *   matrix-product inputs in BF16 (MFMA), sums and master weights in FP32.  Parameters,
+ *   flat FP32 in the order W1 [n_in][64], b1, W2 [64][64], b2, W3, b3, W4 [64][n_out], b4.
+ * Correction: pop_k += P (w rho_k * y_k), the output scaled by w_i rho_k (w repeated for
+ *   f and g), projected off the collision invariants (mass, momentum, total energy) in the
+ *   inner product weighted by 1/w_i, so that no moment of the node changes.
+ * Training targets: t_k = P (pop_true - pop_plain)_k / (w rho_k), rho_k of pop_plain;
+ *   loss = mean over rows and outputs of (y - t)^2; Adam (0.9, 0.999, 1e-8).
+ * ------------------------------------------------------------------------------------ */
+typedef struct sllbm_mlp_s *sllbm_mlp;
+
+/* A network with n_in <= 32 inputs and n_out <= 256 outputs (width 64 and depth 3 only,
+ * else SLLBM_EUNSUPPORTED), on the current device.  Weights uniform in
+ * +-1/sqrt(fan_in) from a splitmix64 counter stream of `seed`, biases 0, Adam state 0. */
+int sllbm_mlp_create(int n_in, int width, int depth, int n_out, uint64_t seed, sllbm_mlp *out);
+void sllbm_mlp_destroy(sllbm_mlp m);
+int sllbm_mlp_num_params(sllbm_mlp m, int64_t *n);
+/* Copy the FP32 master parameters to / from host memory (set also resets Adam). */
+int sllbm_mlp_get_params(sllbm_mlp m, float *host);
+int sllbm_mlp_set_params(sllbm_mlp m, const float *host);
+
+/* Node features of a population field (see above) into feat_bf16 (device, [N][n_feat]). */
+int sllbm_features(sllbm_plan p, const sllbm_params *prm, const void *pop, uint16_t *feat_bf16, void *stream);
+/* y = network(x) for `rows` rows of BF16 inputs [rows][n_in] (device); y device FP32
+ * [rows][n_out]. */
+int sllbm_mlp_forward(sllbm_mlp m, const uint16_t *x_bf16, int64_t rows, float *y, void *stream);
+/* In place on a post-collision population field of plan p: features, network, scaled and
+ * projected correction added.  The network's n_in / n_out must match the plan. */
+int sllbm_mlp_correct(sllbm_plan p, const sllbm_params *prm, sllbm_mlp m, void *pop, void *stream);
+/* Training targets of every node of plan p into t (device FP32 [N][2Q]). */
+int sllbm_learned_targets(sllbm_plan p, const void *pop_plain, const void *pop_true, float *t, void *stream);
+/* Injection of a fine population field onto a nested coarse mesh: coarse node (jx,jy,jz)
+ * takes fine node (r jx, r jy, r jz).  The meshes must be nested at that ratio (checked
+ * on the node coordinates: SLLBM_EINVAL otherwise), with the same velocity set and
+ * precision. */
+int sllbm_restrict(sllbm_plan fine, sllbm_plan coarse, int ratio, const void *pop_fine, void *pop_coarse,
+                   void *stream);
+/* Loss and parameter gradient over `rows` rows (inputs BF16 [rows][n_in], targets FP32
+ * [rows][n_out], device), without updating: grad_host (nparams floats) and loss_host
+ * optional; synchronises the stream when either is given. */
+int sllbm_mlp_gradient(sllbm_mlp m, const uint16_t *x_bf16, const float *t, int64_t rows, float *grad_host,
+                       float *loss_host, void *stream);
+/* One training step: loss and gradient over the rows, then one Adam update of the FP32
+ * master weights with learning rate lr.  loss_host optional (synchronises when given). */
+int sllbm_mlp_train_step(sllbm_mlp m, const uint16_t *x_bf16, const float *t, int64_t rows, float lr,
+                         float *loss_host, void *stream);
+
 const char *sllbm_last_error(void);
 
 #ifdef __cplusplus

@@ -344,6 +344,125 @@ def sllbm_moments(plan: Plan, params: Params, pop, rho=None, u=None, T=None, tot
     return tot
 
 
+# ------------------------------------------------------------------ learned correction
+
+for _name in ("sllbm_mlp_create", "sllbm_mlp_num_params", "sllbm_mlp_get_params", "sllbm_mlp_set_params",
+              "sllbm_features", "sllbm_mlp_forward", "sllbm_mlp_correct", "sllbm_learned_targets", "sllbm_restrict",
+              "sllbm_mlp_gradient", "sllbm_mlp_train_step"):
+    getattr(_lib, _name).restype = ctypes.c_int
+_lib.sllbm_mlp_destroy.restype = None
+
+
+class Mlp:
+    """Owner of an sllbm_mlp handle (a network of n_in -> 64 -> 64 -> 64 -> n_out)."""
+
+    def __init__(self, handle, n_in, n_out):
+        self._lib = _lib
+        self.handle = handle
+        self.n_in, self.n_out = n_in, n_out
+        n = ctypes.c_int64(0)
+        _check(_lib.sllbm_mlp_num_params(handle, ctypes.byref(n)), "sllbm_mlp_num_params")
+        self.nparam = n.value
+
+    def __del__(self):
+        lib = getattr(self, "_lib", None)
+        if getattr(self, "handle", None) and lib is not None:
+            lib.sllbm_mlp_destroy(self.handle)
+            self.handle = None
+
+
+def sllbm_mlp_create(n_in: int, n_out: int, seed: int = 0, width: int = 64, depth: int = 3) -> Mlp:
+    h = ctypes.c_void_p()
+    _check(_lib.sllbm_mlp_create(ctypes.c_int(n_in), ctypes.c_int(width), ctypes.c_int(depth), ctypes.c_int(n_out),
+                                 ctypes.c_uint64(seed), ctypes.byref(h)), "sllbm_mlp_create")
+    return Mlp(h, n_in, n_out)
+
+
+def sllbm_mlp_get_params(m: Mlp) -> np.ndarray:
+    out = np.zeros(m.nparam, dtype=np.float32)
+    _check(_lib.sllbm_mlp_get_params(m.handle, out.ctypes.data_as(ctypes.c_void_p)), "sllbm_mlp_get_params")
+    return out
+
+
+def sllbm_mlp_set_params(m: Mlp, theta) -> None:
+    a = np.ascontiguousarray(theta, dtype=np.float32)
+    if a.size != m.nparam:
+        raise ValueError(f"need {m.nparam} parameters, got {a.size}")
+    _check(_lib.sllbm_mlp_set_params(m.handle, a.ctypes.data_as(ctypes.c_void_p)), "sllbm_mlp_set_params")
+
+
+def n_features(dim: int) -> int:
+    return (dim + 2) * (dim + 1)
+
+
+def sllbm_features(plan: Plan, params: Params, pop, feat, stream=None):
+    """feat: torch.bfloat16 [N, n_features(dim)] on the GPU."""
+    import torch
+    _check(_lib.sllbm_features(plan.handle, ctypes.byref(params.c()),
+                               _dev_ptr(pop, _pop_dtype(plan), 2 * plan.Q * plan.N, "pop"),
+                               _dev_ptr(feat, torch.bfloat16, plan.N * n_features(plan.dim), "feat"), _stream(stream)),
+           "sllbm_features")
+
+
+def sllbm_mlp_forward(m: Mlp, x, y, stream=None):
+    """x: torch.bfloat16 [rows, n_in]; y: torch.float32 [rows, n_out]."""
+    import torch
+    rows = x.shape[0]
+    _check(_lib.sllbm_mlp_forward(m.handle, _dev_ptr(x, torch.bfloat16, rows * m.n_in, "x"), ctypes.c_int64(rows),
+                                  _dev_ptr(y, torch.float32, rows * m.n_out, "y"), _stream(stream)), "sllbm_mlp_forward")
+
+
+def sllbm_mlp_correct(plan: Plan, params: Params, m: Mlp, pop, stream=None):
+    _check(_lib.sllbm_mlp_correct(plan.handle, ctypes.byref(params.c()), m.handle,
+                                  _dev_ptr(pop, _pop_dtype(plan), 2 * plan.Q * plan.N, "pop"), _stream(stream)),
+           "sllbm_mlp_correct")
+
+
+def sllbm_learned_targets(plan: Plan, pop_plain, pop_true, t, stream=None):
+    """t: torch.float32 [N, 2Q]."""
+    import torch
+    n = 2 * plan.Q * plan.N
+    dt = _pop_dtype(plan)
+    _check(_lib.sllbm_learned_targets(plan.handle, _dev_ptr(pop_plain, dt, n, "pop_plain"),
+                                      _dev_ptr(pop_true, dt, n, "pop_true"), _dev_ptr(t, torch.float32, n, "t"),
+                                      _stream(stream)), "sllbm_learned_targets")
+
+
+def sllbm_restrict(fine: Plan, coarse: Plan, ratio: int, pop_fine, pop_coarse, stream=None):
+    dt = _pop_dtype(coarse)
+    _check(_lib.sllbm_restrict(fine.handle, coarse.handle, ctypes.c_int(ratio),
+                               _dev_ptr(pop_fine, dt, 2 * fine.Q * fine.N, "pop_fine"),
+                               _dev_ptr(pop_coarse, dt, 2 * coarse.Q * coarse.N, "pop_coarse"), _stream(stream)),
+           "sllbm_restrict")
+
+
+def sllbm_mlp_gradient(m: Mlp, x, t, stream=None):
+    """(gradient as float32 numpy [nparam], mean-square loss) over the rows of x, t."""
+    import torch
+    rows = x.shape[0]
+    g = np.zeros(m.nparam, dtype=np.float32)
+    loss = ctypes.c_float(0)
+    _check(_lib.sllbm_mlp_gradient(m.handle, _dev_ptr(x, torch.bfloat16, rows * m.n_in, "x"),
+                                   _dev_ptr(t, torch.float32, rows * m.n_out, "t"), ctypes.c_int64(rows),
+                                   g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss), _stream(stream)),
+           "sllbm_mlp_gradient")
+    return g, loss.value
+
+
+def sllbm_mlp_train_step(m: Mlp, x, t, lr: float, want_loss: bool = True, stream=None):
+    import torch
+    rows = x.shape[0]
+    loss = ctypes.c_float(0)
+    _check(_lib.sllbm_mlp_train_step(m.handle, _dev_ptr(x, torch.bfloat16, rows * m.n_in, "x"),
+                                     _dev_ptr(t, torch.float32, rows * m.n_out, "t"), ctypes.c_int64(rows),
+                                     ctypes.c_float(lr), ctypes.byref(loss) if want_loss else None, _stream(stream)),
+           "sllbm_mlp_train_step")
+    return loss.value if want_loss else None
+
+
 __all__ = ["sllbm_velset_gauss_hermite", "sllbm_mesh_build", "sllbm_mesh_nodes", "sllbm_mesh_volumes",
            "sllbm_interp_plan", "sllbm_plan_info", "sllbm_plan_select_kernel", "sllbm_init_equilibrium", "sllbm_step", "sllbm_moments",
-           "Params", "Plan", "Mesh", "SllbmError", "SLLBM_F64", "SLLBM_F32", "LIB_PATH"]
+           "Params", "Plan", "Mesh", "SllbmError", "SLLBM_F64", "SLLBM_F32", "LIB_PATH",
+           "Mlp", "sllbm_mlp_create", "sllbm_mlp_get_params", "sllbm_mlp_set_params", "sllbm_features",
+           "sllbm_mlp_forward", "sllbm_mlp_correct", "sllbm_learned_targets", "sllbm_restrict", "sllbm_mlp_gradient",
+           "sllbm_mlp_train_step", "n_features"]

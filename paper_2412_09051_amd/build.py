@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsllbm.so")
 
-SOURCES = ["sllbm_host.cpp", "sllbm_csr.cpp", "sllbm_device.hip", "sllbm_kernels.hip", "sllbm_tile.hip", "sllbm_csr_kernel.hip"]
+SOURCES = ["sllbm_host.cpp", "sllbm_csr.cpp", "sllbm_device.hip", "sllbm_kernels.hip", "sllbm_tile.hip", "sllbm_csr_kernel.hip", "sllbm_mlp.hip"]
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU ops.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

@@ -164,6 +164,12 @@ struct sllbm_plan_s {
   // host copies kept for the GPU-free info path
   std::vector<double> vol;
   sllbm::Profiler prof;
+  // learned correction (built on first use): node fields [D+2][N], features [N][n_feat],
+  // per-axis derivative stencils [N_a][2][p+1] (node index along the axis, weight)
+  double *lfield = nullptr;
+  uint16_t *lfeat = nullptr;
+  int32_t *ldidx[3] = {nullptr, nullptr, nullptr};
+  double *ldw[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace sllbm {
