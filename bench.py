@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-ogrid", action="store_true", help="skip the curvilinear O-grid workload")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction (mixing layer) workload")
     ap.add_argument("--kernel", choices=["auto", "gather", "tiled"], default="auto")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for byte counters)")
@@ -171,6 +172,192 @@ def ogrid_leg(prec, steps, warmup):
                      bpu=curv_bytes_per_update(prec, mesh.p))
 
 
+MIX_BOX_CELLS = (2.5, 2.75, 1.5)      # coarse cell size per axis in initial momentum thicknesses
+
+
+def mixing_dtheta(S, torch, plan, prm, pop, shape, du, V, box):
+    """Momentum thickness (1 / (rho0 du^2)) int <rho> (du/2 - u~)(du/2 + u~) dy of a
+    population field: plane averages over x and z and the y integral with the nodal
+    quadrature weights, u~ = <rho u> / <rho> (rho0 = 1)."""
+    N = plan.N
+    rho = torch.empty(N, dtype=torch.float64, device="cuda")
+    u = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+    S.sllbm_moments(plan, prm, pop, rho, u, None)
+    Nx, Ny, Nz = shape
+    r = rho.view(Nz, Ny, Nx)
+    ux = u[:N].view(Nz, Ny, Nx)
+    A = (V * r).sum(dim=(0, 2))
+    B = (V * r * ux).sum(dim=(0, 2))
+    Wj = V.sum(dim=(0, 2))
+    rbar, ut = A / Wj, B / A
+    wy = Wj / (box[0] * box[2])
+    return float((wy * rbar * (0.5 * du - ut) * (0.5 * du + ut)).sum() / du ** 2)
+
+
+def learned_leg(ncell=16, ratio=4, steps=300, n_train=8, train_iters=1500, Ma_c=0.7, alphas=(0.0, 0.25, 0.5, 1.0),
+                targets="injected"):
+    """C5: temporal mixing layer on a coarse mesh, plain and with the learned correction,
+    against the 4x finer mesh; FP32 populations.  The network is trained by the library's
+    kernels on restricted one-step samples of a fine run (seed 5); a gain alpha on its
+    output (0 = the plain method) is chosen on that same run's momentum-thickness history;
+    everything is then evaluated on a run it never saw (seed 6): momentum-thickness history
+    and time per coarse step.  targets="injected": a sample starts the plain coarse step
+    from the restricted fine state; "trajectory": from the plain coarse run started at the
+    restricted initial state, so that the features come from coarse-evolved states as in
+    use and the target includes the drift accumulated so far."""
+    import torch
+    import paper_2412_09051_amd as S
+    import workloads as W
+    d0 = W.MIX_DTHETA0
+    box = tuple(ncell * c * d0 for c in MIX_BOX_CELLS)
+    mesh, phys = W.mixing_layer_case(ncell=(ncell,) * 3, box=box, Ma_c=Ma_c)
+    fmesh, fphys = W.mixing_layer_case(ncell=(ncell,) * 3, refine=ratio, box=box, Ma_c=Ma_c)
+    du = 2.0 * Ma_c * math.sqrt(1.4)
+    mats = {}
+    for name, (me, ph) in (("c", (mesh, phys)), ("f", (fmesh, fphys))):
+        mm = S.sllbm_mesh_build(me)
+        pl = S.sllbm_interp_plan(mm, S.sllbm_velset_gauss_hermite(3, 5, ph.T0), ph.dt, S.SLLBM_F32)
+        shape = tuple(me.ncell[a] * me.p + (0 if me.face_bc[a][0] < 0 else 1) for a in range(3))
+        V = torch.tensor(S.sllbm_mesh_volumes(mm), device="cuda").view(shape[2], shape[1], shape[0])
+        mats[name] = (mm, pl, S.Params.from_physics(ph), shape, V)
+    cm, cplan, cprm, cshape, cV = mats["c"]
+    fm, fplan, fprm, fshape, fV = mats["f"]
+    Q, Nc, Nf = cplan.Q, cplan.N, fplan.N
+    nf = S.n_features(3)
+    every_h = 25
+
+    def fine_init(seed):
+        rho, u, T = W.mixing_layer_fields(S.sllbm_mesh_nodes(fm), box=box, amp=0.1, seed=seed, Ma_c=Ma_c)
+        a = torch.empty(2 * Q * Nf, dtype=torch.float32, device="cuda")
+        S.sllbm_init_equilibrium(fplan, fprm, torch.tensor(rho, device="cuda"), torch.tensor(u.T.copy(), device="cuda"),
+                                 torch.tensor(T, device="cuda"), a)
+        return a, torch.empty_like(a)
+
+    def restrict(fa):
+        c = torch.empty(2 * Q * Nc, dtype=torch.float32, device="cuda")
+        S.sllbm_restrict(fplan, cplan, ratio, fa, c)
+        return c
+
+    def dth(which, pop):
+        plan, prm, shape, V = (fplan, fprm, fshape, fV) if which == "f" else (cplan, cprm, cshape, cV)
+        return mixing_dtheta(S, torch, plan, prm, pop, shape, du, V, box)
+
+    def coarse_rollout(c0, net=None, timed=False):
+        a, b = c0.clone(), torch.empty_like(c0)
+        hist, ms = [], 0.0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for n in range(steps + 1):
+            if n % every_h == 0:
+                hist.append(dth("c", a))
+            if n == steps:
+                break
+            e0.record()
+            S.sllbm_step(cplan, cprm, a, b)
+            if net is not None:
+                S.sllbm_mlp_correct(cplan, cprm, net, b)
+            e1.record()
+            a, b = b, a
+            if timed:
+                torch.cuda.synchronize()
+                ms += e0.elapsed_time(e1)
+        return hist, ms
+
+    def fine_history(seed, samples=False, timed=False):
+        fa, fb = fine_init(seed)
+        c_init = restrict(fa)
+        cc = c_init.clone()
+        hist, X, T, ms = [], [], [], 0.0
+        every = max(1, steps // n_train)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for n in range(steps + 1):
+            if n % every_h == 0:
+                hist.append(dth("f", fa))
+            if n == steps:
+                break
+            take = samples and n % every == 0 and len(X) < n_train
+            if samples and targets == "trajectory":
+                plain = torch.empty(2 * Q * Nc, dtype=torch.float32, device="cuda")
+                S.sllbm_step(cplan, cprm, cc, plain)
+                cc = plain
+            elif take:
+                plain = torch.empty(2 * Q * Nc, dtype=torch.float32, device="cuda")
+                S.sllbm_step(cplan, cprm, restrict(fa), plain)
+            e0.record()
+            for _ in range(ratio):
+                S.sllbm_step(fplan, fprm, fa, fb)
+                fa, fb = fb, fa
+            e1.record()
+            if timed:
+                torch.cuda.synchronize()
+                ms += e0.elapsed_time(e1)
+            if take:
+                truth = restrict(fa)
+                x = torch.empty(Nc, nf, dtype=torch.bfloat16, device="cuda")
+                S.sllbm_features(cplan, cprm, plain, x)
+                t = torch.empty(Nc, 2 * Q, dtype=torch.float32, device="cuda")
+                S.sllbm_learned_targets(cplan, plain, truth, t)
+                X.append(x)
+                T.append(t)
+        return c_init, hist, X, T, ms
+
+    def growth_err(h, ref):
+        g = [v - h[0] for v in h]
+        gr = [v - ref[0] for v in ref]
+        return max(abs(a - b) / abs(b) for a, b in zip(g[1:], gr[1:]))
+
+    # ---- training on seed 5
+    t0 = time.perf_counter()
+    c5, f5, X, T, _ = fine_history(5, samples=True)
+    X, T = torch.cat(X), torch.cat(T)
+    net = S.sllbm_mlp_create(nf, 2 * Q, seed=1)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    losses = []
+    for it in range(train_iters):
+        idx = torch.randint(0, X.shape[0], (4096,), device="cuda", generator=gen)
+        want = it in (0, train_iters - 1)
+        l_ = S.sllbm_mlp_train_step(net, X[idx].contiguous(), T[idx].contiguous(),
+                                    2e-3 if it < (2 * train_iters) // 3 else 5e-4, want_loss=want)
+        if want:
+            losses.append(l_)
+    del X, T
+    # ---- output gain chosen on the training run's momentum thickness
+    theta = S.sllbm_mlp_get_params(net)
+    o4 = nf * 64 + 64 + 2 * (64 * 64 + 64)           # W4, b4 follow
+    sel = {}
+    for a in alphas:
+        th = theta.copy()
+        th[o4:] *= a
+        S.sllbm_mlp_set_params(net, th)
+        h, _ = coarse_rollout(c5, None if a == 0.0 else net)
+        sel[a] = growth_err(h, f5)
+    alpha = min(sel, key=sel.get)
+    th = theta.copy()
+    th[o4:] *= alpha
+    S.sllbm_mlp_set_params(net, th)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    # ---- evaluation on seed 6
+    c6, f6, _, _, t_f = fine_history(6, timed=True)
+    hp, t_p = coarse_rollout(c6, None, timed=True)
+    hl, t_l = coarse_rollout(c6, net, timed=True)
+    hist = {"fine": f6, "plain": hp, "learned": hl}
+    return {
+        "workload": f"3D temporal mixing layer Ma_c {Ma_c}, coarse {ncell}^3 cells p=2 ({Nc} nodes) vs "
+                    f"{ratio}x finer ({Nf} nodes), D3V125, FP32; trained on seed 5, evaluated on seed 6",
+        "steps": steps, "targets": targets, "train_samples": n_train, "train_iters": train_iters, "train_loss": losses,
+        "train_s": round(train_s, 2), "alpha_selection_growth_err": {str(k): round(v, 4) for k, v in sel.items()},
+        "alpha": alpha,
+        "ms_per_coarse_step": {"fine": round(t_f / steps, 4), "plain": round(t_p / steps, 4),
+                               "learned": round(t_l / steps, 4)},
+        "time_to_solution_ratio": {"fine_vs_learned": round(t_f / t_l, 2), "fine_vs_plain": round(t_f / t_p, 2)},
+        "dtheta": {k: [round(v, 6) for v in h] for k, h in hist.items()},
+        "dtheta_growth_max_rel_err": {"plain": round(growth_err(hp, f6), 4), "learned": round(growth_err(hl, f6), 4)},
+        "finite": {k: all(math.isfinite(v) for v in h) for k, h in hist.items()},
+    }
+
+
 def copy_calibration():
     """A plain device copy of 1 GiB, three times: the reference for the FETCH_SIZE and
     WRITE_SIZE counters of the profiled runs."""
@@ -224,6 +411,10 @@ def main():
         for prec in ("f32", "f64"):
             og[prec] = ogrid_leg(prec, args.steps, args.warmup)
             print(f"# ogrid {prec} done: {og[prec]['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
+    lrn = None
+    if not args.no_learned:
+        lrn = learned_leg()
+        print(f"# learned done: time-to-solution ratio {lrn['time_to_solution_ratio']}", file=sys.stderr, flush=True)
     cal = copy_calibration() if args.copy_calibration else None
     cpu = None if args.no_cpu else cpu_leg(args.ncell, args.cpu_steps)
     out = {
@@ -256,6 +447,8 @@ def main():
             **{prec: {"value": round(v["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(v["ms_per_step"], 4),
                       "bytes_per_update": v["bpu"], "plan_build_s": round(v["plan_build_s"], 2),
                       "roofline": roofline(v), "finite": v["finite"]} for prec, v in og.items()}}
+    if lrn:
+        out["learned"] = lrn
     if cal:
         out["copy_calibration"] = cal
     print(json.dumps(out), flush=True)

@@ -11,6 +11,7 @@
 #include <new>
 
 #include "sllbm_internal.h"
+#include "sllbm_kernels.h"
 
 namespace sllbm {
 
@@ -639,8 +640,10 @@ extern "C" void sllbm_mesh_destroy(sllbm_mesh m) { delete m; }
 namespace sllbm {
 
 bool tile_cells(int D, int P, int c[3]) {
-  // keep in step with TileShape<D, P> of the tiled kernel
-  static const int shape[2][3][3] = {{{8, 8, 1}, {8, 4, 1}, {8, 4, 1}}, {{4, 4, 4}, {4, 4, 2}, {2, 2, 2}}};
+#define TSHAPE(DD, PP) {TileShape<DD, PP>::CX, TileShape<DD, PP>::CY, TileShape<DD, PP>::CZ}
+  static const int shape[2][3][3] = {{TSHAPE(2, 2), TSHAPE(2, 3), TSHAPE(2, 4)},
+                                     {TSHAPE(3, 2), TSHAPE(3, 3), TSHAPE(3, 4)}};
+#undef TSHAPE
   if (D < 2 || D > 3 || P < 2 || P > 4) return false;
   for (int a = 0; a < 3; a++) c[a] = shape[D - 2][P - 2][a];
   return true;

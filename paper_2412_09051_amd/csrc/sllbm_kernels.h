@@ -32,7 +32,13 @@ template <> struct TileShape<2, 2> { static constexpr int CX = 8, CY = 8, CZ = 1
 template <> struct TileShape<2, 3> { static constexpr int CX = 8, CY = 4, CZ = 1; };
 template <> struct TileShape<2, 4> { static constexpr int CX = 8, CY = 4, CZ = 1; };
 template <> struct TileShape<3, 2> { static constexpr int CX = 4, CY = 4, CZ = 4; };
-template <> struct TileShape<3, 3> { static constexpr int CX = 4, CY = 4, CZ = 2; };
+#ifndef TILE_3_3
+#define TILE_3_3 4, 4, 2
+#endif
+template <> struct TileShape<3, 3> {
+  static constexpr int c[3] = {TILE_3_3};
+  static constexpr int CX = c[0], CY = c[1], CZ = c[2];
+};
 template <> struct TileShape<3, 4> { static constexpr int CX = 2, CY = 2, CZ = 2; };
 
 int launch_step_csr(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout, hipStream_t s);

@@ -188,8 +188,11 @@ __global__ void __launch_bounds__(NT) k_mlp_correct(MlpArgs m, ProjArgs pa, cons
   __shared__ FwdShared S;
   __shared__ float Y[R * NOUTP];
   __shared__ double C[R * 5];
-  const int64_t row0 = (int64_t)blockIdx.x * R;
-  stage_weights(m, S.W);
+  stage_weights(m, S.W);   // once per workgroup; the workgroup then walks its tiles
+  const int64_t ntiles = (N + R - 1) / R;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  const int64_t row0 = tile * R;
+  __syncthreads();
   stage_x(m, feat, row0, N, S.X);
   __syncthreads();
   hidden_layers(m, S);
@@ -267,6 +270,7 @@ __global__ void __launch_bounds__(NT) k_mlp_correct(MlpArgs m, ProjArgs pa, cons
         *pp = (T)((double)*pp + delta);
       }
     }
+  }
   }
 }
 
@@ -940,7 +944,8 @@ extern "C" int sllbm_mlp_correct(sllbm_plan P, const sllbm_params *prm, sllbm_ml
   if ((rc = proj_args(P, pa))) return rc;
   pa.vel = P->tp.vel;
   const int64_t N = P->mesh.n_nodes;
-  dim3 grid((unsigned)((N + R - 1) / R));
+  // a persistent grid: each workgroup stages the weights once and walks several tiles
+  dim3 grid((unsigned)std::min<int64_t>((N + R - 1) / R, 1024));
   {
     ProfScope ps(P, "k_mlp_correct", s);
     if (P->prec == SLLBM_F32)
