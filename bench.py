@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -44,6 +46,7 @@ def parse():
     ap.add_argument("--no-ogrid", action="store_true", help="skip the curvilinear O-grid workload")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction (mixing layer) workload")
+    ap.add_argument("--no-extra", action="store_true", help="skip the C1-R (2D roofline-scale) and C4 (channel) lines")
     ap.add_argument("--kernel", choices=["auto", "gather", "tiled"], default="auto")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for byte counters)")
@@ -126,6 +129,58 @@ def gpu_leg(prec, steps, warmup, ncell, kernel="auto"):
     updates = N * Q
     return summarize(prof, total_ms, wall, steps, updates, BYTES_PER_UPDATE[prec],
                      finite=all(math.isfinite(x) for x in tot), N=N, Q=Q, mass=float(tot[0]))
+
+
+def tensor_case_leg(case, prec, steps, warmup):
+    """Another tensor-product workload: C1-R (2D shear wave at roofline scale) or C4 (the
+    supersonic channel, with the mass rescaling every 10 steps)."""
+    import dataclasses
+    import torch
+    import paper_2412_09051_amd as S
+    import workloads as W
+    if case == "c1r":
+        mesh, phys = W.shear_wave_case(ncell=1024, p=4)
+        fields = W.shear_wave_fields
+        fix_every = 0
+    else:
+        mesh, phys = W.channel_case()
+        fields = W.channel_fields
+        fix_every = 10
+    m = S.sllbm_mesh_build(mesh)
+    plan = S.sllbm_interp_plan(m, S.sllbm_velset_gauss_hermite(mesh.dim, 5, phys.T0), phys.dt,
+                               S.SLLBM_F32 if prec == "f32" else S.SLLBM_F64)
+    prm = S.Params.from_physics(phys)
+    N, Q = plan.N, plan.Q
+    rho, u, T = fields(S.sllbm_mesh_nodes(m))
+    dt = torch.float32 if prec == "f32" else torch.float64
+    a = torch.empty(2 * Q * N, dtype=dt, device="cuda")
+    b = torch.empty_like(a)
+    S.sllbm_init_equilibrium(plan, prm, torch.tensor(rho, device="cuda"), torch.tensor(np.ascontiguousarray(u.T), device="cuda"),
+                             torch.tensor(T, device="cuda"), a)
+    mref = float(S.sllbm_moments(plan, prm, a, totals=True)[0]) if fix_every else 0.0
+    fixp = dataclasses.replace(prm, mass_fix=1, mass_ref=mref)
+    stream = torch.cuda.current_stream()
+    for n in range(warmup):
+        S.sllbm_step(plan, fixp if fix_every and n % fix_every == 0 else prm, a, b, stream)
+        a, b = b, a
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    S.sllbm_plan_profile(plan, True)
+    t0.record(stream)
+    for n in range(steps):
+        S.sllbm_step(plan, fixp if fix_every and n % fix_every == 0 else prm, a, b, stream)
+        a, b = b, a
+    t1.record(stream)
+    torch.cuda.synchronize()
+    prof = S.sllbm_plan_profile_read(plan)
+    S.sllbm_plan_profile(plan, False)
+    tot = S.sllbm_moments(plan, prm, a, totals=True)
+    r = summarize(prof, t0.elapsed_time(t1), 0.0, steps, N * Q, BYTES_PER_UPDATE[prec],
+                  finite=all(math.isfinite(x) for x in tot), N=N, Q=Q)
+    del a, b
+    torch.cuda.empty_cache()
+    return r
 
 
 def summarize(prof, total_ms, wall, steps, updates, bytes_per_update, **extra):
@@ -411,6 +466,12 @@ def main():
         for prec in ("f32", "f64"):
             og[prec] = ogrid_leg(prec, args.steps, args.warmup)
             print(f"# ogrid {prec} done: {og[prec]['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
+    extra = {}
+    if not args.no_extra:
+        for case, precs in (("c1r", ("f64", "f32")), ("c4", ("f32",))):
+            for prec in precs:
+                extra[f"{case}_{prec}"] = tensor_case_leg(case, prec, max(10, args.steps // 5), 3)
+                print(f"# {case} {prec} done: {extra[f'{case}_{prec}']['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
     lrn = None
     if not args.no_learned:
         lrn = learned_leg()
@@ -447,6 +508,14 @@ def main():
             **{prec: {"value": round(v["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(v["ms_per_step"], 4),
                       "bytes_per_update": v["bpu"], "plan_build_s": round(v["plan_build_s"], 2),
                       "roofline": roofline(v), "finite": v["finite"]} for prec, v in og.items()}}
+    names = {"c1r": "2D periodic shear wave, 1024^2 cells p=4 GLL (16.8M nodes), D2V25",
+             "c4": "3D supersonic channel Ma_b 1.5 Re_b 3000, 128x96x64 cells p=2 (6.3M nodes), D3V125, "
+                   "isothermal walls, forcing, mass rescaling every 10 steps"}
+    for key, v in extra.items():
+        case, prec = key.split("_")
+        out[key] = {"workload": names[case], "dtype": prec, "value": round(v["gqups"], 4), "unit": "GQUPS",
+                    "ms_per_step": round(v["ms_per_step"], 4), "roofline": roofline(v), "kernels": v["kernels"],
+                    "finite": v["finite"]}
     if lrn:
         out["learned"] = lrn
     if cal:
