@@ -158,10 +158,26 @@ def tensor_case_leg(case, prec, steps, warmup):
     S.sllbm_init_equilibrium(plan, prm, torch.tensor(rho, device="cuda"), torch.tensor(np.ascontiguousarray(u.T), device="cuda"),
                              torch.tensor(T, device="cuda"), a)
     mref = float(S.sllbm_moments(plan, prm, a, totals=True)[0]) if fix_every else 0.0
-    fixp = dataclasses.replace(prm, mass_fix=1, mass_ref=mref)
     stream = torch.cuda.current_stream()
+    ctl = None
+    if case == "c4":
+        # the force starts at F_x = rho_w Re_tau^2 mu_w^2 / delta_c^3 and is then held by
+        # the device-side PI controller, updated with the mass rescaling
+        ctl = W.channel_controller()
+        S.sllbm_force_reset(plan, phys.force, stream)
+        prm = dataclasses.replace(prm, force_device=1)
+    fixp = dataclasses.replace(prm, mass_fix=1, mass_ref=mref)
+
+    def one(n, a, b):
+        if fix_every and n % fix_every == 0:
+            if ctl:
+                S.sllbm_force_update(plan, a, dt=fix_every * phys.dt, stream=stream, **ctl)
+            S.sllbm_step(plan, fixp, a, b, stream)
+        else:
+            S.sllbm_step(plan, prm, a, b, stream)
+
     for n in range(warmup):
-        S.sllbm_step(plan, fixp if fix_every and n % fix_every == 0 else prm, a, b, stream)
+        one(n, a, b)
         a, b = b, a
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -169,15 +185,21 @@ def tensor_case_leg(case, prec, steps, warmup):
     S.sllbm_plan_profile(plan, True)
     t0.record(stream)
     for n in range(steps):
-        S.sllbm_step(plan, fixp if fix_every and n % fix_every == 0 else prm, a, b, stream)
+        one(n, a, b)
         a, b = b, a
     t1.record(stream)
     torch.cuda.synchronize()
     prof = S.sllbm_plan_profile_read(plan)
     S.sllbm_plan_profile(plan, False)
     tot = S.sllbm_moments(plan, prm, a, totals=True)
+    extra = {}
+    if ctl:
+        st = S.sllbm_force_read(plan, stream)
+        extra["force_control"] = {"force_x": float(st["force"][0]), "force_x0": float(phys.force[0]),
+                                  "mean_momentum": float(st["mean_momentum"]), "target": ctl["target"],
+                                  "updates": st["updates"]}
     r = summarize(prof, t0.elapsed_time(t1), 0.0, steps, N * Q, BYTES_PER_UPDATE[prec],
-                  finite=all(math.isfinite(x) for x in tot), N=N, Q=Q)
+                  finite=all(math.isfinite(x) for x in tot), N=N, Q=Q, **extra)
     del a, b
     torch.cuda.empty_cache()
     return r
@@ -510,12 +532,12 @@ def main():
                       "roofline": roofline(v), "finite": v["finite"]} for prec, v in og.items()}}
     names = {"c1r": "2D periodic shear wave, 1024^2 cells p=4 GLL (16.8M nodes), D2V25",
              "c4": "3D supersonic channel Ma_b 1.5 Re_b 3000, 128x96x64 cells p=2 (6.3M nodes), D3V125, "
-                   "isothermal walls, forcing, mass rescaling every 10 steps"}
+                   "isothermal walls, forcing held by the PI force controller and mass rescaling, both every 10 steps"}
     for key, v in extra.items():
         case, prec = key.split("_")
         out[key] = {"workload": names[case], "dtype": prec, "value": round(v["gqups"], 4), "unit": "GQUPS",
                     "ms_per_step": round(v["ms_per_step"], 4), "roofline": roofline(v), "kernels": v["kernels"],
-                    "finite": v["finite"]}
+                    "finite": v["finite"], **({"force_control": v["force_control"]} if "force_control" in v else {})}
     if lrn:
         out["learned"] = lrn
     if cal:

@@ -176,6 +176,8 @@ typedef struct {
   double force[3];     /* body force per unit volume, Kupershtokh exact difference (Sec. 4.3) */
   int mass_fix;        /* 1: scale all populations by mass_ref/M before streaming (Sec. 4.3) */
   double mass_ref;
+  int force_device;    /* 1: the force is the plan's controlled device value (sllbm_force_reset,
+                          sllbm_force_update) and force[] is ignored; EINVAL before a reset */
 } sllbm_params;
 
 /* Populations in equilibrium with nodal fields: f = f^eq(rho,u,T), g = g^eq.
@@ -185,6 +187,29 @@ int sllbm_init_equilibrium(sllbm_plan p, const sllbm_params *prm, const double *
 
 /* One time step: pop_out <- collide(stream(pop_in)).  Both hold post-collision states. */
 int sllbm_step(sllbm_plan p, const sllbm_params *prm, const void *pop_in, void *pop_out, void *stream);
+
+/* Force controller of the driven channel (Sec. 4.3: the streamwise force starts from an
+ * estimate and is then adjusted by a PI controller that holds the mean momentum).  The
+ * force lives in plan-owned device memory, so a controlled run never waits for the host:
+ *   e = target - M_axis / V,   I <- I + e dt,   F_axis = F0_axis + kp e + ki I,
+ * with M_axis = sum_k V_k sum_i zeta_i,axis f_i(k) and V = sum_k V_k (nodal quadrature
+ * volumes) of the populations passed to the update. */
+typedef struct {
+  int axis;            /* force component controlled, 0 .. dim-1 */
+  double target;       /* target mean momentum density (the bulk rho u of the axis) */
+  double kp, ki;       /* proportional and integral gains (finite; 0 disables a term) */
+  double dt;           /* time since the previous update, >= 0: the integral adds e dt */
+} sllbm_force_ctl;
+/* Sets the plan's device force and F0 to force0 (host [3]; components beyond dim are
+ * taken as 0) and clears the integral.  Enqueued on `stream`; no synchronisation. */
+int sllbm_force_reset(sllbm_plan p, const double *force0, void *stream);
+/* Measures the mean momentum of pop (device, plan precision, step layout) and applies
+ * the controller law on the device.  Steps enqueued after it on the same stream with
+ * force_device = 1 use the new force.  EINVAL before sllbm_force_reset. */
+int sllbm_force_update(sllbm_plan p, const sllbm_force_ctl *c, const void *pop, void *stream);
+/* Synchronises the stream and writes the controller state to host [7]: force[3],
+ * integral I, last error e, last mean momentum, number of updates since the reset. */
+int sllbm_force_read(sllbm_plan p, double *state_host, void *stream);
 
 /* Nodal rho, u ([dim][N]), T of a population set (eq:density, eq:momentum, energy display
  * read as total energy), each output optional (NULL), device doubles.  If totals_host

@@ -289,6 +289,42 @@ class TensorOracle:
         return mass, mom, energy
 
 
+    def set_force(self, force):
+        """Body force of the following steps (Kupershtokh forcing, Sec. 4.3)."""
+        f = list(force) + [0.0] * 3
+        for a in range(3):
+            self._s.force[a] = f[a] if a < self.dim else 0.0
+
+
+class ForceController:
+    """The driven channel's force controller (Sec. 4.3): the streamwise force starts at
+    force0 and a PI law adjusts it to hold the mean momentum density at `target`.  Its
+    discrete form (the paper gives none): at each update, with the mean momentum density
+    m = sum_k V_k j_axis(k) / sum_k V_k over the nodal quadrature volumes,
+        e = target - m,   I <- I + e dt,   F_axis = force0_axis + kp e + ki I.
+    The new force is handed to the oracle for the steps that follow."""
+
+    def __init__(self, oracle, force0, axis, target, kp, ki):
+        self.o = oracle
+        self.force0 = np.zeros(3)
+        self.force0[:len(force0)] = force0
+        self.force = self.force0.copy()
+        self.axis, self.target, self.kp, self.ki = int(axis), float(target), float(kp), float(ki)
+        self.integral = 0.0
+        self.error = 0.0
+        self.mean = 0.0
+        oracle.set_force(self.force)
+
+    def update(self, pop, dt):
+        _, mom, _ = self.o.totals(pop)
+        self.mean = mom[self.axis] / float(np.sum(self.o.node_vol))
+        self.error = self.target - self.mean
+        self.integral += self.error * dt
+        self.force[self.axis] = self.force0[self.axis] + self.kp * self.error + self.ki * self.integral
+        self.o.set_force(self.force)
+        return self.force.copy()
+
+
 def equilibrium(dim: int, rho: float, u, T: float, gamma: float = 1.4, T0: float = 1.0, n_gh: int = 5):
     """f^eq and g^eq of one state for every velocity of the D{dim}V{n^dim} set."""
     zeta, w, _ = velocity_set(dim, n_gh, T0)

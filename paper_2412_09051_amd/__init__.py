@@ -78,13 +78,19 @@ class sllbm_params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("relax_mode", ctypes.c_int), ("tau_bar", ctypes.c_double),
                 ("mu_ref", ctypes.c_double), ("T_ref", ctypes.c_double), ("mu_exp", ctypes.c_double),
                 ("Pr", ctypes.c_double), ("force", ctypes.c_double * 3), ("mass_fix", ctypes.c_int),
-                ("mass_ref", ctypes.c_double)]
+                ("mass_ref", ctypes.c_double), ("force_device", ctypes.c_int)]
+
+
+class sllbm_force_ctl(ctypes.Structure):
+    _fields_ = [("axis", ctypes.c_int), ("target", ctypes.c_double), ("kp", ctypes.c_double),
+                ("ki", ctypes.c_double), ("dt", ctypes.c_double)]
 
 
 _lib.sllbm_last_error.restype = ctypes.c_char_p
 for _name in ("sllbm_mesh_build", "sllbm_mesh_nodes", "sllbm_mesh_volumes", "sllbm_velset_gauss_hermite",
               "sllbm_interp_plan", "sllbm_plan_info", "sllbm_plan_select_kernel", "sllbm_init_equilibrium",
-              "sllbm_step", "sllbm_moments", "sllbm_plan_profile", "sllbm_plan_profile_read"):
+              "sllbm_step", "sllbm_moments", "sllbm_plan_profile", "sllbm_plan_profile_read",
+              "sllbm_force_reset", "sllbm_force_update", "sllbm_force_read"):
     getattr(_lib, _name).restype = ctypes.c_int
 _lib.sllbm_mesh_destroy.restype = None
 _lib.sllbm_plan_destroy.restype = None
@@ -152,6 +158,7 @@ class Params:
     force: Sequence[float] = (0.0, 0.0, 0.0)
     mass_fix: int = 0
     mass_ref: float = 0.0
+    force_device: int = 0
 
     def c(self):
         p = sllbm_params()
@@ -161,6 +168,7 @@ class Params:
         for a in range(3):
             p.force[a] = f[a]
         p.mass_fix, p.mass_ref = int(self.mass_fix), float(self.mass_ref)
+        p.force_device = int(self.force_device)
         return p
 
     @staticmethod
@@ -344,6 +352,24 @@ def sllbm_moments(plan: Plan, params: Params, pop, rho=None, u=None, T=None, tot
     return tot
 
 
+def sllbm_force_reset(plan: Plan, force0, stream=None):
+    f = np.zeros(3)
+    f[:len(force0)] = force0
+    _check(_lib.sllbm_force_reset(plan.handle, _np_ptr(f), _stream(stream)), "sllbm_force_reset")
+
+
+def sllbm_force_update(plan: Plan, pop, axis: int, target: float, kp: float, ki: float, dt: float, stream=None):
+    c = sllbm_force_ctl(axis=int(axis), target=float(target), kp=float(kp), ki=float(ki), dt=float(dt))
+    _check(_lib.sllbm_force_update(plan.handle, ctypes.byref(c), _dev_ptr(pop, _pop_dtype(plan), 2 * plan.Q * plan.N,
+                                                                         "pop"), _stream(stream)), "sllbm_force_update")
+
+
+def sllbm_force_read(plan: Plan, stream=None) -> dict:
+    h = np.zeros(7)
+    _check(_lib.sllbm_force_read(plan.handle, _np_ptr(h), _stream(stream)), "sllbm_force_read")
+    return {"force": h[:3].copy(), "integral": h[3], "error": h[4], "mean_momentum": h[5], "updates": int(h[6])}
+
+
 # ------------------------------------------------------------------ learned correction
 
 for _name in ("sllbm_mlp_create", "sllbm_mlp_num_params", "sllbm_mlp_get_params", "sllbm_mlp_set_params",
@@ -462,7 +488,7 @@ def sllbm_mlp_train_step(m: Mlp, x, t, lr: float, want_loss: bool = True, stream
 
 __all__ = ["sllbm_velset_gauss_hermite", "sllbm_mesh_build", "sllbm_mesh_nodes", "sllbm_mesh_volumes",
            "sllbm_interp_plan", "sllbm_plan_info", "sllbm_plan_select_kernel", "sllbm_init_equilibrium", "sllbm_step", "sllbm_moments",
-           "Params", "Plan", "Mesh", "SllbmError", "SLLBM_F64", "SLLBM_F32", "LIB_PATH",
+           "sllbm_force_reset", "sllbm_force_update", "sllbm_force_read", "Params", "Plan", "Mesh", "SllbmError", "SLLBM_F64", "SLLBM_F32", "LIB_PATH",
            "Mlp", "sllbm_mlp_create", "sllbm_mlp_get_params", "sllbm_mlp_set_params", "sllbm_features",
            "sllbm_mlp_forward", "sllbm_mlp_correct", "sllbm_learned_targets", "sllbm_restrict", "sllbm_mlp_gradient",
            "sllbm_mlp_train_step", "n_features"]

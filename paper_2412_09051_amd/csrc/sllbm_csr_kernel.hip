@@ -66,10 +66,7 @@ __device__ __forceinline__ NodeRelax node_relax(const StepArgs &sa, double rho, 
   s.eq = eq_prepare(rho, u0, u1, 0.0, Tn, sa, 2);
   if (s.thermal) s.eqp = eq_prepare(rho, u0, u1, 0.0, s.Tpre, sa, 2);
   s.force = sa.has_force;
-  if (s.force) {
-    double r = sa.dt / rho;
-    s.eqf = eq_prepare(rho, u0 + sa.force[0] * r, u1 + sa.force[1] * r, 0.0, Tn, sa, 2);
-  }
+  if (s.force) s.eqf = eq_forced(rho, u0, u1, 0.0, Tn, sa, 2);
   s.itau = 0.0;
   if (sa.relax_mode == 0) s.itau = 1.0 / sa.tau_bar;
   if (sa.relax_mode == 1) s.itau = 1.0 / (sa.mu_ref * pow(Tn / sa.T_ref, sa.mu_exp) / (rho * Tn * sa.dt) + 0.5);

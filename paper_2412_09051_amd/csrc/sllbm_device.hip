@@ -49,7 +49,9 @@ int check_params(const sllbm_plan_s *P, const sllbm_params *prm) {
   if (prm->mass_fix && !(prm->mass_ref > 0)) return fail(SLLBM_EINVAL, "mass_fix needs mass_ref > 0");
   for (int a = 0; a < 3; a++)
     if (!std::isfinite(prm->force[a])) return fail(SLLBM_EINVAL, "force must be finite");
-  (void)P;
+  if (prm->force_device != 0 && prm->force_device != 1) return fail(SLLBM_EINVAL, "force_device must be 0 or 1");
+  if (prm->force_device && !P->force_ready)
+    return fail(SLLBM_EINVAL, "force_device = 1 before sllbm_force_reset set the plan's force");
   return SLLBM_OK;
 }
 
@@ -71,6 +73,11 @@ StepArgs make_args(const sllbm_plan_s *P, const sllbm_params *prm) {
   for (int d = 0; d < 3; d++) {
     a.force[d] = d < D ? prm->force[d] : 0.0;
     if (a.force[d] != 0.0) a.has_force = 1;
+  }
+  a.force_dev = nullptr;
+  if (prm->force_device) {
+    a.force_dev = P->scratch + kSlotForce;
+    a.has_force = 1;
   }
   a.scale = nullptr;
   a.inlet = P->inlet_dev;
@@ -415,6 +422,48 @@ extern "C" int sllbm_step(sllbm_plan P, const sllbm_params *prm, const void *pin
     a.scale = P->scratch + kSlotScale;
   }
   return launch_step(P, a, pin, pout, s);
+}
+
+extern "C" int sllbm_force_reset(sllbm_plan P, const double *force0, void *stream) {
+  if (!P || !force0) return fail(SLLBM_EINVAL, "force_reset: NULL argument");
+  double F[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < P->mesh.dim; a++) {
+    if (!std::isfinite(force0[a])) return fail(SLLBM_EINVAL, "force_reset: force must be finite");
+    F[a] = force0[a];
+  }
+  int rc;
+  if ((rc = require_device(P))) return rc;
+  if ((rc = launch_force_reset(P, F, (hipStream_t)stream))) return rc;
+  P->force_ready = true;
+  return SLLBM_OK;
+}
+
+extern "C" int sllbm_force_update(sllbm_plan P, const sllbm_force_ctl *c, const void *pop, void *stream) {
+  if (!P || !c) return fail(SLLBM_EINVAL, "force_update: NULL argument");
+  if (!P->force_ready) return fail(SLLBM_EINVAL, "force_update: call sllbm_force_reset first");
+  if (c->axis < 0 || c->axis >= P->mesh.dim)
+    return fail(SLLBM_EINVAL, "force_update: axis %d outside 0..%d", c->axis, P->mesh.dim - 1);
+  if (!std::isfinite(c->target) || !std::isfinite(c->kp) || !std::isfinite(c->ki) || !(c->dt >= 0) ||
+      !std::isfinite(c->dt))
+    return fail(SLLBM_EINVAL, "force_update: target, gains must be finite and dt >= 0");
+  int rc;
+  if ((rc = check_pop(P, pop, "pop"))) return rc;
+  if ((rc = require_device(P))) return rc;
+  return launch_force_update(P, c->axis, c->target, c->kp, c->ki, c->dt, pop, (hipStream_t)stream);
+}
+
+extern "C" int sllbm_force_read(sllbm_plan P, double *state_host, void *stream) {
+  if (!P || !state_host) return fail(SLLBM_EINVAL, "force_read: NULL argument");
+  if (!P->force_ready) return fail(SLLBM_EINVAL, "force_read: call sllbm_force_reset first");
+  int rc;
+  if ((rc = require_device(P))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  double h[12];
+  HIP_TRY(hipMemcpyAsync(h, P->scratch + kSlotForce, sizeof(double) * 12, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int q = 0; q < 3; q++) state_host[q] = h[q];
+  for (int q = 0; q < 4; q++) state_host[3 + q] = h[kSlotCtl - kSlotForce + q];
+  return SLLBM_OK;
 }
 
 extern "C" int sllbm_moments(sllbm_plan P, const sllbm_params *prm, const void *pop, double *rho, double *u,

@@ -38,6 +38,20 @@ __device__ __forceinline__ EqNode eq_prepare(double rho, double u0, double u1, d
   return e;
 }
 
+// Equilibrium at the forced velocity u + F dt / rho (Kupershtokh's exact difference,
+// Sec. 4.3): F is the step's constant force, or the plan's controlled device value.
+__device__ __forceinline__ EqNode eq_forced(double rho, double u0, double u1, double u2, double T,
+                                            const StepArgs &a, int D) {
+  double F0 = a.force[0], F1 = a.force[1], F2 = a.force[2];
+  if (a.force_dev) {
+    F0 = a.force_dev[0];
+    F1 = a.force_dev[1];
+    F2 = a.force_dev[2];
+  }
+  const double r = a.dt / rho;
+  return eq_prepare(rho, u0 + F0 * r, u1 + F1 * r, u2 + F2 * r, T, a, D);
+}
+
 // vel: [zeta x,y,z, xi x,y,z, |xi|^2, w] of one velocity
 __device__ __forceinline__ double eq_f(const EqNode &e, const double *vel) {
   double s = vel[3] * e.ux + vel[4] * e.uy + vel[5] * e.uz;

@@ -161,6 +161,7 @@ struct sllbm_plan_s {
   double *scratch = nullptr;    // device scratch: reduction partials + scalars
   double *nstate = nullptr;     // tiled kernel: node state between its two launches, [6][N]
   int64_t scratch_len = 0;      // doubles
+  bool force_ready = false;     // the controller's device force has been set (sllbm_force_reset)
   // host copies kept for the GPU-free info path
   std::vector<double> vol;
   sllbm::Profiler prof;

@@ -12,7 +12,10 @@ constexpr int kRedWidth = 8;       // doubles per block partial: mass, momentum[
 constexpr int kScratchHead = 64;   // scratch doubles before the block partials
 constexpr int kSlotTotals = 0;     // [kRedWidth] final totals
 constexpr int kSlotScale = 16;     // mass-rescale factor mass_ref / M
-constexpr int kSlotMass = 24;      // final mass of the rescale reduction
+constexpr int kSlotMass = 24;      // final [mass, momentum[3], volume] of the f-only reduction
+constexpr int kSlotForce = 32;     // controlled body force [3] (sllbm_force_reset / _update)
+constexpr int kSlotForce0 = 36;    // force at the last reset [3]
+constexpr int kSlotCtl = 40;       // controller: integral, error, mean momentum, updates
 
 // Step parameters as the kernels see them (all derived on the host per call).
 struct StepArgs {
@@ -22,6 +25,7 @@ struct StepArgs {
   double tau_bar, mu_ref, T_ref, mu_exp;
   double force[3];
   int has_force;
+  const double *force_dev;         // device force [3] of the plan's controller, or nullptr
   const double *scale;             // device mass-rescale factor, or nullptr
   const double *inlet;             // device [n_bc][5] inlet states
 };
@@ -49,6 +53,9 @@ int launch_step(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout,
 int launch_moments(sllbm_plan_s *P, const StepArgs &a, const void *pop, double *rho, double *u, double *T,
                    bool totals, hipStream_t s);
 int launch_mass_scale(sllbm_plan_s *P, const void *pop, double mass_ref, hipStream_t s);
+int launch_force_reset(sllbm_plan_s *P, const double *force0, hipStream_t s);
+int launch_force_update(sllbm_plan_s *P, int axis, double target, double kp, double ki, double dt, const void *pop,
+                        hipStream_t s);
 
 // Per-kernel timing: while the plan's profiler is on, a ProfScope around a launch
 // records HIP events before and after it on the launch stream.

@@ -138,10 +138,7 @@ __global__ void __launch_bounds__(kBlock) k_step_gather(const DevTensorPlan pl, 
   EqNode eqp;
   if (thermal) eqp = eq_prepare(rho, u0, u1, u2, Tpre, sa, D);
   EqNode eqf;
-  if (sa.has_force) {
-    double r = sa.dt / rho;
-    eqf = eq_prepare(rho, u0 + sa.force[0] * r, u1 + sa.force[1] * r, u2 + sa.force[2] * r, Tn, sa, D);
-  }
+  if (sa.has_force) eqf = eq_forced(rho, u0, u1, u2, Tn, sa, D);
   double inv_tau = 0.0;
   if (sa.relax_mode == 0) inv_tau = 1.0 / sa.tau_bar;
   if (sa.relax_mode == 1) {
@@ -235,19 +232,59 @@ __global__ void __launch_bounds__(kBlock) k_moments(int64_t N, int Q, int D, con
   if (do_part) block_partial(v, part);
 }
 
+// f-only totals of a population set: mass, momentum[3] (both from f alone, eq:density and
+// eq:momentum) and the volume, weighted by the nodal quadrature volumes.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_mass_partial(int64_t N, int Q, const double *__restrict__ vol,
-                                                          const T *__restrict__ pop, double *__restrict__ part) {
+__global__ void __launch_bounds__(kBlock) k_mass_partial(int64_t N, int Q, int D, const double *__restrict__ vel,
+                                                          const double *__restrict__ vol, const T *__restrict__ pop,
+                                                          double *__restrict__ part) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   double v[kRedWidth];
 #pragma unroll
   for (int q = 0; q < kRedWidth; q++) v[q] = 0.0;
   if (k < N) {
-    double r = 0;
-    for (int i = 0; i < Q; i++) r += (double)pop[(size_t)i * N + k];
-    v[0] = vol[k] * r;
+    double r = 0, j0 = 0, j1 = 0, j2 = 0;
+    for (int i = 0; i < Q; i++) {
+      const double f = (double)pop[(size_t)i * N + k];
+      const double *vi = vel + 8 * i;
+      r += f;
+      j0 += vi[0] * f;
+      j1 += vi[1] * f;
+      j2 += vi[2] * f;
+    }
+    const double V = vol[k];
+    v[0] = V * r;
+    v[1] = V * j0;
+    v[2] = V * j1;
+    v[3] = D == 3 ? V * j2 : 0.0;
+    v[4] = V;
   }
   block_partial(v, part);
+}
+
+// Force controller (Sec. 4.3: the force is adjusted by a PI controller that holds the
+// mean momentum): e = target - M_a / V, I += e dt, F_a = F0_a + kp e + ki I.  One thread.
+__global__ void k_force_update(const double *__restrict__ tot, double *__restrict__ force,
+                               const double *__restrict__ force0, double *__restrict__ ctl, int axis, double target,
+                               double kp, double ki, double dt) {
+  if (threadIdx.x != 0) return;
+  const double mean = tot[1 + axis] / tot[4];
+  const double e = target - mean;
+  const double I = ctl[0] + e * dt;
+  force[axis] = force0[axis] + kp * e + ki * I;
+  ctl[0] = I;
+  ctl[1] = e;
+  ctl[2] = mean;
+  ctl[3] += 1.0;
+}
+
+__global__ void k_force_reset(double *__restrict__ force, double *__restrict__ force0, double *__restrict__ ctl,
+                              double F0, double F1, double F2) {
+  if (threadIdx.x != 0) return;
+  force[0] = force0[0] = F0;
+  force[1] = force0[1] = F1;
+  force[2] = force0[2] = F2;
+  ctl[0] = ctl[1] = ctl[2] = ctl[3] = 0.0;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -345,20 +382,49 @@ int launch_moments(sllbm_plan_s *Pl, const StepArgs &a, const void *pop, double 
   return SLLBM_OK;
 }
 
-int launch_mass_scale(sllbm_plan_s *Pl, const void *pop, double mass_ref, hipStream_t s) {
+namespace {
+// f-only totals of pop into scratch[kSlotMass..]; mode 1 also writes the rescale factor
+int launch_f_totals(sllbm_plan_s *Pl, const void *pop, int mode, double mass_ref, hipStream_t s) {
   int64_t N = Pl->mesh.n_nodes, nb = nblocks(N);
+  const double *vel = Pl->kernel == 0 ? Pl->tp.vel : Pl->cp.vel;
   const double *vol = Pl->kernel == 0 ? Pl->tp.vol : Pl->cp.vol;
   double *part = Pl->scratch + kScratchHead;
-  ProfScope ps(Pl, "k_mass_scale", s);
+  const int Q = Pl->vel.Q, D = Pl->mesh.dim;
   if (Pl->prec == SLLBM_F32)
-    hipLaunchKernelGGL(k_mass_partial<float>, dim3((unsigned)nb), dim3(kBlock), 0, s, N, Pl->vel.Q, vol,
+    hipLaunchKernelGGL(k_mass_partial<float>, dim3((unsigned)nb), dim3(kBlock), 0, s, N, Q, D, vel, vol,
                        (const float *)pop, part);
   else
-    hipLaunchKernelGGL(k_mass_partial<double>, dim3((unsigned)nb), dim3(kBlock), 0, s, N, Pl->vel.Q, vol,
+    hipLaunchKernelGGL(k_mass_partial<double>, dim3((unsigned)nb), dim3(kBlock), 0, s, N, Q, D, vel, vol,
                        (const double *)pop, part);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, (const double *)part, nb,
-                     Pl->scratch + kSlotMass, 1, mass_ref, Pl->scratch + kSlotScale);
+                     Pl->scratch + kSlotMass, mode, mass_ref, Pl->scratch + kSlotScale);
+  HIP_TRY(hipGetLastError());
+  return SLLBM_OK;
+}
+}  // namespace
+
+int launch_mass_scale(sllbm_plan_s *Pl, const void *pop, double mass_ref, hipStream_t s) {
+  ProfScope ps(Pl, "k_mass_scale", s);
+  return launch_f_totals(Pl, pop, 1, mass_ref, s);
+}
+
+int launch_force_reset(sllbm_plan_s *Pl, const double *force0, hipStream_t s) {
+  double *sc = Pl->scratch;
+  hipLaunchKernelGGL(k_force_reset, dim3(1), dim3(64), 0, s, sc + kSlotForce, sc + kSlotForce0, sc + kSlotCtl,
+                     force0[0], force0[1], force0[2]);
+  HIP_TRY(hipGetLastError());
+  return SLLBM_OK;
+}
+
+int launch_force_update(sllbm_plan_s *Pl, int axis, double target, double kp, double ki, double dt, const void *pop,
+                        hipStream_t s) {
+  ProfScope ps(Pl, "k_force_update", s);
+  int rc = launch_f_totals(Pl, pop, 0, 0.0, s);
+  if (rc) return rc;
+  double *sc = Pl->scratch;
+  hipLaunchKernelGGL(k_force_update, dim3(1), dim3(64), 0, s, (const double *)(sc + kSlotMass), sc + kSlotForce,
+                     (const double *)(sc + kSlotForce0), sc + kSlotCtl, axis, target, kp, ki, dt);
   HIP_TRY(hipGetLastError());
   return SLLBM_OK;
 }

@@ -417,9 +417,7 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
           fo = f - (f - fe) * itau[m];
           go = g - (g - gT * fe) * itau[m];
           if (sa.has_force) {
-            double r = sa.dt / r_m;
-            EqNode ef = eq_prepare(r_m, nu0[m] + sa.force[0] * r, nu1[m] + sa.force[1] * r,
-                                   nu2[m] + sa.force[2] * r, Tn[m], sa, D);
+            EqNode ef = eq_forced(r_m, nu0[m], nu1[m], nu2[m], Tn[m], sa, D);
             double df = eq_f(ef, vi) - fe;
             fo += df;
             go += gT * df;
@@ -455,10 +453,7 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
   const double Tn = nstate[4 * N + k], itau = nstate[5 * N + k];
   const EqNode e = eq_prepare(rho, u0, u1, u2, Tn, sa, D);
   EqNode ef = e;
-  if (sa.has_force) {
-    double r = sa.dt / rho;
-    ef = eq_prepare(rho, u0 + sa.force[0] * r, u1 + sa.force[1] * r, u2 + sa.force[2] * r, Tn, sa, D);
-  }
+  if (sa.has_force) ef = eq_forced(rho, u0, u1, u2, Tn, sa, D);
   const double gT = Tn * sa.gbase;
   for (int i = 0; i < Q; i++) {
     const double *vi = pl.vel + 8 * i;

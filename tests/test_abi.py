@@ -187,6 +187,17 @@ def test_step_argument_validation_before_any_launch():
     assert lib.sllbm_step(None, ctypes.byref(prm.c()), _fake_ptr(a), _fake_ptr(b), None) == S.SLLBM_EINVAL
     if not S.sllbm_plan_info(plan)["has_device"]:
         assert lib.sllbm_step(plan.handle, ctypes.byref(prm.c()), _fake_ptr(a), _fake_ptr(b), None) == S.SLLBM_EHIP
+    # the controlled force must be set before a step or an update uses it
+    fd = S.Params.from_physics(phys, force_device=1)
+    assert lib.sllbm_step(plan.handle, ctypes.byref(fd.c()), _fake_ptr(a), _fake_ptr(b), None) == S.SLLBM_EINVAL
+    assert "sllbm_force_reset" in lib.sllbm_last_error().decode()
+    ctl = S.sllbm_force_ctl(axis=0, target=1.0, kp=1.0, ki=0.0, dt=0.1)
+    assert lib.sllbm_force_update(plan.handle, ctypes.byref(ctl), _fake_ptr(a), None) == S.SLLBM_EINVAL
+    state = (ctypes.c_double * 7)()
+    assert lib.sllbm_force_read(plan.handle, state, None) == S.SLLBM_EINVAL
+    assert lib.sllbm_force_reset(plan.handle, None, None) == S.SLLBM_EINVAL
+    bad_fd = S.Params.from_physics(phys, force_device=2)
+    assert lib.sllbm_step(plan.handle, ctypes.byref(bad_fd.c()), _fake_ptr(a), _fake_ptr(b), None) == S.SLLBM_EINVAL
 
 
 def test_tiled_kernel_eligibility_follows_the_halo_rule():

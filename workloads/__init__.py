@@ -191,6 +191,14 @@ def channel_case(ncell=(128, 96, 64), p: int = 2, nodes: str = "gll", Ma_b: floa
     return mesh, phys
 
 
+def channel_controller(Ma_b: float = 1.5, T_wall: float = 1.0, rho_b: float = 1.0, tau_c: float = 1.0):
+    """Inputs of the channel's force controller: hold the mean streamwise momentum density
+    at rho_b u_b; gains of a critically damped loop with time constant tau_c
+    (kp = 2 / tau_c, ki = 1 / tau_c^2), since the paper gives none."""
+    u_b = Ma_b * math.sqrt(1.4 * T_wall)
+    return {"axis": 0, "target": rho_b * u_b, "kp": 2.0 / tau_c, "ki": 1.0 / tau_c ** 2}
+
+
 def channel_fields(xyz: np.ndarray, Ma_b: float = 1.5, T_wall: float = 1.0, amp: float = 0.05,
                    kmax: int = 4, seed: int = 4, box=(4.0 * math.pi, 2.0, 2.0 * math.pi)):
     """Poiseuille profile 1.5 u_b (1 - (y-1)^2) plus random-phase modes scaled by a parabola."""
