@@ -31,8 +31,10 @@ PEAK_HBM_GBS = 8000.0
 BYTES_PER_UPDATE = {"f64": 32, "f32": 16}
 
 
-def curv_bytes_per_update(prec, p):
-    return BYTES_PER_UPDATE[prec] + (p + 1) ** 2 * (8 if prec == "f64" else 4) + 4
+def curv_bytes_per_update(prec):
+    """f and g read and written, plus the plan row of the (node, velocity) pair: its cell
+    and source (two int32) and the departure point's reference coordinates (two doubles)."""
+    return BYTES_PER_UPDATE[prec] + 8 + 16
 
 
 def parse():
@@ -244,9 +246,9 @@ def ogrid_leg(prec, steps, warmup):
     a, total_ms, wall, prof = timed_steps(S, plan, prm, a, b, steps, warmup, torch)
     tot = S.sllbm_moments(plan, prm, a, totals=True)
     torch.cuda.synchronize()
-    return summarize(prof, total_ms, wall, steps, N * Q, curv_bytes_per_update(prec, mesh.p),
+    return summarize(prof, total_ms, wall, steps, N * Q, curv_bytes_per_update(prec),
                      finite=all(math.isfinite(x) for x in tot), N=N, Q=Q, plan_build_s=plan_s,
-                     bpu=curv_bytes_per_update(prec, mesh.p))
+                     bpu=curv_bytes_per_update(prec))
 
 
 MIX_BOX_CELLS = (2.5, 2.75, 1.5)      # coarse cell size per axis in initial momentum thicknesses

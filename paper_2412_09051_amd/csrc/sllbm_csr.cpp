@@ -468,7 +468,7 @@ int build_csr_tables(const Mesh &m, const VelSet &v, double dt, HostTables &t, i
   const int64_t N = m.n_nodes;
   t.row_cell.assign((size_t)Q * N, -1);
   t.row_src.assign((size_t)Q * N, 0);
-  t.row_w.assign((size_t)Q * npc * N, 0.0);
+  t.row_xi.assign((size_t)Q * 2 * N, 0.0);
   t.node_Tw.assign(N, std::numeric_limits<double>::quiet_NaN());
   std::atomic<int> status{SLLBM_OK};
   std::atomic<int64_t> bad_k{-1}, bad_i{-1}, exc{0};
@@ -519,14 +519,10 @@ int build_csr_tables(const Mesh &m, const VelSet &v, double dt, HostTables &t, i
             return;
           }
         }
-        double lx[kMaxP + 1], ly[kMaxP + 1];
-        lagrange_weights(m.xref, r[0], lx);
-        lagrange_weights(m.xref, r[1], ly);
         t.row_cell[(size_t)i * N + k] = (int32_t)c;
         t.row_src[(size_t)i * N + k] = src;
-        for (int jy = 0; jy <= m.p; jy++)
-          for (int jx = 0; jx <= m.p; jx++)
-            t.row_w[((size_t)i * npc + jx + (m.p + 1) * jy) * N + k] = lx[jx] * ly[jy];
+        t.row_xi[((size_t)i * 2) * N + k] = r[0];
+        t.row_xi[((size_t)i * 2 + 1) * N + k] = r[1];
       }
     }
     exc += local_exc;

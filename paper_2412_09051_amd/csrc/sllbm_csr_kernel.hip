@@ -1,9 +1,10 @@
 // CSR step kernel for curvilinear meshes (gfx950): one node per lane; every
 // (velocity, node) row names the cell holding the departure point, the source
-// population (bounce-back: the opposite one) and the (p+1)^2 interpolation weights
-// (eq:intf), or an inlet state (Sec. 3.3.1).  For Q = 25 (D2V25) the 50 streamed
-// values stay in registers between the moments and the relaxation, so every row's
-// weights are read once per step.
+// population (bounce-back: the opposite one) and the departure point's reference
+// coordinates in that cell, from which the kernel evaluates the (p+1)^2 weights of
+// eq:intf, or an inlet state (Sec. 3.3.1).  Interpolation accumulates in FP64 for both
+// storage precisions.  For Q = 25 (D2V25) the 50 streamed values stay in registers
+// between the moments and the relaxation, so every row is read once per step.
 #include <hip/hip_runtime.h>
 
 #include "sllbm_device_common.h"
@@ -11,13 +12,23 @@
 
 namespace sllbm {
 
-template <typename T> struct CsrW;
-template <> struct CsrW<double> {
-  __device__ static const double *get(const DevCsrPlan &p) { return p.row_w64; }
-};
-template <> struct CsrW<float> {
-  __device__ static const float *get(const DevCsrPlan &p) { return p.row_w32; }
-};
+// Lagrange basis of the cell's support points at t (eq:intf): l_a = lam_a prod_{b != a} (t - x_b),
+// by prefix and suffix products (no division; exact 0/1 at a support point).
+template <int P>
+__device__ __forceinline__ void basis_at(const DevCsrPlan &pl, double t, double (&l)[P + 1]) {
+  double d[P + 1], pre[P + 1];
+#pragma unroll
+  for (int b = 0; b <= P; b++) d[b] = t - pl.xref[b];
+  pre[0] = 1.0;
+#pragma unroll
+  for (int a = 1; a <= P; a++) pre[a] = pre[a - 1] * d[a - 1];
+  double suf = 1.0;
+#pragma unroll
+  for (int a = P; a >= 0; a--) {
+    l[a] = pl.lam[a] * pre[a] * suf;
+    suf *= d[a];
+  }
+}
 
 template <typename T, int P>
 __device__ __forceinline__ void stream_csr(const DevCsrPlan &pl, const StepArgs &sa, const T *__restrict__ pin,
@@ -33,20 +44,30 @@ __device__ __forceinline__ void stream_csr(const DevCsrPlan &pl, const StepArgs 
     gv = st[4] * sa.gbase * fv;
     return;
   }
+  // the (p+1)^2 weights are products of the 1D bases at the departure point's reference
+  // coordinates, evaluated here instead of being read from the plan (16 B per row
+  // instead of 8 (p+1)^2)
+  double lx[P + 1], ly[P + 1];
+  basis_at<P>(pl, pl.row_xi[(size_t)(2 * i) * N + k], lx);
+  basis_at<P>(pl, pl.row_xi[(size_t)(2 * i + 1) * N + k], ly);
   const int32_t *cn = pl.cell_nodes + (size_t)c * NPC;
   const T *F = pin + (size_t)src * N;
   const T *G = pin + ((size_t)pl.Q + src) * N;
-  const T *W = CsrW<T>::get(pl) + (size_t)i * NPC * N + k;
-  T a = 0, b = 0;
+  double a = 0, b = 0;
 #pragma unroll
-  for (int j = 0; j < NPC; j++) {
-    const T w = W[(size_t)j * N];
-    const int n = cn[j];
-    a += w * F[n];
-    b += w * G[n];
+  for (int jy = 0; jy <= P; jy++) {
+    double ax = 0, bx = 0;
+#pragma unroll
+    for (int jx = 0; jx <= P; jx++) {
+      const int n = cn[jx + (P + 1) * jy];
+      ax += lx[jx] * (double)F[n];
+      bx += lx[jx] * (double)G[n];
+    }
+    a += ly[jy] * ax;
+    b += ly[jy] * bx;
   }
-  fv = scale * (double)a;
-  gv = scale * (double)b;
+  fv = scale * a;
+  gv = scale * b;
 }
 
 // relaxation of one node given its streamed populations (thermal wall, BGK, force)

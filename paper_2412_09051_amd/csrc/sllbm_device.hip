@@ -195,6 +195,7 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
       DevAxis &ax = tp.ax[a];
       ax.N = m.N[a];
       ax.periodic = a < m.dim ? (m.periodic(a) ? 1 : 0) : 1;
+      ax.ntab = t.ntab[a];
       std::vector<float> w32(t.w[a].size());
       for (size_t r = 0; r < t.w[a].size(); r += m.p + 1) round_weights_f32(&t.w[a][r], m.p + 1, &w32[r]);
       UP(t.start[a], ax.start);
@@ -226,21 +227,13 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
     UP(cn32, cp.cell_nodes);
     UP(t.row_cell, cp.row_cell);
     UP(t.row_src, cp.row_src);
-    if (prec == SLLBM_F32) {
-      // float weights per row (strided by N in the SoA layout), sum kept at 1
-      std::vector<float> w32(t.row_w.size());
-      int64_t N = m.n_nodes;
-      double wr[kMaxP * kMaxP + 2 * kMaxP + 1];
-      float fr[kMaxP * kMaxP + 2 * kMaxP + 1];
-      for (int i = 0; i < V.Q; i++)
-        for (int64_t k = 0; k < N; k++) {
-          for (int j = 0; j < cp.npc; j++) wr[j] = t.row_w[((size_t)i * cp.npc + j) * N + k];
-          round_weights_f32(wr, cp.npc, fr);
-          for (int j = 0; j < cp.npc; j++) w32[((size_t)i * cp.npc + j) * N + k] = fr[j];
-        }
-      UP(w32, cp.row_w32);
-    } else {
-      UP(t.row_w, cp.row_w64);
+    UP(t.row_xi, cp.row_xi);
+    for (int a = 0; a <= m.p; a++) {
+      cp.xref[a] = m.xref[a];
+      double l = 1.0;
+      for (int b = 0; b <= m.p; b++)
+        if (b != a) l *= m.xref[a] - m.xref[b];
+      cp.lam[a] = 1.0 / l;
     }
     UP(t.node_Tw, cp.node_Tw);
     cp.vel = vel_d;

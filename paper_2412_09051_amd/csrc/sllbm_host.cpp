@@ -651,6 +651,14 @@ bool tile_cells(int D, int P, int c[3]) {
 
 bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]) {
   int P = m.p;
+  // the kernel holds byte offsets within a staged region's span of a population in 32 bits
+  const int64_t span = m.dim == 3 ? (int64_t)m.N[0] * m.N[1] * (c[2] * P + P + 1)
+                                  : (int64_t)m.N[0] * (c[1] * P + P + 1);
+  if (span * (int64_t)sizeof(double) >= ((int64_t)1 << 31)) return false;
+  // the tile keeps the tables of the regular departure points in LDS (boundary entries
+  // may add more tables; the gather kernel reads those)
+  for (size_t q = 0; q < t.tab_reg.size(); q++)
+    if (t.tab_reg[q] >= kTileTabs) return false;
   for (int a = 0; a < m.dim; a++) {
     int T = c[a] * P, N = m.N[a];
     if (m.periodic(a) && N <= T + P) return false;

@@ -78,6 +78,7 @@ struct ExcEntry {
 struct DevAxis {
   int N;
   int periodic;
+  int ntab;               // interpolation tables (distinct displacements along the axis)
   const int32_t *start;   // [ntab][N]
   const double *w64;      // [ntab][N][p+1]
   const float *w32;       // same, single precision
@@ -110,8 +111,9 @@ struct DevCsrPlan {
   const int32_t *cell_nodes;// [n_cells][npc]
   const int32_t *row_cell;  // [Q][N] cell of the departure point, -1 inlet
   const int32_t *row_src;   // [Q][N] source velocity, or bc index for inlet rows
-  const double *row_w64;    // [Q][npc][N] (SoA over nodes: coalesced per weight)
-  const float *row_w32;
+  const double *row_xi;     // [Q][2][N] reference coordinates (xi, eta) of the departure point in its cell
+  double xref[kMaxP + 1];   // support points on [-1, 1]
+  double lam[kMaxP + 1];    // 1 / prod_{b != a} (xref_a - xref_b)
   const double *node_Tw;    // [N] thermal-wall temperature, NaN = none
   const double *vel;
   const double *vol;
@@ -188,7 +190,7 @@ struct HostTables {
   std::vector<double> face_Tw[2];
   // csr
   std::vector<int32_t> row_cell, row_src;
-  std::vector<double> row_w;
+  std::vector<double> row_xi;       // [Q][2][N]
   std::vector<double> node_Tw;
   // common
   std::vector<double> vel;          // [Q][8]

@@ -30,12 +30,23 @@ struct StepArgs {
   const double *inlet;             // device [n_bc][5] inlet states
 };
 
+// The tiled kernel keeps the weight rows of the interpolation tables of the regular
+// departure points in LDS: their table ids (one per distinct velocity component along
+// an axis) must be below this bound.
+constexpr int kTileTabs = 5;
+
 // Cell-aligned tile (cells per axis) of the LDS-tiled step kernel for (dim, order).
 template <int D, int P> struct TileShape;
 template <> struct TileShape<2, 2> { static constexpr int CX = 8, CY = 8, CZ = 1; };
 template <> struct TileShape<2, 3> { static constexpr int CX = 8, CY = 4, CZ = 1; };
 template <> struct TileShape<2, 4> { static constexpr int CX = 8, CY = 4, CZ = 1; };
-template <> struct TileShape<3, 2> { static constexpr int CX = 4, CY = 4, CZ = 4; };
+#ifndef TILE_3_2
+#define TILE_3_2 4, 4, 4
+#endif
+template <> struct TileShape<3, 2> {
+  static constexpr int c[3] = {TILE_3_2};
+  static constexpr int CX = c[0], CY = c[1], CZ = c[2];
+};
 #ifndef TILE_3_3
 #define TILE_3_3 4, 4, 2
 #endif

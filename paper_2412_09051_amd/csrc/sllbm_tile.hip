@@ -3,15 +3,15 @@
 // One workgroup owns a cell-aligned tile of TX x TY x TZ nodes.  For every velocity i
 // it stages the departure region of f_i and g_i (the tile shifted by the velocity's
 // displacement, at most one cell of halo on one side per axis) from HBM into LDS, then
-// applies the separable interpolant of eq:intf as three 1D passes (x, y, z) in LDS:
-// the cost per streamed value is 3(p+1) multiply-adds instead of (p+1)^3 gathers.
+// applies the separable interpolant of eq:intf as an x-pass over the staged rows and,
+// per owned node, the y and z contractions of the x-passed values: (p+1) + (p+1)^2
+// multiply-adds per streamed value instead of (p+1)^3 gathers.
 // Two launches per step: the first streams every velocity, stores the streamed f_i, g_i
 // and reduces their conserved moments per node into a small node-state array (6 doubles
 // per node); the second relaxes the stored populations in place, one node per lane.
-// (Built with TILE_STORE=0, the second launch re-streams instead of reading the stored
-// values: half the HBM writes, twice the interpolation.)  Nodes in the boundary layers of a bounded
-// face (where some departure point leaves the domain, and where the isothermal-wall
-// correction acts) are left to the per-node gather kernel, launched on those slabs.
+// Nodes in the boundary layers of a bounded face (where some departure point leaves the
+// domain, and where the isothermal-wall correction acts) are left to the per-node gather
+// kernel, launched on those slabs.
 #include <hip/hip_runtime.h>
 
 #include "sllbm_device_common.h"
@@ -22,16 +22,29 @@ namespace sllbm {
 #ifndef TILE_WPE
 #define TILE_WPE 4
 #endif
-#ifndef TILE_WPE2
-#define TILE_WPE2 2
+#ifndef TILE_BS3
+#define TILE_BS3 512
 #endif
-#ifndef PASS_UNROLL
-#define PASS_UNROLL 1
+#ifndef RELAX_BATCH
+#define RELAX_BATCH 5
 #endif
-// 1: the moments launch also stores the streamed populations and a per-node kernel
-// relaxes them in place; 0: the second launch re-streams them instead
-#ifndef TILE_STORE
-#define TILE_STORE 1
+// 3D: 1 = the y and z contractions per owned node straight out of the x-pass buffer
+// (two barriers per velocity); 0 = a y-pass through LDS, then the z contraction per node
+#ifndef TILE_YZF3
+#define TILE_YZF3 0
+#endif
+// row padding (elements) of the staging buffer, against LDS bank conflicts of the x-pass
+#ifndef TILE_SPAD
+#define TILE_SPAD 0
+#endif
+// staging loads of regions away from a periodic seam: 1 = buffer loads (32-bit
+// offsets), 0 = global loads
+#ifndef TILE_BUFLOAD
+#define TILE_BUFLOAD 1
+#endif
+// unroll factor of the row loops of the x- and y-passes
+#ifndef TILE_ROW_UNROLL
+#define TILE_ROW_UNROLL 4
 #endif
 
 struct TileGrid {
@@ -93,16 +106,44 @@ __device__ __forceinline__ void axis_weights(const DevAxis &ax, const AxGeo &g, 
   for (int j = 0; j <= P; j++) w[j] = wp[j];
 }
 
+// Loads through a buffer resource: the base address stays in scalar registers and each
+// lane supplies a 32-bit byte offset; the hardware returns 0 past num_records bytes.
+template <typename T> struct BufLoad;
+template <> struct BufLoad<double> {
+  __device__ static double get(__amdgpu_buffer_rsrc_t r, int off) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    return __builtin_bit_cast(double, v);
+  }
+};
+template <> struct BufLoad<float> {
+  __device__ static float get(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  }
+};
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const T *base, int64_t elems) {
+  const int64_t bytes = elems * (int64_t)sizeof(T);
+  return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)(bytes < 0x7fffffff ? bytes : 0x7fffffff),
+                                           0x00020000);
+}
+
 __device__ __forceinline__ int wrap_idx(int g, int N) {
   if (g < 0) g += N;
   else if (g >= N) g -= N;
   return g;
 }
 
-// MODE 1: streamed moments -> node state (rho, u, T, 1/tau_bar as [6][N] doubles), and
-// with TILE_STORE the streamed populations -> pout;
-// MODE 2: re-stream, relax against the node state, store.
-template <typename T, int D, int P, int CX, int CY, int CZ, int BS, int WPE, int MODE>
+// Streams every velocity of one tile: stores the streamed f_i, g_i of the owned nodes
+// and their node state (rho, u0, u1, u2, T, 1/tau_bar as [6][N] doubles).
+//
+// Per velocity i the workgroup passes two barriers:
+//   barrier; x-pass of i (staging S -> X); barrier;
+//   commit i+1 (registers -> S, weight tables -> buffer (i+1)&1) and issue the loads
+//   of i+2; y and z passes of i per owned node straight out of X; store; moments.
+// So the loads of a velocity are in flight for a whole iteration, and the y/z work of
+// velocity i overlaps the staging of i+1.
+template <typename T, int D, int P, int CX, int CY, int CZ, int BS, int WPE>
 __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, const StepArgs sa, const TileGrid tg,
                                                     const T *__restrict__ pin, T *__restrict__ pout,
                                                     double *__restrict__ nstate) {
@@ -110,17 +151,20 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
   constexpr int RX = TX + P + 1, RY = TY + P + 1, RZ = (D == 3) ? TZ + P + 1 : 1;
   constexpr int NT = TX * TY * TZ;
   constexpr int NPT = (NT + BS - 1) / BS;
-  constexpr int SS = RZ * RY * RX;           // one population's staging size
+  constexpr bool YZF = (D == 2) || TILE_YZF3;
+  constexpr int RXP = RX + TILE_SPAD;        // staging row stride
+  constexpr int SE = RZ * RY * RX;           // staged elements of one population
+  constexpr int SS = RZ * RY * RXP;          // one population's staging size
   constexpr int XS = RZ * RY * TX;           // one population's x-pass output
-  constexpr int YS = RZ * TY * TX;           // one population's y-pass output (3D)
-  constexpr int NST = (SS + BS - 1) / BS;      // staged elements per thread and population
-  constexpr int NW = TX + TY + TZ;           // weight rows: one per tile position and axis
-  static_assert(NW <= BS, "weight rows exceed the workgroup");
+  constexpr int YS = RZ * TY * TX;           // one population's y-pass output (3D, y-pass through LDS)
+  constexpr int NST = (SE + BS - 1) / BS;    // staged elements per thread and population
+  constexpr int NW = TX + TY + TZ;           // weight rows of one table: one per tile position and axis
+  static_assert(YZF || 2 * YS <= 2 * SS, "the y-pass output reuses the staging buffer");
   __shared__ T S[2 * SS];
   __shared__ T X[2 * XS];
-  __shared__ T WT[NW * (P + 1)];
-  __shared__ int OT[NW];
   T *Yb = S;
+  __shared__ T WT[kTileTabs * NW * (P + 1)];   // row tb * NW + (axis base) + t
+  __shared__ int OT[kTileTabs * NW];           // stencil start relative to the table's region
 
   const int Q = pl.Q;
   const int tid = threadIdx.x;
@@ -162,11 +206,46 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
   auto node_index = [&](int m) __attribute__((always_inline)) -> int64_t {
     return (int64_t)(n0x + otx[m]) + (int64_t)Nx * ((int64_t)(n0y + oty[m]) + (int64_t)Ny * (n0z + otz[m]));
   };
-  // ---- software pipeline: the departure region of velocity i+1 is loaded into
-  // registers while velocity i is interpolated out of LDS
+
+  // weight rows and stencil offsets of every table of every axis, for this tile (read
+  // by the passes of all velocities; the loop's first barrier publishes them)
+  for (int r = tid; r < kTileTabs * NW; r += BS) {
+    const int tb = r / NW, q0 = r % NW;
+    const int ax = q0 < TX ? 0 : (q0 < TX + TY ? 1 : 2);
+    const int t = q0 - (ax == 0 ? 0 : (ax == 1 ? TX : TX + TY));
+    const int vt = ax == 0 ? vx : (ax == 1 ? vy : vz);
+    const int n0a = ax == 0 ? n0x : (ax == 1 ? n0y : n0z);
+    const int Ta = ax == 0 ? TX : (ax == 1 ? TY : TZ);
+    const DevAxis &da = ax == 0 ? pl.ax[0] : (ax == 1 ? pl.ax[1] : pl.ax[2]);
+    if (ax >= D || tb >= da.ntab || t >= vt) continue;
+    const AxGeo g = axis_geo<P>(da, tb, n0a, vt, Ta);
+    int off, len;
+    T w[P + 1];
+    axis_weights<T, P>(da, g, n0a, t, Ta, off, len, w);
+#pragma unroll
+    for (int j = 0; j <= P; j++) WT[r * (P + 1) + j] = w[j];
+    OT[r] = off;
+  }
+
+  // staging elements of this thread: region coordinates and their offset in a population
+  // when the region does not cross a periodic seam (both independent of the velocity)
+  // (coordinates packed 10 bits each: x | y << 10 | z << 20; x = RX marks no element)
+  int epk[NST], eoff[NST];
+#pragma unroll
+  for (int s = 0; s < NST; s++) {
+    const int e = tid + BS * s;
+    const int rx = e < SE ? e % RX : RX, ry = e < SE ? (e / RX) % RY : 0, rz = e < SE ? e / (RX * RY) : 0;
+    epk[s] = rx | (ry << 10) | (rz << 20);
+    eoff[s] = (rx + Nx * (ry + Ny * rz)) * (int)sizeof(T);   // bytes
+  }
+  static_assert(RX < 1024 && RY < 1024 && RZ < 1024, "staging coordinates are packed in 10 bits");
+  auto staged = [&](int s, const AxGeo (&g)[3]) __attribute__((always_inline)) -> bool {
+    return (epk[s] & 1023) < g[0].R && ((epk[s] >> 10) & 1023) < g[1].R && (epk[s] >> 20) < g[2].R;
+  };
+
+  // ---- software pipeline: registers hold the departure region of the velocity after
+  // the one in LDS
   T pf[NST], pg[NST];
-  T pw[P + 1];
-  int poff = 0;
   AxGeo ng[3], cg[3];
   auto prefetch = [&](int i) __attribute__((always_inline)) {
     ng[0] = axis_geo<P>(pl.ax[0], pl.tab_reg[i], n0x, vx, TX);
@@ -178,139 +257,157 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
     }
     const T *F = pin + (size_t)i * N;
     const T *G = pin + ((size_t)Q + i) * N;
+    const int sx = n0x + ng[0].rs, sy = n0y + ng[1].rs, sz = (D == 3) ? n0z + ng[2].rs : 0;
+    const bool inside = sx >= 0 && sx + ng[0].R <= Nx && sy >= 0 && sy + ng[1].R <= Ny &&
+                        (D == 2 || (sz >= 0 && sz + ng[2].R <= Nz));
+    if (inside) {
+      const int64_t kb = (int64_t)sx + (int64_t)Nx * ((int64_t)sy + (int64_t)Ny * sz);
+      if (TILE_BUFLOAD) {
+        const __amdgpu_buffer_rsrc_t rf = buf_rsrc(F + kb, N - kb), rg = buf_rsrc(G + kb, N - kb);
 #pragma unroll
-    for (int s = 0; s < NST; s++) {
-      int e = tid + BS * s;
-      int rx = e % RX, ry = (e / RX) % RY, rz = e / (RX * RY);
-      if (e < SS && rx < ng[0].R && ry < ng[1].R && rz < ng[2].R) {
-        int gxx = wrap_idx(n0x + ng[0].rs + rx, Nx);
-        int gyy = wrap_idx(n0y + ng[1].rs + ry, Ny);
-        int gzz = (D == 3) ? wrap_idx(n0z + ng[2].rs + rz, Nz) : 0;
-        size_t k = (size_t)gxx + (size_t)Nx * ((size_t)gyy + (size_t)Ny * gzz);
-        pf[s] = F[k];
-        pg[s] = G[k];
+        for (int s = 0; s < NST; s++) {
+          if (staged(s, ng)) {
+            pf[s] = BufLoad<T>::get(rf, eoff[s]);
+            pg[s] = BufLoad<T>::get(rg, eoff[s]);
+          }
+        }
+      } else {
+        const char *Fb = (const char *)(F + kb), *Gb = (const char *)(G + kb);
+#pragma unroll
+        for (int s = 0; s < NST; s++) {
+          if (staged(s, ng)) {
+            pf[s] = *(const T *)(Fb + eoff[s]);
+            pg[s] = *(const T *)(Gb + eoff[s]);
+          }
+        }
       }
-    }
-    if (tid < NW) {
-      int ax = tid < TX ? 0 : (tid < TX + TY ? 1 : 2);
-      int q = tid - (ax == 0 ? 0 : (ax == 1 ? TX : TX + TY));
-      int vt = ax == 0 ? vx : (ax == 1 ? vy : vz);
-      int n0a = ax == 0 ? n0x : (ax == 1 ? n0y : n0z);
-      int Ta = ax == 0 ? TX : (ax == 1 ? TY : TZ);
-      int len;
-      const AxGeo &ga = ax == 0 ? ng[0] : (ax == 1 ? ng[1] : ng[2]);
-      const DevAxis &da = ax == 0 ? pl.ax[0] : (ax == 1 ? pl.ax[1] : pl.ax[2]);
-      if (ax < D && q < vt) axis_weights<T, P>(da, ga, n0a, q, Ta, poff, len, pw);
+    } else {
+#pragma unroll
+      for (int s = 0; s < NST; s++) {
+        if (staged(s, ng)) {
+          int gxx = wrap_idx(sx + (epk[s] & 1023), Nx);
+          int gyy = wrap_idx(sy + ((epk[s] >> 10) & 1023), Ny);
+          int gzz = (D == 3) ? wrap_idx(sz + (epk[s] >> 20), Nz) : 0;
+          size_t k = (size_t)gxx + (size_t)Nx * ((size_t)gyy + (size_t)Ny * gzz);
+          pf[s] = F[k];
+          pg[s] = G[k];
+        }
+      }
     }
   };
   auto commit = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < NST; s++) {
-      int e = tid + BS * s;
-      int rx = e % RX, ry = (e / RX) % RY, rz = e / (RX * RY);
-      if (e < SS && rx < ng[0].R && ry < ng[1].R && rz < ng[2].R) {
-        S[e] = pf[s];
-        S[SS + e] = pg[s];
+      if (staged(s, ng)) {
+        const int e = tid + BS * s;
+        const int se = (e / RX) * RXP + e % RX;   // padded row
+        S[se] = pf[s];
+        S[SS + se] = pg[s];
       }
-    }
-    if (tid < NW) {
-#pragma unroll
-      for (int j = 0; j <= P; j++) WT[tid * (P + 1) + j] = pw[j];
-      OT[tid] = poff;
     }
     cg[0] = ng[0];
     cg[1] = ng[1];
     cg[2] = ng[2];
   };
 
-  // Streamed f_i, g_i of every owned node out of the committed LDS region: three 1D
-  // passes (two in 2D), then the boundary-layer pairs by per-node gather.
-  auto interpolate = [&](double (&fv)[NPT], double (&gv)[NPT]) __attribute__((always_inline)) {
+  // x-pass: S[rz][ry][*] -> X[rz][ry][tx]; each thread keeps one tx (and its weights)
+  // and walks the rows of the committed region
+  auto xpass = [&]() __attribute__((always_inline)) {
+    constexpr int NRX = BS / TX;          // rows in flight per sweep of the workgroup
     const int Ry = cg[1].R, Rz = cg[2].R;
-    {  // x-pass: S[rz][ry][*] -> X[rz][ry][tx]; each thread keeps one tx (and its
-       // weights) and walks the rows
-      constexpr int NRX = BS / TX;          // rows in flight per sweep of the workgroup
-      const int len = cg[0].ident ? 1 : P + 1;
-      const int tx = tid % TX, r0 = tid / TX;
-      if (r0 < NRX && tx < vx) {
-        const int off = OT[tx];
-        T w[P + 1];
+    const int len = cg[0].ident ? 1 : P + 1;
+    const int tx = tid % TX, r0 = tid / TX;
+    if (r0 < NRX && tx < vx) {
+      const int row = cg[0].tb * NW + tx;
+      const int off = OT[row];
+      T w[P + 1];
 #pragma unroll
-        for (int j = 0; j <= P; j++) w[j] = WT[tx * (P + 1) + j];
-        const int nrows = Ry * Rz;
-#pragma unroll PASS_UNROLL
-        for (int rr = r0; rr < RY * RZ; rr += NRX) {
-          int ry = rr % Ry, rz = rr / Ry;
-          if (rr >= nrows) break;
-          const T *sf = S + (rz * RY + ry) * RX + off;
-          T a = 0, b = 0;
-#pragma unroll
-          for (int j = 0; j <= P; j++) {
-            if (j >= len) break;
-            a += w[j] * sf[j];
-            b += w[j] * sf[SS + j];
-          }
-          int l = (rz * RY + ry) * TX + tx;
-          X[l] = a;
-          X[XS + l] = b;
-        }
-      }
-    }
-    __syncthreads();
-    if constexpr (D == 3) {
-      {  // y-pass: X[rz][*][tx] -> Yb[rz][ty][tx]; each thread keeps one (tx, ty)
-        constexpr int NRY = BS / (TX * TY);
-        static_assert(NRY >= 1, "tile cross-section exceeds the workgroup");
-        const int len = cg[1].ident ? 1 : P + 1;
-        const int tx = tid % TX, ty = (tid / TX) % TY, z0 = tid / (TX * TY);
-        if (z0 < NRY && tx < vx && ty < vy) {
-          const int off = OT[TX + ty];
-          T w[P + 1];
-#pragma unroll
-          for (int j = 0; j <= P; j++) w[j] = WT[(TX + ty) * (P + 1) + j];
-#pragma unroll PASS_UNROLL
-          for (int rz = z0; rz < RZ; rz += NRY) {
-            if (rz >= Rz) break;
-            const T *xf = X + (rz * RY + off) * TX + tx;
-            T a = 0, b = 0;
-#pragma unroll
-            for (int j = 0; j <= P; j++) {
-              if (j >= len) break;
-              a += w[j] * xf[j * TX];
-              b += w[j] * xf[XS + j * TX];
-            }
-            int l = (rz * TY + ty) * TX + tx;
-            Yb[l] = a;
-            Yb[YS + l] = b;
-          }
-        }
-      }
-      __syncthreads();
-      const int len = cg[2].ident ? 1 : P + 1;
-#pragma unroll
-      for (int m = 0; m < NPT; m++) {  // z-pass for the owned nodes
-        fv[m] = gv[m] = 0.0;
-        if (!own[m]) continue;
-        const T *yf = Yb + (OT[TX + TY + otz[m]] * TY + oty[m]) * TX + otx[m];
-        const T *w = WT + (TX + TY + otz[m]) * (P + 1);
+      for (int j = 0; j <= P; j++) w[j] = WT[row * (P + 1) + j];
+      const int nrows = Ry * Rz;
+      constexpr int MR = (RY * RZ + NRX - 1) / NRX;   // rows per thread at most
+#pragma unroll TILE_ROW_UNROLL
+      for (int q = 0; q < MR; q++) {
+        const int rr = r0 + q * NRX;
+        if (rr >= nrows) break;
+        const int ry = rr % Ry, rz = rr / Ry;
+        const T *sf = S + (rz * RY + ry) * RXP + off;
         T a = 0, b = 0;
 #pragma unroll
         for (int j = 0; j <= P; j++) {
           if (j >= len) break;
-          a += w[j] * yf[j * TY * TX];
-          b += w[j] * yf[YS + j * TY * TX];
+          a += w[j] * sf[j];
+          b += w[j] * sf[SS + j];
         }
-        fv[m] = scale * (double)a;
-        gv[m] = scale * (double)b;
+        const int l = (rz * RY + ry) * TX + tx;
+        X[l] = a;
+        X[XS + l] = b;
       }
-    } else {
-      const int len = cg[1].ident ? 1 : P + 1;
+    }
+  };
+
+  // y (and z) passes for the owned nodes straight out of X: per node (P+1)^2 reads in 3D
+  auto yzpass = [&](int tby, int tbz, int leny, int lenz, double (&fv)[NPT], double (&gv)[NPT])
+                    __attribute__((always_inline)) {
 #pragma unroll
-      for (int m = 0; m < NPT; m++) {  // y-pass (last in 2D) for the owned nodes
-        fv[m] = gv[m] = 0.0;
-        if (!own[m]) continue;
-        const T *xf = X + OT[TX + oty[m]] * TX + otx[m];
-        const T *w = WT + (TX + oty[m]) * (P + 1);
+    for (int m = 0; m < NPT; m++) {
+      fv[m] = gv[m] = 0.0;
+      if (!own[m]) continue;
+      const int ry = tby * NW + TX + oty[m];
+      const int offy = OT[ry];
+      const T *wy = WT + ry * (P + 1);
+      T a = 0, b = 0;
+      if constexpr (D == 3) {
+        const int rz = tbz * NW + TX + TY + otz[m];
+        const int offz = OT[rz];
+        const T *wz = WT + rz * (P + 1);
+#pragma unroll 1
+        for (int jz = 0; jz < lenz; jz++) {
+          const T *xr = X + ((offz + jz) * RY + offy) * TX + otx[m];
+          T ay = 0, by = 0;
+#pragma unroll
+          for (int jy = 0; jy <= P; jy++) {
+            if (jy >= leny) break;
+            ay += wy[jy] * xr[jy * TX];
+            by += wy[jy] * xr[XS + jy * TX];
+          }
+          a += wz[jz] * ay;
+          b += wz[jz] * by;
+        }
+      } else {
+        (void)lenz;
+        (void)tbz;
+        const T *xr = X + offy * TX + otx[m];
+#pragma unroll
+        for (int jy = 0; jy <= P; jy++) {
+          if (jy >= leny) break;
+          a += wy[jy] * xr[jy * TX];
+          b += wy[jy] * xr[XS + jy * TX];
+        }
+      }
+      fv[m] = scale * (double)a;
+      gv[m] = scale * (double)b;
+    }
+  };
+
+  // 3D y-pass through LDS: X[rz][*][tx] -> Yb[rz][ty][tx]; each thread keeps one (tx, ty)
+  auto ypass = [&]() __attribute__((always_inline)) {
+    constexpr int NRY = BS / (TX * TY);
+    static_assert(YZF || NRY >= 1, "tile cross-section exceeds the workgroup");
+    const int Rz = cg[2].R;
+    const int len = cg[1].ident ? 1 : P + 1;
+    const int tx = tid % TX, ty = (tid / TX) % TY, z0 = tid / (TX * TY);
+    if (z0 < NRY && tx < vx && ty < vy) {
+      const int row = cg[1].tb * NW + TX + ty;
+      const int off = OT[row];
+      T w[P + 1];
+#pragma unroll
+      for (int j = 0; j <= P; j++) w[j] = WT[row * (P + 1) + j];
+      constexpr int MZ = NRY > 0 ? (RZ + NRY - 1) / NRY : 0;
+#pragma unroll TILE_ROW_UNROLL
+      for (int q = 0; q < MZ; q++) {
+        const int rz = z0 + q * NRY;
+        if (rz >= Rz) break;
+        const T *xf = X + (rz * RY + off) * TX + tx;
         T a = 0, b = 0;
 #pragma unroll
         for (int j = 0; j <= P; j++) {
@@ -318,122 +415,107 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
           a += w[j] * xf[j * TX];
           b += w[j] * xf[XS + j * TX];
         }
-        fv[m] = scale * (double)a;
-        gv[m] = scale * (double)b;
+        const int l = (rz * TY + ty) * TX + tx;
+        Yb[l] = a;
+        Yb[YS + l] = b;
       }
     }
   };
-  // one pipeline stage: velocity i is committed to LDS, velocity `next` (or -1) is
-  // prefetched, and i is interpolated
-  auto stream_velocity = [&](int i, int next, double (&fv)[NPT], double (&gv)[NPT]) __attribute__((always_inline)) {
-    __syncthreads();  // everyone is done reading the previous velocity out of LDS
-    commit();
-    if (next >= 0) prefetch(next);
-    __syncthreads();
-    interpolate(fv, gv);
+  // z contraction of the y-passed values for the owned nodes
+  auto zpass = [&](double (&fv)[NPT], double (&gv)[NPT]) __attribute__((always_inline)) {
+    const int len = cg[2].ident ? 1 : P + 1;
+#pragma unroll
+    for (int m = 0; m < NPT; m++) {
+      fv[m] = gv[m] = 0.0;
+      if (!own[m]) continue;
+      const int row = cg[2].tb * NW + TX + TY + otz[m];
+      const T *yf = Yb + (OT[row] * TY + oty[m]) * TX + otx[m];
+      const T *w = WT + row * (P + 1);
+      T a = 0, b = 0;
+#pragma unroll
+      for (int j = 0; j <= P; j++) {
+        if (j >= len) break;
+        a += w[j] * yf[j * TY * TX];
+        b += w[j] * yf[YS + j * TY * TX];
+      }
+      fv[m] = scale * (double)a;
+      gv[m] = scale * (double)b;
+    }
   };
 
+  double rho[NPT], j0[NPT], j1[NPT], j2[NPT], E[NPT];
+#pragma unroll
+  for (int m = 0; m < NPT; m++) rho[m] = j0[m] = j1[m] = j2[m] = E[m] = 0.0;
   prefetch(0);
-  if (MODE == 1) {
-    // -------- sweep 1: conserved moments of the streamed populations -> node state
-    double rho[NPT], j0[NPT], j1[NPT], j2[NPT], E[NPT];
-#pragma unroll
-    for (int m = 0; m < NPT; m++) rho[m] = j0[m] = j1[m] = j2[m] = E[m] = 0.0;
-    for (int i = 0; i < Q; i++) {
-      double fv[NPT], gv[NPT];
-      stream_velocity(i, i + 1 < Q ? i + 1 : -1, fv, gv);
-      const double *vi = pl.vel + 8 * i;
-      const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
-      if (TILE_STORE) {
-#pragma unroll
-        for (int m = 0; m < NPT; m++) {
-          if (!own[m]) continue;
-          const int64_t k = node_index(m);
-          pout[(size_t)i * N + k] = (T)fv[m];
-          pout[((size_t)Q + i) * N + k] = (T)gv[m];
-        }
+  if (YZF) {
+    commit();
+    if (Q > 1) prefetch(1);
+  }
+  for (int i = 0; i < Q; i++) {
+    double fv[NPT], gv[NPT];
+    if constexpr (YZF) {
+      __syncthreads();   // velocity i is in S; X is free
+      xpass();
+      __syncthreads();   // X holds velocity i; S is free
+      const int tby = cg[1].tb, tbz = cg[2].tb;
+      const int leny = cg[1].ident ? 1 : P + 1, lenz = cg[2].ident ? 1 : P + 1;
+      if (i + 1 < Q) {
+        commit();
+        if (i + 2 < Q) prefetch(i + 2);
       }
-#pragma unroll
-      for (int m = 0; m < NPT; m++) {
-        rho[m] += fv[m];
-        j0[m] += vi[0] * fv[m];
-        j1[m] += vi[1] * fv[m];
-        j2[m] += vi[2] * fv[m];
-        E[m] += z2 * fv[m] + gv[m];
-      }
+      yzpass(tby, tbz, leny, lenz, fv, gv);
+    } else {
+      __syncthreads();   // the previous z contraction is done reading Yb (= S)
+      commit();
+      if (i + 1 < Q) prefetch(i + 1);
+      __syncthreads();   // velocity i is in S
+      xpass();
+      __syncthreads();   // X holds velocity i
+      ypass();
+      __syncthreads();   // Yb holds velocity i
+      zpass(fv, gv);
     }
-    // node state: rho, u, T, 1/tau_bar (isothermal walls act only inside the boundary
-    // layers, which the gather kernel handles)
+    const double *vi = pl.vel + 8 * i;
+    const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
 #pragma unroll
     for (int m = 0; m < NPT; m++) {
       if (!own[m]) continue;
-      double r = rho[m];
-      double u0 = j0[m] / r, u1 = j1[m] / r, u2 = j2[m] / r;
-      double Tn = (E[m] - r * (u0 * u0 + u1 * u1 + u2 * u2)) / (2.0 * r * sa.cv);
-      double it = 0.0;
-      if (sa.relax_mode == 0) it = 1.0 / sa.tau_bar;
-      if (sa.relax_mode == 1) {
-        double mu = sa.mu_ref * pow(Tn / sa.T_ref, sa.mu_exp);
-        it = 1.0 / (mu / (r * Tn * sa.dt) + 0.5);
-      }
       const int64_t k = node_index(m);
-      nstate[k] = r;
-      nstate[N + k] = u0;
-      nstate[2 * N + k] = u1;
-      nstate[3 * N + k] = u2;
-      nstate[4 * N + k] = Tn;
-      nstate[5 * N + k] = it;
+      pout[(size_t)i * N + k] = (T)fv[m];
+      pout[((size_t)Q + i) * N + k] = (T)gv[m];
+      rho[m] += fv[m];
+      j0[m] += vi[0] * fv[m];
+      j1[m] += vi[1] * fv[m];
+      j2[m] += vi[2] * fv[m];
+      E[m] += z2 * fv[m] + gv[m];
     }
-  } else {
-    // -------- sweep 2: re-stream, BGK relaxation, forcing, store
-    double rho[NPT], nu0[NPT], nu1[NPT], nu2[NPT], Tn[NPT], itau[NPT];
+  }
+  // node state: rho, u, T, 1/tau_bar (isothermal walls act only inside the boundary
+  // layers, which the gather kernel handles)
 #pragma unroll
-    for (int m = 0; m < NPT; m++) {
-      const int64_t k = own[m] ? node_index(m) : 0;
-      rho[m] = nstate[k];
-      nu0[m] = nstate[N + k];
-      nu1[m] = nstate[2 * N + k];
-      nu2[m] = nstate[3 * N + k];
-      Tn[m] = nstate[4 * N + k];
-      itau[m] = nstate[5 * N + k];
+  for (int m = 0; m < NPT; m++) {
+    if (!own[m]) continue;
+    double r = rho[m];
+    double u0 = j0[m] / r, u1 = j1[m] / r, u2 = j2[m] / r;
+    double Tn = (E[m] - r * (u0 * u0 + u1 * u1 + u2 * u2)) / (2.0 * r * sa.cv);
+    double it = 0.0;
+    if (sa.relax_mode == 0) it = 1.0 / sa.tau_bar;
+    if (sa.relax_mode == 1) {
+      double mu = sa.mu_ref * pow(Tn / sa.T_ref, sa.mu_exp);
+      it = 1.0 / (mu / (r * Tn * sa.dt) + 0.5);
     }
-    for (int i = 0; i < Q; i++) {
-      double fv[NPT], gv[NPT];
-      stream_velocity(i, i + 1 < Q ? i + 1 : -1, fv, gv);
-      const double *vi = pl.vel + 8 * i;
-#pragma unroll
-      for (int m = 0; m < NPT; m++) {
-        if (!own[m]) continue;
-        double f = fv[m], g = gv[m];
-        // the node's equilibrium coefficients are rebuilt per velocity on purpose:
-        // "+ 0 * w_i" keeps them inside the loop (hoisting them costs ~40 registers
-        // per node and halves the occupancy)
-        const double r_m = rho[m] + 0.0 * vi[7];
-        EqNode e = eq_prepare(r_m, nu0[m], nu1[m], nu2[m], Tn[m], sa, D);
-        double fe = eq_f(e, vi);
-        const double gT = Tn[m] * sa.gbase;
-        double fo = f, go = g;
-        if (sa.relax_mode != 2) {
-          fo = f - (f - fe) * itau[m];
-          go = g - (g - gT * fe) * itau[m];
-          if (sa.has_force) {
-            EqNode ef = eq_forced(r_m, nu0[m], nu1[m], nu2[m], Tn[m], sa, D);
-            double df = eq_f(ef, vi) - fe;
-            fo += df;
-            go += gT * df;
-          }
-        }
-        const int64_t k = node_index(m);
-        pout[(size_t)i * N + k] = (T)fo;
-        pout[((size_t)Q + i) * N + k] = (T)go;
-      }
-    }
+    const int64_t k = node_index(m);
+    nstate[k] = r;
+    nstate[N + k] = u0;
+    nstate[2 * N + k] = u1;
+    nstate[3 * N + k] = u2;
+    nstate[4 * N + k] = Tn;
+    nstate[5 * N + k] = it;
   }
 }
 
-// In-place BGK relaxation and forcing of the streamed populations the moments launch
-// stored, one node per lane (its equilibrium coefficients built once); nodes in the
-// boundary layers of a bounded face belong to the gather kernel and are skipped.
+// In place: relax the stored streamed populations of every node the tile kernel owns
+// (BGK against the closed-form equilibrium of its node state, Kupershtokh forcing).
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, const StepArgs sa,
                                                         T *__restrict__ pop, const double *__restrict__ nstate) {
@@ -455,21 +537,36 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
   EqNode ef = e;
   if (sa.has_force) ef = eq_forced(rho, u0, u1, u2, Tn, sa, D);
   const double gT = Tn * sa.gbase;
-  for (int i = 0; i < Q; i++) {
-    const double *vi = pl.vel + 8 * i;
-    T *pf = pop + (size_t)i * N + k;
-    T *pg = pop + ((size_t)Q + i) * N + k;
-    double f = (double)*pf, g = (double)*pg;
-    double fe = eq_f(e, vi);
-    double fo = f - (f - fe) * itau;
-    double go = g - (g - gT * fe) * itau;
-    if (sa.has_force) {
-      double df = eq_f(ef, vi) - fe;
-      fo += df;
-      go += gT * df;
+  // velocities in batches of RB: all loads of a batch are issued before its stores, so
+  // each lane keeps 2 RB reads in flight
+  constexpr int RB = RELAX_BATCH;
+  T *pf = pop + k;
+  T *pg = pop + (size_t)Q * N + k;
+  for (int i0 = 0; i0 < Q; i0 += RB) {
+    T fb[RB], gb[RB];
+#pragma unroll
+    for (int b = 0; b < RB; b++) {
+      if (i0 + b < Q) {
+        fb[b] = pf[(size_t)(i0 + b) * N];
+        gb[b] = pg[(size_t)(i0 + b) * N];
+      }
     }
-    *pf = (T)fo;
-    *pg = (T)go;
+#pragma unroll
+    for (int b = 0; b < RB; b++) {
+      if (i0 + b >= Q) break;
+      const double *vi = pl.vel + 8 * (i0 + b);
+      const double f = (double)fb[b], g = (double)gb[b];
+      const double fe = eq_f(e, vi);
+      double fo = f - (f - fe) * itau;
+      double go = g - (g - gT * fe) * itau;
+      if (sa.has_force) {
+        const double df = eq_f(ef, vi) - fe;
+        fo += df;
+        go += gT * df;
+      }
+      pf[(size_t)(i0 + b) * N] = (T)fo;
+      pg[(size_t)(i0 + b) * N] = (T)go;
+    }
   }
 }
 
@@ -478,9 +575,9 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
 namespace {
 template <typename T, int D, int P, int CX, int CY, int CZ>
 int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
-  constexpr int BS = D == 3 ? 512 : 256;   // threads per workgroup
+  constexpr int BS = D == 3 ? TILE_BS3 : 256;   // threads per workgroup
   // minimum waves per SIMD the register budget must allow, per launch
-  constexpr int WPE = TILE_WPE, WPE2 = TILE_WPE2;
+  constexpr int WPE = TILE_WPE;
   constexpr int TX = CX * P, TY = CY * P, TZ = (D == 3) ? CZ * P : 1;
   const DevTensorPlan &tp = Pl->tp;
   TileGrid tg;
@@ -492,18 +589,13 @@ int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *po
   tg.r = ntiles % 8;
   {
     ProfScope ps(Pl, "k_step_tile", s);
-    hipLaunchKernelGGL((k_step_tile<T, D, P, CX, CY, CZ, BS, WPE, 1>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
+    hipLaunchKernelGGL((k_step_tile<T, D, P, CX, CY, CZ, BS, WPE>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
                        (const T *)pin, (T *)pout, Pl->nstate);
   }
-  if (TILE_STORE) {
-    (void)WPE2;
+  {
     ProfScope ps(Pl, "k_relax_nodes", s);
     hipLaunchKernelGGL((k_relax_nodes<T, D>), dim3((unsigned)((tp.N + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, tp,
                        a, (T *)pout, (const double *)Pl->nstate);
-  } else {
-    ProfScope ps(Pl, "k_step_tile_restream", s);
-    hipLaunchKernelGGL((k_step_tile<T, D, P, CX, CY, CZ, BS, WPE2, 2>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
-                       (const T *)pin, (T *)pout, Pl->nstate);
   }
   return SLLBM_OK;
 }
