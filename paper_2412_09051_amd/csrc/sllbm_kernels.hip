@@ -244,13 +244,22 @@ __global__ void __launch_bounds__(kBlock) k_mass_partial(int64_t N, int Q, int D
   for (int q = 0; q < kRedWidth; q++) v[q] = 0.0;
   if (k < N) {
     double r = 0, j0 = 0, j1 = 0, j2 = 0;
-    for (int i = 0; i < Q; i++) {
-      const double f = (double)pop[(size_t)i * N + k];
-      const double *vi = vel + 8 * i;
-      r += f;
-      j0 += vi[0] * f;
-      j1 += vi[1] * f;
-      j2 += vi[2] * f;
+    constexpr int RB = 5;   // loads issued per batch, ahead of their use
+    for (int i0 = 0; i0 < Q; i0 += RB) {
+      T fb[RB];
+#pragma unroll
+      for (int b = 0; b < RB; b++)
+        if (i0 + b < Q) fb[b] = pop[(size_t)(i0 + b) * N + k];
+#pragma unroll
+      for (int b = 0; b < RB; b++) {
+        if (i0 + b >= Q) break;
+        const double f = (double)fb[b];
+        const double *vi = vel + 8 * (i0 + b);
+        r += f;
+        j0 += vi[0] * f;
+        j1 += vi[1] * f;
+        j2 += vi[2] * f;
+      }
     }
     const double V = vol[k];
     v[0] = V * r;

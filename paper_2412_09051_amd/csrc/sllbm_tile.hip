@@ -1,17 +1,23 @@
 // LDS-tiled fused SLLBM step on tensor-product meshes (gfx950, wave64).
 //
-// One workgroup owns a cell-aligned tile of TX x TY x TZ nodes.  For every velocity i
+// One workgroup owns a cell-aligned tile of TX x TY (x TZ) nodes.  For every velocity i
 // it stages the departure region of f_i and g_i (the tile shifted by the velocity's
 // displacement, at most one cell of halo on one side per axis) from HBM into LDS, then
-// applies the separable interpolant of eq:intf as an x-pass over the staged rows and,
-// per owned node, the y and z contractions of the x-passed values: (p+1) + (p+1)^2
-// multiply-adds per streamed value instead of (p+1)^3 gathers.
+// applies the separable interpolant of eq:intf as 1D passes: (p+1) multiply-adds per
+// pass and streamed value instead of (p+1)^d gathers.
 // Two launches per step: the first streams every velocity, stores the streamed f_i, g_i
 // and reduces their conserved moments per node into a small node-state array (6 doubles
 // per node); the second relaxes the stored populations in place, one node per lane.
 // Nodes in the boundary layers of a bounded face (where some departure point leaves the
 // domain, and where the isothermal-wall correction acts) are left to the per-node gather
 // kernel, launched on those slabs.
+//
+// The 2D and 3D stream kernels differ in their schedule (measured on MI355X: each is the
+// faster of the two designs for its dimension): in 2D the weight rows of every table sit
+// in LDS for the whole tile, staging uses buffer loads, and the y contraction runs per
+// node straight out of the x-pass buffer (two barriers per velocity); in 3D the x, y and
+// z passes each go through LDS and the weight rows of each velocity travel with its
+// staged region (four barriers per velocity).
 #include <hip/hip_runtime.h>
 
 #include "sllbm_device_common.h"
@@ -21,30 +27,6 @@ namespace sllbm {
 
 #ifndef TILE_WPE
 #define TILE_WPE 4
-#endif
-#ifndef TILE_BS3
-#define TILE_BS3 512
-#endif
-#ifndef RELAX_BATCH
-#define RELAX_BATCH 5
-#endif
-// 3D: 1 = the y and z contractions per owned node straight out of the x-pass buffer
-// (two barriers per velocity); 0 = a y-pass through LDS, then the z contraction per node
-#ifndef TILE_YZF3
-#define TILE_YZF3 0
-#endif
-// row padding (elements) of the staging buffer, against LDS bank conflicts of the x-pass
-#ifndef TILE_SPAD
-#define TILE_SPAD 0
-#endif
-// staging loads of regions away from a periodic seam: 1 = buffer loads (32-bit
-// offsets), 0 = global loads
-#ifndef TILE_BUFLOAD
-#define TILE_BUFLOAD 1
-#endif
-// unroll factor of the row loops of the x- and y-passes
-#ifndef TILE_ROW_UNROLL
-#define TILE_ROW_UNROLL 4
 #endif
 
 struct TileGrid {
@@ -134,35 +116,30 @@ __device__ __forceinline__ int wrap_idx(int g, int N) {
   return g;
 }
 
-// Streams every velocity of one tile: stores the streamed f_i, g_i of the owned nodes
-// and their node state (rho, u0, u1, u2, T, 1/tau_bar as [6][N] doubles).
-//
-// Per velocity i the workgroup passes two barriers:
+// 2D: streams every velocity of one tile and stores the streamed f_i, g_i of the owned
+// nodes and their node state (rho, u0, u1, u2, T, 1/tau_bar as [6][N] doubles).  The
+// weight rows of every table are staged in LDS once per tile.  Per velocity i the
+// workgroup passes two barriers:
 //   barrier; x-pass of i (staging S -> X); barrier;
-//   commit i+1 (registers -> S, weight tables -> buffer (i+1)&1) and issue the loads
-//   of i+2; y and z passes of i per owned node straight out of X; store; moments.
-// So the loads of a velocity are in flight for a whole iteration, and the y/z work of
+//   commit i+1 (registers -> S) and issue the loads of i+2; y contraction of i per owned
+//   node straight out of X; store; moments.
+// So the loads of a velocity are in flight for a whole iteration, and the y work of
 // velocity i overlaps the staging of i+1.
 template <typename T, int D, int P, int CX, int CY, int CZ, int BS, int WPE>
-__global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, const StepArgs sa, const TileGrid tg,
+__global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl, const StepArgs sa, const TileGrid tg,
                                                     const T *__restrict__ pin, T *__restrict__ pout,
                                                     double *__restrict__ nstate) {
   constexpr int TX = CX * P, TY = CY * P, TZ = (D == 3) ? CZ * P : 1;
   constexpr int RX = TX + P + 1, RY = TY + P + 1, RZ = (D == 3) ? TZ + P + 1 : 1;
   constexpr int NT = TX * TY * TZ;
   constexpr int NPT = (NT + BS - 1) / BS;
-  constexpr bool YZF = (D == 2) || TILE_YZF3;
-  constexpr int RXP = RX + TILE_SPAD;        // staging row stride
-  constexpr int SE = RZ * RY * RX;           // staged elements of one population
-  constexpr int SS = RZ * RY * RXP;          // one population's staging size
+  static_assert(D == 2, "the 2D tile kernel");
+  constexpr int SS = RZ * RY * RX;           // one population's staging size
   constexpr int XS = RZ * RY * TX;           // one population's x-pass output
-  constexpr int YS = RZ * TY * TX;           // one population's y-pass output (3D, y-pass through LDS)
-  constexpr int NST = (SE + BS - 1) / BS;    // staged elements per thread and population
+  constexpr int NST = (SS + BS - 1) / BS;    // staged elements per thread and population
   constexpr int NW = TX + TY + TZ;           // weight rows of one table: one per tile position and axis
-  static_assert(YZF || 2 * YS <= 2 * SS, "the y-pass output reuses the staging buffer");
   __shared__ T S[2 * SS];
   __shared__ T X[2 * XS];
-  T *Yb = S;
   __shared__ T WT[kTileTabs * NW * (P + 1)];   // row tb * NW + (axis base) + t
   __shared__ int OT[kTileTabs * NW];           // stencil start relative to the table's region
 
@@ -234,7 +211,7 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
 #pragma unroll
   for (int s = 0; s < NST; s++) {
     const int e = tid + BS * s;
-    const int rx = e < SE ? e % RX : RX, ry = e < SE ? (e / RX) % RY : 0, rz = e < SE ? e / (RX * RY) : 0;
+    const int rx = e < SS ? e % RX : RX, ry = e < SS ? (e / RX) % RY : 0, rz = e < SS ? e / (RX * RY) : 0;
     epk[s] = rx | (ry << 10) | (rz << 20);
     eoff[s] = (rx + Nx * (ry + Ny * rz)) * (int)sizeof(T);   // bytes
   }
@@ -262,23 +239,12 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
                         (D == 2 || (sz >= 0 && sz + ng[2].R <= Nz));
     if (inside) {
       const int64_t kb = (int64_t)sx + (int64_t)Nx * ((int64_t)sy + (int64_t)Ny * sz);
-      if (TILE_BUFLOAD) {
-        const __amdgpu_buffer_rsrc_t rf = buf_rsrc(F + kb, N - kb), rg = buf_rsrc(G + kb, N - kb);
+      const __amdgpu_buffer_rsrc_t rf = buf_rsrc(F + kb, N - kb), rg = buf_rsrc(G + kb, N - kb);
 #pragma unroll
-        for (int s = 0; s < NST; s++) {
-          if (staged(s, ng)) {
-            pf[s] = BufLoad<T>::get(rf, eoff[s]);
-            pg[s] = BufLoad<T>::get(rg, eoff[s]);
-          }
-        }
-      } else {
-        const char *Fb = (const char *)(F + kb), *Gb = (const char *)(G + kb);
-#pragma unroll
-        for (int s = 0; s < NST; s++) {
-          if (staged(s, ng)) {
-            pf[s] = *(const T *)(Fb + eoff[s]);
-            pg[s] = *(const T *)(Gb + eoff[s]);
-          }
+      for (int s = 0; s < NST; s++) {
+        if (staged(s, ng)) {
+          pf[s] = BufLoad<T>::get(rf, eoff[s]);
+          pg[s] = BufLoad<T>::get(rg, eoff[s]);
         }
       }
     } else {
@@ -300,9 +266,8 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
     for (int s = 0; s < NST; s++) {
       if (staged(s, ng)) {
         const int e = tid + BS * s;
-        const int se = (e / RX) * RXP + e % RX;   // padded row
-        S[se] = pf[s];
-        S[SS + se] = pg[s];
+        S[e] = pf[s];
+        S[SS + e] = pg[s];
       }
     }
     cg[0] = ng[0];
@@ -325,12 +290,12 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
       for (int j = 0; j <= P; j++) w[j] = WT[row * (P + 1) + j];
       const int nrows = Ry * Rz;
       constexpr int MR = (RY * RZ + NRX - 1) / NRX;   // rows per thread at most
-#pragma unroll TILE_ROW_UNROLL
+#pragma unroll 4
       for (int q = 0; q < MR; q++) {
         const int rr = r0 + q * NRX;
         if (rr >= nrows) break;
         const int ry = rr % Ry, rz = rr / Ry;
-        const T *sf = S + (rz * RY + ry) * RXP + off;
+        const T *sf = S + (rz * RY + ry) * RX + off;
         T a = 0, b = 0;
 #pragma unroll
         for (int j = 0; j <= P; j++) {
@@ -345,98 +310,21 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
     }
   };
 
-  // y (and z) passes for the owned nodes straight out of X: per node (P+1)^2 reads in 3D
-  auto yzpass = [&](int tby, int tbz, int leny, int lenz, double (&fv)[NPT], double (&gv)[NPT])
-                    __attribute__((always_inline)) {
+  // y contraction for the owned nodes straight out of X
+  auto ypass_nodes = [&](int tby, int leny, double (&fv)[NPT], double (&gv)[NPT]) __attribute__((always_inline)) {
 #pragma unroll
     for (int m = 0; m < NPT; m++) {
       fv[m] = gv[m] = 0.0;
       if (!own[m]) continue;
       const int ry = tby * NW + TX + oty[m];
-      const int offy = OT[ry];
       const T *wy = WT + ry * (P + 1);
-      T a = 0, b = 0;
-      if constexpr (D == 3) {
-        const int rz = tbz * NW + TX + TY + otz[m];
-        const int offz = OT[rz];
-        const T *wz = WT + rz * (P + 1);
-#pragma unroll 1
-        for (int jz = 0; jz < lenz; jz++) {
-          const T *xr = X + ((offz + jz) * RY + offy) * TX + otx[m];
-          T ay = 0, by = 0;
-#pragma unroll
-          for (int jy = 0; jy <= P; jy++) {
-            if (jy >= leny) break;
-            ay += wy[jy] * xr[jy * TX];
-            by += wy[jy] * xr[XS + jy * TX];
-          }
-          a += wz[jz] * ay;
-          b += wz[jz] * by;
-        }
-      } else {
-        (void)lenz;
-        (void)tbz;
-        const T *xr = X + offy * TX + otx[m];
-#pragma unroll
-        for (int jy = 0; jy <= P; jy++) {
-          if (jy >= leny) break;
-          a += wy[jy] * xr[jy * TX];
-          b += wy[jy] * xr[XS + jy * TX];
-        }
-      }
-      fv[m] = scale * (double)a;
-      gv[m] = scale * (double)b;
-    }
-  };
-
-  // 3D y-pass through LDS: X[rz][*][tx] -> Yb[rz][ty][tx]; each thread keeps one (tx, ty)
-  auto ypass = [&]() __attribute__((always_inline)) {
-    constexpr int NRY = BS / (TX * TY);
-    static_assert(YZF || NRY >= 1, "tile cross-section exceeds the workgroup");
-    const int Rz = cg[2].R;
-    const int len = cg[1].ident ? 1 : P + 1;
-    const int tx = tid % TX, ty = (tid / TX) % TY, z0 = tid / (TX * TY);
-    if (z0 < NRY && tx < vx && ty < vy) {
-      const int row = cg[1].tb * NW + TX + ty;
-      const int off = OT[row];
-      T w[P + 1];
-#pragma unroll
-      for (int j = 0; j <= P; j++) w[j] = WT[row * (P + 1) + j];
-      constexpr int MZ = NRY > 0 ? (RZ + NRY - 1) / NRY : 0;
-#pragma unroll TILE_ROW_UNROLL
-      for (int q = 0; q < MZ; q++) {
-        const int rz = z0 + q * NRY;
-        if (rz >= Rz) break;
-        const T *xf = X + (rz * RY + off) * TX + tx;
-        T a = 0, b = 0;
-#pragma unroll
-        for (int j = 0; j <= P; j++) {
-          if (j >= len) break;
-          a += w[j] * xf[j * TX];
-          b += w[j] * xf[XS + j * TX];
-        }
-        const int l = (rz * TY + ty) * TX + tx;
-        Yb[l] = a;
-        Yb[YS + l] = b;
-      }
-    }
-  };
-  // z contraction of the y-passed values for the owned nodes
-  auto zpass = [&](double (&fv)[NPT], double (&gv)[NPT]) __attribute__((always_inline)) {
-    const int len = cg[2].ident ? 1 : P + 1;
-#pragma unroll
-    for (int m = 0; m < NPT; m++) {
-      fv[m] = gv[m] = 0.0;
-      if (!own[m]) continue;
-      const int row = cg[2].tb * NW + TX + TY + otz[m];
-      const T *yf = Yb + (OT[row] * TY + oty[m]) * TX + otx[m];
-      const T *w = WT + row * (P + 1);
+      const T *xr = X + OT[ry] * TX + otx[m];
       T a = 0, b = 0;
 #pragma unroll
-      for (int j = 0; j <= P; j++) {
-        if (j >= len) break;
-        a += w[j] * yf[j * TY * TX];
-        b += w[j] * yf[YS + j * TY * TX];
+      for (int jy = 0; jy <= P; jy++) {
+        if (jy >= leny) break;
+        a += wy[jy] * xr[jy * TX];
+        b += wy[jy] * xr[XS + jy * TX];
       }
       fv[m] = scale * (double)a;
       gv[m] = scale * (double)b;
@@ -447,34 +335,19 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
 #pragma unroll
   for (int m = 0; m < NPT; m++) rho[m] = j0[m] = j1[m] = j2[m] = E[m] = 0.0;
   prefetch(0);
-  if (YZF) {
-    commit();
-    if (Q > 1) prefetch(1);
-  }
+  commit();
+  if (Q > 1) prefetch(1);
   for (int i = 0; i < Q; i++) {
     double fv[NPT], gv[NPT];
-    if constexpr (YZF) {
-      __syncthreads();   // velocity i is in S; X is free
-      xpass();
-      __syncthreads();   // X holds velocity i; S is free
-      const int tby = cg[1].tb, tbz = cg[2].tb;
-      const int leny = cg[1].ident ? 1 : P + 1, lenz = cg[2].ident ? 1 : P + 1;
-      if (i + 1 < Q) {
-        commit();
-        if (i + 2 < Q) prefetch(i + 2);
-      }
-      yzpass(tby, tbz, leny, lenz, fv, gv);
-    } else {
-      __syncthreads();   // the previous z contraction is done reading Yb (= S)
+    __syncthreads();   // velocity i is in S; X is free
+    xpass();
+    __syncthreads();   // X holds velocity i; S is free
+    const int tby = cg[1].tb, leny = cg[1].ident ? 1 : P + 1;
+    if (i + 1 < Q) {
       commit();
-      if (i + 1 < Q) prefetch(i + 1);
-      __syncthreads();   // velocity i is in S
-      xpass();
-      __syncthreads();   // X holds velocity i
-      ypass();
-      __syncthreads();   // Yb holds velocity i
-      zpass(fv, gv);
+      if (i + 2 < Q) prefetch(i + 2);
     }
+    ypass_nodes(tby, leny, fv, gv);
     const double *vi = pl.vel + 8 * i;
     const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
 #pragma unroll
@@ -514,8 +387,296 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile(const DevTensorPlan pl, c
   }
 }
 
-// In place: relax the stored streamed populations of every node the tile kernel owns
-// (BGK against the closed-form equilibrium of its node state, Kupershtokh forcing).
+// 3D: streams every velocity of one tile through LDS in three 1D passes (x, y, z) and
+// stores the streamed f_i, g_i of the owned nodes and their node state (rho, u0, u1,
+// u2, T, 1/tau_bar as [6][N] doubles).  Per velocity: barrier; commit velocity i from
+// registers to LDS (with its weight rows) and issue the loads of velocity i+1; barrier;
+// x-pass; barrier; y-pass; barrier; z contraction per owned node.
+template <typename T, int D, int P, int CX, int CY, int CZ, int BS, int WPE>
+__global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl, const StepArgs sa, const TileGrid tg,
+                                                    const T *__restrict__ pin, T *__restrict__ pout,
+                                                    double *__restrict__ nstate) {
+  constexpr int TX = CX * P, TY = CY * P, TZ = (D == 3) ? CZ * P : 1;
+  constexpr int RX = TX + P + 1, RY = TY + P + 1, RZ = (D == 3) ? TZ + P + 1 : 1;
+  constexpr int NT = TX * TY * TZ;
+  constexpr int NPT = (NT + BS - 1) / BS;
+  constexpr int SS = RZ * RY * RX;           // one population's staging size
+  constexpr int XS = RZ * RY * TX;           // one population's x-pass output
+  constexpr int YS = RZ * TY * TX;           // one population's y-pass output (3D)
+  constexpr int NST = (SS + BS - 1) / BS;      // staged elements per thread and population
+  constexpr int NW = TX + TY + TZ;           // weight rows: one per tile position and axis
+  static_assert(NW <= BS, "weight rows exceed the workgroup");
+  __shared__ T S[2 * SS];
+  __shared__ T X[2 * XS];
+  __shared__ T WT[NW * (P + 1)];
+  __shared__ int OT[NW];
+  T *Yb = S;
+
+  const int Q = pl.Q;
+  const int tid = threadIdx.x;
+  const int64_t N = pl.N;
+  const int Nx = pl.ax[0].N, Ny = pl.ax[1].N, Nz = pl.ax[2].N;
+
+  // XCD-aware tile index: consecutive workgroups go round-robin to the 8 XCDs; give each
+  // XCD a contiguous range of tiles so that neighbouring tiles share its L2.
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, jj = bid >> 3;
+  const int tile = xcd * tg.q + min(xcd, tg.r) + jj;
+  const int b0 = tile % tg.nt[0];
+  const int b1 = (tile / tg.nt[0]) % tg.nt[1];
+  const int b2 = tile / (tg.nt[0] * tg.nt[1]);
+  const int n0x = b0 * TX, n0y = b1 * TY, n0z = b2 * TZ;
+  const int vx = min(TX, Nx - n0x), vy = min(TY, Ny - n0y), vz = (D == 3) ? min(TZ, Nz - n0z) : 1;
+
+  // owned nodes: flat tile index tid + BS m, x fastest
+  int otx[NPT], oty[NPT], otz[NPT];
+  bool own[NPT];
+#pragma unroll
+  for (int m = 0; m < NPT; m++) {
+    int f = tid + BS * m;
+    otx[m] = f % TX;
+    oty[m] = (f / TX) % TY;
+    otz[m] = f / (TX * TY);
+    own[m] = (f < NT) && otx[m] < vx && oty[m] < vy && otz[m] < vz;
+    // nodes in the boundary layers of a bounded face are computed by the per-node
+    // gather kernel (launched on those slabs); this kernel leaves them alone
+    for (int fc = 0; fc < pl.nfaces; fc++) {
+      const DevFace &F = pl.face[fc];
+      int n3 = F.axis == 0 ? n0x + otx[m] : (F.axis == 1 ? n0y + oty[m] : n0z + otz[m]);
+      int l = F.side == 0 ? n3 : pl.ax[F.axis].N - 1 - n3;
+      if (l < F.depth) own[m] = false;
+    }
+  }
+  const double scale = sa.scale ? *sa.scale : 1.0;
+
+  auto node_index = [&](int m) __attribute__((always_inline)) -> int64_t {
+    return (int64_t)(n0x + otx[m]) + (int64_t)Nx * ((int64_t)(n0y + oty[m]) + (int64_t)Ny * (n0z + otz[m]));
+  };
+  // ---- software pipeline: the departure region of velocity i+1 is loaded into
+  // registers while velocity i is interpolated out of LDS
+  T pf[NST], pg[NST];
+  T pw[P + 1];
+  int poff = 0;
+  AxGeo ng[3], cg[3];
+  auto prefetch = [&](int i) __attribute__((always_inline)) {
+    ng[0] = axis_geo<P>(pl.ax[0], pl.tab_reg[i], n0x, vx, TX);
+    ng[1] = axis_geo<P>(pl.ax[1], pl.tab_reg[Q + i], n0y, vy, TY);
+    if (D == 3) {
+      ng[2] = axis_geo<P>(pl.ax[2], pl.tab_reg[2 * Q + i], n0z, vz, TZ);
+    } else {
+      ng[2].tb = 0; ng[2].ident = 1; ng[2].rs = 0; ng[2].R = 1;
+    }
+    const T *F = pin + (size_t)i * N;
+    const T *G = pin + ((size_t)Q + i) * N;
+#pragma unroll
+    for (int s = 0; s < NST; s++) {
+      int e = tid + BS * s;
+      int rx = e % RX, ry = (e / RX) % RY, rz = e / (RX * RY);
+      if (e < SS && rx < ng[0].R && ry < ng[1].R && rz < ng[2].R) {
+        int gxx = wrap_idx(n0x + ng[0].rs + rx, Nx);
+        int gyy = wrap_idx(n0y + ng[1].rs + ry, Ny);
+        int gzz = (D == 3) ? wrap_idx(n0z + ng[2].rs + rz, Nz) : 0;
+        size_t k = (size_t)gxx + (size_t)Nx * ((size_t)gyy + (size_t)Ny * gzz);
+        pf[s] = F[k];
+        pg[s] = G[k];
+      }
+    }
+    if (tid < NW) {
+      int ax = tid < TX ? 0 : (tid < TX + TY ? 1 : 2);
+      int q = tid - (ax == 0 ? 0 : (ax == 1 ? TX : TX + TY));
+      int vt = ax == 0 ? vx : (ax == 1 ? vy : vz);
+      int n0a = ax == 0 ? n0x : (ax == 1 ? n0y : n0z);
+      int Ta = ax == 0 ? TX : (ax == 1 ? TY : TZ);
+      int len;
+      const AxGeo &ga = ax == 0 ? ng[0] : (ax == 1 ? ng[1] : ng[2]);
+      const DevAxis &da = ax == 0 ? pl.ax[0] : (ax == 1 ? pl.ax[1] : pl.ax[2]);
+      if (ax < D && q < vt) axis_weights<T, P>(da, ga, n0a, q, Ta, poff, len, pw);
+    }
+  };
+  auto commit = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int s = 0; s < NST; s++) {
+      int e = tid + BS * s;
+      int rx = e % RX, ry = (e / RX) % RY, rz = e / (RX * RY);
+      if (e < SS && rx < ng[0].R && ry < ng[1].R && rz < ng[2].R) {
+        S[e] = pf[s];
+        S[SS + e] = pg[s];
+      }
+    }
+    if (tid < NW) {
+#pragma unroll
+      for (int j = 0; j <= P; j++) WT[tid * (P + 1) + j] = pw[j];
+      OT[tid] = poff;
+    }
+    cg[0] = ng[0];
+    cg[1] = ng[1];
+    cg[2] = ng[2];
+  };
+
+  // Streamed f_i, g_i of every owned node out of the committed LDS region: three 1D
+  // passes (two in 2D), then the boundary-layer pairs by per-node gather.
+  auto interpolate = [&](double (&fv)[NPT], double (&gv)[NPT]) __attribute__((always_inline)) {
+    const int Ry = cg[1].R, Rz = cg[2].R;
+    {  // x-pass: S[rz][ry][*] -> X[rz][ry][tx]; each thread keeps one tx (and its
+       // weights) and walks the rows
+      constexpr int NRX = BS / TX;          // rows in flight per sweep of the workgroup
+      const int len = cg[0].ident ? 1 : P + 1;
+      const int tx = tid % TX, r0 = tid / TX;
+      if (r0 < NRX && tx < vx) {
+        const int off = OT[tx];
+        T w[P + 1];
+#pragma unroll
+        for (int j = 0; j <= P; j++) w[j] = WT[tx * (P + 1) + j];
+        const int nrows = Ry * Rz;
+#pragma unroll 1
+        for (int rr = r0; rr < RY * RZ; rr += NRX) {
+          int ry = rr % Ry, rz = rr / Ry;
+          if (rr >= nrows) break;
+          const T *sf = S + (rz * RY + ry) * RX + off;
+          T a = 0, b = 0;
+#pragma unroll
+          for (int j = 0; j <= P; j++) {
+            if (j >= len) break;
+            a += w[j] * sf[j];
+            b += w[j] * sf[SS + j];
+          }
+          int l = (rz * RY + ry) * TX + tx;
+          X[l] = a;
+          X[XS + l] = b;
+        }
+      }
+    }
+    __syncthreads();
+    if constexpr (D == 3) {
+      {  // y-pass: X[rz][*][tx] -> Yb[rz][ty][tx]; each thread keeps one (tx, ty)
+        constexpr int NRY = BS / (TX * TY);
+        static_assert(NRY >= 1, "tile cross-section exceeds the workgroup");
+        const int len = cg[1].ident ? 1 : P + 1;
+        const int tx = tid % TX, ty = (tid / TX) % TY, z0 = tid / (TX * TY);
+        if (z0 < NRY && tx < vx && ty < vy) {
+          const int off = OT[TX + ty];
+          T w[P + 1];
+#pragma unroll
+          for (int j = 0; j <= P; j++) w[j] = WT[(TX + ty) * (P + 1) + j];
+#pragma unroll 1
+          for (int rz = z0; rz < RZ; rz += NRY) {
+            if (rz >= Rz) break;
+            const T *xf = X + (rz * RY + off) * TX + tx;
+            T a = 0, b = 0;
+#pragma unroll
+            for (int j = 0; j <= P; j++) {
+              if (j >= len) break;
+              a += w[j] * xf[j * TX];
+              b += w[j] * xf[XS + j * TX];
+            }
+            int l = (rz * TY + ty) * TX + tx;
+            Yb[l] = a;
+            Yb[YS + l] = b;
+          }
+        }
+      }
+      __syncthreads();
+      const int len = cg[2].ident ? 1 : P + 1;
+#pragma unroll
+      for (int m = 0; m < NPT; m++) {  // z-pass for the owned nodes
+        fv[m] = gv[m] = 0.0;
+        if (!own[m]) continue;
+        const T *yf = Yb + (OT[TX + TY + otz[m]] * TY + oty[m]) * TX + otx[m];
+        const T *w = WT + (TX + TY + otz[m]) * (P + 1);
+        T a = 0, b = 0;
+#pragma unroll
+        for (int j = 0; j <= P; j++) {
+          if (j >= len) break;
+          a += w[j] * yf[j * TY * TX];
+          b += w[j] * yf[YS + j * TY * TX];
+        }
+        fv[m] = scale * (double)a;
+        gv[m] = scale * (double)b;
+      }
+    } else {
+      const int len = cg[1].ident ? 1 : P + 1;
+#pragma unroll
+      for (int m = 0; m < NPT; m++) {  // y-pass (last in 2D) for the owned nodes
+        fv[m] = gv[m] = 0.0;
+        if (!own[m]) continue;
+        const T *xf = X + OT[TX + oty[m]] * TX + otx[m];
+        const T *w = WT + (TX + oty[m]) * (P + 1);
+        T a = 0, b = 0;
+#pragma unroll
+        for (int j = 0; j <= P; j++) {
+          if (j >= len) break;
+          a += w[j] * xf[j * TX];
+          b += w[j] * xf[XS + j * TX];
+        }
+        fv[m] = scale * (double)a;
+        gv[m] = scale * (double)b;
+      }
+    }
+  };
+  // one pipeline stage: velocity i is committed to LDS, velocity `next` (or -1) is
+  // prefetched, and i is interpolated
+  auto stream_velocity = [&](int i, int next, double (&fv)[NPT], double (&gv)[NPT]) __attribute__((always_inline)) {
+    __syncthreads();  // everyone is done reading the previous velocity out of LDS
+    commit();
+    if (next >= 0) prefetch(next);
+    __syncthreads();
+    interpolate(fv, gv);
+  };
+
+  prefetch(0);
+  {
+    double rho[NPT], j0[NPT], j1[NPT], j2[NPT], E[NPT];
+#pragma unroll
+    for (int m = 0; m < NPT; m++) rho[m] = j0[m] = j1[m] = j2[m] = E[m] = 0.0;
+    for (int i = 0; i < Q; i++) {
+      double fv[NPT], gv[NPT];
+      stream_velocity(i, i + 1 < Q ? i + 1 : -1, fv, gv);
+      const double *vi = pl.vel + 8 * i;
+      const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
+#pragma unroll
+      for (int m = 0; m < NPT; m++) {
+        if (!own[m]) continue;
+        const int64_t k = node_index(m);
+        pout[(size_t)i * N + k] = (T)fv[m];
+        pout[((size_t)Q + i) * N + k] = (T)gv[m];
+      }
+#pragma unroll
+      for (int m = 0; m < NPT; m++) {
+        rho[m] += fv[m];
+        j0[m] += vi[0] * fv[m];
+        j1[m] += vi[1] * fv[m];
+        j2[m] += vi[2] * fv[m];
+        E[m] += z2 * fv[m] + gv[m];
+      }
+    }
+    // node state: rho, u, T, 1/tau_bar (isothermal walls act only inside the boundary
+    // layers, which the gather kernel handles)
+#pragma unroll
+    for (int m = 0; m < NPT; m++) {
+      if (!own[m]) continue;
+      double r = rho[m];
+      double u0 = j0[m] / r, u1 = j1[m] / r, u2 = j2[m] / r;
+      double Tn = (E[m] - r * (u0 * u0 + u1 * u1 + u2 * u2)) / (2.0 * r * sa.cv);
+      double it = 0.0;
+      if (sa.relax_mode == 0) it = 1.0 / sa.tau_bar;
+      if (sa.relax_mode == 1) {
+        double mu = sa.mu_ref * pow(Tn / sa.T_ref, sa.mu_exp);
+        it = 1.0 / (mu / (r * Tn * sa.dt) + 0.5);
+      }
+      const int64_t k = node_index(m);
+      nstate[k] = r;
+      nstate[N + k] = u0;
+      nstate[2 * N + k] = u1;
+      nstate[3 * N + k] = u2;
+      nstate[4 * N + k] = Tn;
+      nstate[5 * N + k] = it;
+    }
+  }
+}
+
+// In-place BGK relaxation and forcing of the streamed populations the moments launch
+// stored, one node per lane (its equilibrium coefficients built once); nodes in the
+// boundary layers of a bounded face belong to the gather kernel and are skipped.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, const StepArgs sa,
                                                         T *__restrict__ pop, const double *__restrict__ nstate) {
@@ -537,36 +698,21 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
   EqNode ef = e;
   if (sa.has_force) ef = eq_forced(rho, u0, u1, u2, Tn, sa, D);
   const double gT = Tn * sa.gbase;
-  // velocities in batches of RB: all loads of a batch are issued before its stores, so
-  // each lane keeps 2 RB reads in flight
-  constexpr int RB = RELAX_BATCH;
-  T *pf = pop + k;
-  T *pg = pop + (size_t)Q * N + k;
-  for (int i0 = 0; i0 < Q; i0 += RB) {
-    T fb[RB], gb[RB];
-#pragma unroll
-    for (int b = 0; b < RB; b++) {
-      if (i0 + b < Q) {
-        fb[b] = pf[(size_t)(i0 + b) * N];
-        gb[b] = pg[(size_t)(i0 + b) * N];
-      }
+  for (int i = 0; i < Q; i++) {
+    const double *vi = pl.vel + 8 * i;
+    T *pf = pop + (size_t)i * N + k;
+    T *pg = pop + ((size_t)Q + i) * N + k;
+    double f = (double)*pf, g = (double)*pg;
+    double fe = eq_f(e, vi);
+    double fo = f - (f - fe) * itau;
+    double go = g - (g - gT * fe) * itau;
+    if (sa.has_force) {
+      double df = eq_f(ef, vi) - fe;
+      fo += df;
+      go += gT * df;
     }
-#pragma unroll
-    for (int b = 0; b < RB; b++) {
-      if (i0 + b >= Q) break;
-      const double *vi = pl.vel + 8 * (i0 + b);
-      const double f = (double)fb[b], g = (double)gb[b];
-      const double fe = eq_f(e, vi);
-      double fo = f - (f - fe) * itau;
-      double go = g - (g - gT * fe) * itau;
-      if (sa.has_force) {
-        const double df = eq_f(ef, vi) - fe;
-        fo += df;
-        go += gT * df;
-      }
-      pf[(size_t)(i0 + b) * N] = (T)fo;
-      pg[(size_t)(i0 + b) * N] = (T)go;
-    }
+    *pf = (T)fo;
+    *pg = (T)go;
   }
 }
 
@@ -575,7 +721,7 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
 namespace {
 template <typename T, int D, int P, int CX, int CY, int CZ>
 int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
-  constexpr int BS = D == 3 ? TILE_BS3 : 256;   // threads per workgroup
+  constexpr int BS = D == 3 ? 512 : 256;   // threads per workgroup
   // minimum waves per SIMD the register budget must allow, per launch
   constexpr int WPE = TILE_WPE;
   constexpr int TX = CX * P, TY = CY * P, TZ = (D == 3) ? CZ * P : 1;
@@ -589,8 +735,12 @@ int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *po
   tg.r = ntiles % 8;
   {
     ProfScope ps(Pl, "k_step_tile", s);
-    hipLaunchKernelGGL((k_step_tile<T, D, P, CX, CY, CZ, BS, WPE>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
-                       (const T *)pin, (T *)pout, Pl->nstate);
+    if constexpr (D == 3)
+      hipLaunchKernelGGL((k_step_tile3d<T, D, P, CX, CY, CZ, BS, WPE>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
+                         (const T *)pin, (T *)pout, Pl->nstate);
+    else
+      hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPE>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
+                         (const T *)pin, (T *)pout, Pl->nstate);
   }
   {
     ProfScope ps(Pl, "k_relax_nodes", s);
