@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-ogrid", action="store_true", help="skip the curvilinear O-grid workload")
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction (mixing layer) workload")
     ap.add_argument("--no-extra", action="store_true", help="skip the C1-R (2D roofline-scale) and C4 (channel) lines")
     ap.add_argument("--kernel", choices=["auto", "gather", "tiled"], default="auto")
@@ -55,15 +55,16 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_from_profiles(prec):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources (else None)."""
+def traffic_from_profiles(key):
+    """HBM bytes per launch of a workload's dominant kernel (key: tgv_f64, ogrid_f32, ...)
+    from the committed rocprofv3 counter summary, if it was taken on the current kernel
+    sources (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
-        e = d.get(prec)
+        e = d.get(key)
         if not e or e.get("kernel_source_hash") != kernel_source_hash():
             return None
         return e.get("bytes_per_launch")
@@ -518,27 +519,29 @@ def main():
         "config": {"workload": f"3D periodic compressible Taylor-Green vortex Ma 0.8 Re 400, "
                                f"{args.ncell}^3 cells p=3 GLL ({r64['N']} nodes), D3V125 Gauss-Hermite, FP64",
                    "nodes": r64["N"], "Q": r64["Q"], "order_p": 3, "velocity_set": "D3V125"},
-        "roofline": roofline(r64, traffic_from_profiles("f64")),
+        "roofline": roofline(r64, traffic_from_profiles("tgv_f64")),
         "cpu_baseline": cpu,
         "kernels": r64["kernels"],
     }
     if r32:
         out["fp32"] = {"value": round(r32["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(r32["ms_per_step"], 4),
-                       "roofline": roofline(r32, traffic_from_profiles("f32")), "kernels": r32["kernels"]}
+                       "roofline": roofline(r32, traffic_from_profiles("tgv_f32")), "kernels": r32["kernels"]}
     if og:
         out["ogrid"] = {
             "workload": "supersonic NACA 0012 O-grid Ma 1.5 Re 1e4, 256x128 cells p=4 GLL (525312 nodes), D2V25, "
                         "curvilinear CSR plan",
             **{prec: {"value": round(v["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(v["ms_per_step"], 4),
                       "bytes_per_update": v["bpu"], "plan_build_s": round(v["plan_build_s"], 2),
-                      "roofline": roofline(v), "finite": v["finite"]} for prec, v in og.items()}}
+                      "roofline": roofline(v, traffic_from_profiles("ogrid_" + prec)), "finite": v["finite"]}
+               for prec, v in og.items()}}
     names = {"c1r": "2D periodic shear wave, 1024^2 cells p=4 GLL (16.8M nodes), D2V25",
              "c4": "3D supersonic channel Ma_b 1.5 Re_b 3000, 128x96x64 cells p=2 (6.3M nodes), D3V125, "
                    "isothermal walls, forcing held by the PI force controller and mass rescaling, both every 10 steps"}
     for key, v in extra.items():
         case, prec = key.split("_")
         out[key] = {"workload": names[case], "dtype": prec, "value": round(v["gqups"], 4), "unit": "GQUPS",
-                    "ms_per_step": round(v["ms_per_step"], 4), "roofline": roofline(v), "kernels": v["kernels"],
+                    "ms_per_step": round(v["ms_per_step"], 4), "roofline": roofline(v, traffic_from_profiles(key)),
+                    "kernels": v["kernels"],
                     "finite": v["finite"], **({"force_control": v["force_control"]} if "force_control" in v else {})}
     if lrn:
         out["learned"] = lrn
