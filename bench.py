@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-ogrid", action="store_true", help="skip the curvilinear O-grid workload")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction (mixing layer) workload")
+    ap.add_argument("--learned-mach", default="0.7",
+                    help="convective Mach numbers of the learned-correction legs, comma separated (first one is 'learned')")
     ap.add_argument("--no-extra", action="store_true", help="skip the C1-R (2D roofline-scale) and C4 (channel) lines")
     ap.add_argument("--kernel", choices=["auto", "gather", "tiled"], default="auto")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -498,9 +500,17 @@ def main():
                 extra[f"{case}_{prec}"] = tensor_case_leg(case, prec, max(10, args.steps // 5), 3)
                 print(f"# {case} {prec} done: {extra[f'{case}_{prec}']['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
     lrn = None
+    lrn_more = {}
     if not args.no_learned:
-        lrn = learned_leg()
-        print(f"# learned done: time-to-solution ratio {lrn['time_to_solution_ratio']}", file=sys.stderr, flush=True)
+        machs = [float(x) for x in args.learned_mach.split(",")]
+        for i, mc in enumerate(machs):
+            r = learned_leg(Ma_c=mc)
+            print(f"# learned Ma_c {mc} done: time-to-solution ratio {r['time_to_solution_ratio']}", file=sys.stderr,
+                  flush=True)
+            if i == 0:
+                lrn = r
+            else:
+                lrn_more[str(mc)] = r
     cal = copy_calibration() if args.copy_calibration else None
     cpu = None if args.no_cpu else cpu_leg(args.ncell, args.cpu_steps)
     out = {
@@ -545,6 +555,8 @@ def main():
                     "finite": v["finite"], **({"force_control": v["force_control"]} if "force_control" in v else {})}
     if lrn:
         out["learned"] = lrn
+        if lrn_more:
+            out["learned_other_mach"] = lrn_more
     if cal:
         out["copy_calibration"] = cal
     print(json.dumps(out), flush=True)
