@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--ncell", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--precision-steps", type=int, default=1000,
+                    help="steps of the side-by-side FP64 / FP32 Taylor-Green comparison (0 = skip)")
     ap.add_argument("--no-ogrid", action="store_true", help="skip the curvilinear O-grid workload")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction (mixing layer) workload")
@@ -134,6 +136,69 @@ def gpu_leg(prec, steps, warmup, ncell, kernel="auto"):
     updates = N * Q
     return summarize(prof, total_ms, wall, steps, updates, BYTES_PER_UPDATE[prec],
                      finite=all(math.isfinite(x) for x in tot), N=N, Q=Q, mass=float(tot[0]))
+
+
+def precision_leg(ncell, steps=1000, every=100):
+    """The Taylor-Green workload in FP64 and in FP32 storage side by side from the same
+    nodal fields: per field (rho, u over all components, T) max_k |q32 - q64| / max_k |q64|
+    every `every` steps, and the volume-weighted kinetic energy of each run."""
+    import torch
+    import numpy as np
+    import paper_2412_09051_amd as S
+    import workloads as W
+    mesh, phys = W.tgv_case(ncell=ncell)
+    m = S.sllbm_mesh_build(mesh)
+    vs = S.sllbm_velset_gauss_hermite(3, 5, phys.T0)
+    prm = S.Params.from_physics(phys)
+    xyz = S.sllbm_mesh_nodes(m)
+    rho, u, T = W.tgv_fields(xyz)
+    V = torch.tensor(S.sllbm_mesh_volumes(m), device="cuda")
+    dev = torch.device("cuda")
+    runs = {}
+    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        plan = S.sllbm_interp_plan(m, vs, phys.dt, S.SLLBM_F32 if prec == "f32" else S.SLLBM_F64)
+        N, Q = plan.N, plan.Q
+        a = torch.empty(2 * Q * N, dtype=dt, device=dev)
+        b = torch.empty_like(a)
+        S.sllbm_init_equilibrium(plan, prm, torch.tensor(rho, device=dev),
+                                 torch.tensor(np.ascontiguousarray(u.T), device=dev), torch.tensor(T, device=dev), a)
+        runs[prec] = [plan, a, b]
+    hist = {"step": [], "rho": [], "u": [], "T": [], "ke_f64": [], "ke_f32": []}
+    fields = {}
+
+    def moments(plan, pop):
+        N = plan.N
+        r = torch.empty(N, dtype=torch.float64, device=dev)
+        uu = torch.empty(3 * N, dtype=torch.float64, device=dev)
+        t = torch.empty(N, dtype=torch.float64, device=dev)
+        S.sllbm_moments(plan, prm, pop, r, uu, t)
+        return r, uu.view(3, N), t
+
+    for n in range(steps + 1):
+        if n % every == 0:
+            for prec in ("f64", "f32"):
+                fields[prec] = moments(runs[prec][0], runs[prec][1])
+            r64, u64, t64 = fields["f64"]
+            r32, u32, t32 = fields["f32"]
+            hist["step"].append(n)
+            hist["rho"].append(float((r32 - r64).abs().max() / r64.abs().max()))
+            hist["u"].append(float((u32 - u64).abs().max() / u64.abs().max()))
+            hist["T"].append(float((t32 - t64).abs().max() / t64.abs().max()))
+            for prec in ("f64", "f32"):
+                r, uu, _ = fields[prec]
+                hist["ke_" + prec].append(float((0.5 * r * (uu * uu).sum(0) * V).sum() / V.sum()))
+        if n == steps:
+            break
+        for prec in ("f64", "f32"):
+            plan, a, b = runs[prec]
+            S.sllbm_step(plan, prm, a, b)
+            runs[prec][1], runs[prec][2] = b, a
+    torch.cuda.synchronize()
+    del runs
+    torch.cuda.empty_cache()
+    return {"workload": f"3D Taylor-Green vortex {ncell}^3 cells p=3, FP32 storage against FP64, same initial fields",
+            "steps": steps, "max_rel_diff_at_end": {k: round(hist[k][-1], 9) for k in ("rho", "u", "T")},
+            "history": {k: [round(x, 10) for x in v] for k, v in hist.items()}}
 
 
 def tensor_case_leg(case, prec, steps, warmup):
@@ -499,6 +564,11 @@ def main():
             for prec in precs:
                 extra[f"{case}_{prec}"] = tensor_case_leg(case, prec, max(10, args.steps // 5), 3)
                 print(f"# {case} {prec} done: {extra[f'{case}_{prec}']['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
+    prec_cmp = None
+    if not args.no_fp32 and args.precision_steps > 0:
+        prec_cmp = precision_leg(args.ncell, args.precision_steps)
+        print(f"# FP32 vs FP64 after {args.precision_steps} steps: {prec_cmp['max_rel_diff_at_end']}", file=sys.stderr,
+              flush=True)
     lrn = None
     lrn_more = {}
     if not args.no_learned:
@@ -553,6 +623,8 @@ def main():
                     "ms_per_step": round(v["ms_per_step"], 4), "roofline": roofline(v, traffic_from_profiles(key)),
                     "kernels": v["kernels"],
                     "finite": v["finite"], **({"force_control": v["force_control"]} if "force_control" in v else {})}
+    if prec_cmp:
+        out["fp32_vs_fp64"] = prec_cmp
     if lrn:
         out["learned"] = lrn
         if lrn_more:

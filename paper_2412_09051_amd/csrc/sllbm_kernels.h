@@ -37,9 +37,11 @@ constexpr int kTileTabs = 5;
 
 // Cell-aligned tile (cells per axis) of the LDS-tiled step kernel for (dim, order).
 template <int D, int P> struct TileShape;
+// 2D tiles hold at most 256 nodes: one node per lane of a 256-thread workgroup, so that the
+// single-pass kernel keeps a node's streamed values in that lane's registers
 template <> struct TileShape<2, 2> { static constexpr int CX = 8, CY = 8, CZ = 1; };
-template <> struct TileShape<2, 3> { static constexpr int CX = 8, CY = 4, CZ = 1; };
-template <> struct TileShape<2, 4> { static constexpr int CX = 8, CY = 4, CZ = 1; };
+template <> struct TileShape<2, 3> { static constexpr int CX = 8, CY = 3, CZ = 1; };
+template <> struct TileShape<2, 4> { static constexpr int CX = 8, CY = 2, CZ = 1; };
 #ifndef TILE_3_2
 #define TILE_3_2 4, 4, 4
 #endif

@@ -29,6 +29,10 @@ namespace sllbm {
 #define TILE_WPE 4
 #endif
 
+// 2D plans with this many velocities (D2V25) run the single-pass tile kernel, at 3 waves
+// per SIMD (FP64: 168 VGPRs and a 36-byte spill, which beats 2 waves without one)
+constexpr int kStashQ = 25;
+
 struct TileGrid {
   int nt[3];   // tiles per axis
   int q, r;    // ntiles = 8 q + r (XCD remap)
@@ -125,7 +129,7 @@ __device__ __forceinline__ int wrap_idx(int g, int N) {
 //   node straight out of X; store; moments.
 // So the loads of a velocity are in flight for a whole iteration, and the y work of
 // velocity i overlaps the staging of i+1.
-template <typename T, int D, int P, int CX, int CY, int CZ, int BS, int WPE>
+template <typename T, int D, int P, int CX, int CY, int CZ, int BS, int WPE, int QR>
 __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl, const StepArgs sa, const TileGrid tg,
                                                     const T *__restrict__ pin, T *__restrict__ pout,
                                                     double *__restrict__ nstate) {
@@ -334,11 +338,8 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
   double rho[NPT], j0[NPT], j1[NPT], j2[NPT], E[NPT];
 #pragma unroll
   for (int m = 0; m < NPT; m++) rho[m] = j0[m] = j1[m] = j2[m] = E[m] = 0.0;
-  prefetch(0);
-  commit();
-  if (Q > 1) prefetch(1);
-  for (int i = 0; i < Q; i++) {
-    double fv[NPT], gv[NPT];
+  // one velocity: x-pass, commit of the next one, y contraction, moments
+  auto velocity = [&](int i, double (&fv)[NPT], double (&gv)[NPT]) __attribute__((always_inline)) {
     __syncthreads();   // velocity i is in S; X is free
     xpass();
     __syncthreads();   // X holds velocity i; S is free
@@ -352,15 +353,43 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
     const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
 #pragma unroll
     for (int m = 0; m < NPT; m++) {
-      if (!own[m]) continue;
-      const int64_t k = node_index(m);
-      pout[(size_t)i * N + k] = (T)fv[m];
-      pout[((size_t)Q + i) * N + k] = (T)gv[m];
       rho[m] += fv[m];
       j0[m] += vi[0] * fv[m];
       j1[m] += vi[1] * fv[m];
       j2[m] += vi[2] * fv[m];
       E[m] += z2 * fv[m] + gv[m];
+    }
+  };
+  // QR > 0 (Q = QR): the streamed values stay in registers and every owned node is
+  // relaxed and stored at the end, a single pass over the populations; QR = 0: the
+  // streamed values are stored and a second launch relaxes them
+  constexpr int QL = QR > 0 ? QR : 1;
+  T fs[NPT][QL], gs[NPT][QL];
+  prefetch(0);
+  commit();
+  if (Q > 1) prefetch(1);
+  if constexpr (QR > 0) {
+#pragma unroll
+    for (int i = 0; i < QR; i++) {
+      double fv[NPT], gv[NPT];
+      velocity(i, fv, gv);
+#pragma unroll
+      for (int m = 0; m < NPT; m++) {
+        fs[m][i] = (T)fv[m];
+        gs[m][i] = (T)gv[m];
+      }
+    }
+  } else {
+    for (int i = 0; i < Q; i++) {
+      double fv[NPT], gv[NPT];
+      velocity(i, fv, gv);
+#pragma unroll
+      for (int m = 0; m < NPT; m++) {
+        if (!own[m]) continue;
+        const int64_t k = node_index(m);
+        pout[(size_t)i * N + k] = (T)fv[m];
+        pout[((size_t)Q + i) * N + k] = (T)gv[m];
+      }
     }
   }
   // node state: rho, u, T, 1/tau_bar (isothermal walls act only inside the boundary
@@ -378,12 +407,44 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
       it = 1.0 / (mu / (r * Tn * sa.dt) + 0.5);
     }
     const int64_t k = node_index(m);
-    nstate[k] = r;
-    nstate[N + k] = u0;
-    nstate[2 * N + k] = u1;
-    nstate[3 * N + k] = u2;
-    nstate[4 * N + k] = Tn;
-    nstate[5 * N + k] = it;
+    if constexpr (QR > 0) {
+      // BGK relaxation and Kupershtokh forcing of the stored (rounded) streamed values,
+      // as the relaxation launch does for the two-launch path
+      if (sa.relax_mode == 2) {
+#pragma unroll
+        for (int i = 0; i < QR; i++) {
+          pout[(size_t)i * N + k] = fs[m][i];
+          pout[((size_t)QR + i) * N + k] = gs[m][i];
+        }
+        continue;
+      }
+      const EqNode e = eq_prepare(r, u0, u1, u2, Tn, sa, D);
+      EqNode ef = e;
+      if (sa.has_force) ef = eq_forced(r, u0, u1, u2, Tn, sa, D);
+      const double gT = Tn * sa.gbase;
+#pragma unroll
+      for (int i = 0; i < QR; i++) {
+        const double *vi = pl.vel + 8 * i;
+        const double f = (double)fs[m][i], g = (double)gs[m][i];
+        const double fe = eq_f(e, vi);
+        double fo = f - (f - fe) * it;
+        double go = g - (g - gT * fe) * it;
+        if (sa.has_force) {
+          const double df = eq_f(ef, vi) - fe;
+          fo += df;
+          go += gT * df;
+        }
+        pout[(size_t)i * N + k] = (T)fo;
+        pout[((size_t)QR + i) * N + k] = (T)go;
+      }
+    } else {
+      nstate[k] = r;
+      nstate[N + k] = u0;
+      nstate[2 * N + k] = u1;
+      nstate[3 * N + k] = u2;
+      nstate[4 * N + k] = Tn;
+      nstate[5 * N + k] = it;
+    }
   }
 }
 
@@ -733,13 +794,23 @@ int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *po
   int ntiles = tg.nt[0] * tg.nt[1] * tg.nt[2];
   tg.q = ntiles / 8;
   tg.r = ntiles % 8;
+  if constexpr (D == 2) {
+    if (tp.Q == kStashQ) {
+      // single pass: the 2Q streamed values of a node stay in registers
+      constexpr int WPES = 3;
+      ProfScope ps(Pl, "k_step_tile", s);
+      hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPES, kStashQ>), dim3(ntiles), dim3(BS), 0, s, tp, a,
+                         tg, (const T *)pin, (T *)pout, Pl->nstate);
+      return SLLBM_OK;
+    }
+  }
   {
     ProfScope ps(Pl, "k_step_tile", s);
     if constexpr (D == 3)
       hipLaunchKernelGGL((k_step_tile3d<T, D, P, CX, CY, CZ, BS, WPE>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
                          (const T *)pin, (T *)pout, Pl->nstate);
     else
-      hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPE>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
+      hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPE, 0>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
                          (const T *)pin, (T *)pout, Pl->nstate);
   }
   {
