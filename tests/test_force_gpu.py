@@ -78,7 +78,9 @@ def test_controlled_channel_matches_the_oracle(kernel):
             S.sllbm_force_update(g.plan, g.a, dt=every * phys.dt, **ctl)
             st = S.sllbm_force_read(g.plan)
             say(n, "force", F[0], st["force"][0])
-            assert abs(st["force"][0] - F[0]) <= 1e-12 * abs(F[0]), (n, st["force"][0], F[0])
+            # the controller multiplies the mean momentum's error (1e-12 relative) by its gains
+            scale = abs(phys.force[0]) + ctl["kp"] * abs(ctl["target"]) + ctl["ki"] * abs(c.integral)
+            assert abs(st["force"][0] - F[0]) <= 1e-12 * scale, (n, st["force"][0], F[0])
             assert abs(st["mean_momentum"] - c.mean) <= 1e-12 * abs(c.mean)
         pop = o.step(pop)
         S.sllbm_step(g.plan, prm, g.a, g.b)

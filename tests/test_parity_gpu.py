@@ -273,3 +273,62 @@ def test_plan_profile_counts_every_launch():
     assert all(ms > 0 for ms, _ in prof.values())
     g.run(2)
     assert g.S.sllbm_plan_profile_read(g.plan) == prof   # stopped: nothing more recorded
+
+
+# ------------------------------------------------------------------ 2D single-pass tile kernel
+
+def _shear_2d_tiled(relax_mode, force=(0.0, 0.0)):
+    """A 2D periodic mesh large enough for the tiled kernel (its single pass with D2V25)."""
+    mesh, phys = W.shear_wave_case(ncell=12, p=4)
+    phys = copy.copy(phys)
+    phys.relax_mode = relax_mode
+    if relax_mode == 1:
+        phys.mu_ref, phys.T_ref, phys.mu_exp = 0.02, 1.0, 0.7
+    phys.force = tuple(force) + (0.0,)
+    return mesh, phys
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_2d_single_pass_viscosity_law_and_force(prec, tol):
+    """mu(T) power law and a Kupershtokh body force through the single-pass 2D tile kernel."""
+    say("case 2D single pass, relax mode 1 + force", prec)
+    mesh, phys = _shear_2d_tiled(1, force=(0.03, -0.02))
+    _run_compare(mesh, phys, prec, lambda x: W.shear_wave_fields(x, amp=0.05, noise=0.01, seed=12), 40, tol,
+                 compare_pops=(prec == "f64"), kernel=TILED)
+
+
+def test_2d_single_pass_pure_streaming():
+    """relax mode 2: the kernel stores the streamed values as they are."""
+    say("case 2D single pass, pure streaming")
+    mesh, phys = _shear_2d_tiled(2)
+    _run_compare(mesh, phys, "f64", lambda x: W.random_fields(x.shape[0], 2, seed=13), 6, TOL64, kernel=TILED)
+
+
+def test_2d_single_pass_controlled_force():
+    """The device-side force controller on the single-pass 2D kernel: force history and
+    populations against the oracle's controller."""
+    import dataclasses
+    say("case 2D single pass, force controller")
+    mesh, phys = _shear_2d_tiled(0, force=(0.02, 0.0))
+    o, g, (rho, u, T) = _pair(mesh, phys, "f64", lambda x: W.shear_wave_fields(x, amp=0.05, seed=14), TILED)
+    pop = o.init(rho, u, T)
+    g.init(rho, u, T)
+    ctl = {"axis": 0, "target": 0.9, "kp": 3.0, "ki": 2.0}
+    c = oracle.ForceController(o, phys.force, **ctl)
+    g.S.sllbm_force_reset(g.plan, phys.force)
+    prm = dataclasses.replace(g.prm, force_device=1)
+    for n in range(9):
+        if n % 3 == 0:
+            F = c.update(pop, 3 * phys.dt)
+            g.S.sllbm_force_update(g.plan, g.a, dt=3 * phys.dt, **ctl)
+            st = g.S.sllbm_force_read(g.plan)
+            # the controller multiplies the mean momentum's error (1e-12 relative) by its gains
+            scale = abs(phys.force[0]) + ctl["kp"] * abs(ctl["target"]) + ctl["ki"] * abs(c.integral)
+            assert abs(st["force"][0] - F[0]) <= 1e-12 * scale, (n, st["force"][0], F[0])
+        pop = o.step(pop)
+        g.S.sllbm_step(g.plan, prm, g.a, g.b)
+        g.a, g.b = g.b, g.a
+    g.torch.cuda.synchronize()
+    e = rel_err(g.pop(), pop)
+    say("pop error", e)
+    assert e <= TOL64
