@@ -76,13 +76,18 @@ def traffic_from_profiles(key):
         return None
 
 
+# the sources of the step kernels whose HBM traffic profiles/traffic.json records, and the
+# device headers they include
+KERNEL_SOURCES = ("sllbm_tile.hip", "sllbm_csr_kernel.hip", "sllbm_kernels.hip", "sllbm_device_common.h",
+                  "sllbm_kernels.h")
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2412_09051_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -518,6 +523,28 @@ def copy_calibration():
     return {"bytes_read": 8 * n, "bytes_written": 8 * n, "launches": 3}
 
 
+def copy_ceiling(reps=10):
+    """The practical HBM ceiling: a plain 1 GiB device-to-device copy, timed with events
+    (bytes read + bytes written per second)."""
+    import torch
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBs": round(2 * 8 * n / (ms * 1e-3) / 1e9, 1), "bytes": 2 * 8 * n, "ms": round(ms, 4)}
+
+
 def cpu_leg(ncell, steps):
     """The oracle, as it stands, on the host cores: one (or more) full step(s) of the
     same workload in FP64."""
@@ -582,6 +609,8 @@ def main():
             else:
                 lrn_more[str(mc)] = r
     cal = copy_calibration() if args.copy_calibration else None
+    ceil = copy_ceiling()
+    print(f"# device copy: {ceil['GBs']} GB/s", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_leg(args.ncell, args.cpu_steps)
     out = {
         "metric": "GQUPS (node x velocity updates/s, f and g together)",
@@ -629,6 +658,8 @@ def main():
         out["learned"] = lrn
         if lrn_more:
             out["learned_other_mach"] = lrn_more
+    out["copy_ceiling"] = dict(ceil, note="1 GiB device-to-device copy, read + written bytes per second: the "
+                                          "practical HBM peak; step_frac and frac are against 8 TB/s")
     if cal:
         out["copy_calibration"] = cal
     print(json.dumps(out), flush=True)

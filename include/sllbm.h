@@ -36,6 +36,7 @@
 #ifndef SLLBM_H
 #define SLLBM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -164,6 +165,16 @@ int sllbm_plan_profile(sllbm_plan p, int enable);
  * exceed max), or a negative error code. */
 int sllbm_plan_profile_read(sllbm_plan p, int max, char (*names)[32], double *total_ms, int64_t *launches);
 void sllbm_plan_destroy(sllbm_plan p);
+
+/* Device memory of the library's own objects (plans, their learned-mode buffers, networks).
+ * By default hipMalloc / hipFree.  A caller that manages device memory itself (a caching
+ * allocator, a memory pool) passes alloc(bytes, ctx) -> device pointer (NULL on failure;
+ * the memory must be on the device current at the call and stay valid until release) and
+ * release(ptr, ctx); both NULL restores the default.  Giving only one is EINVAL.  Each
+ * object keeps the functions current when it was created and releases its memory through
+ * them on destroy (after the caller's work on it has finished).  Set it before creating
+ * handles; the setting itself is guarded by a lock. */
+int sllbm_set_allocator(void *(*alloc)(size_t bytes, void *ctx), void (*release)(void *ptr, void *ctx), void *ctx);
 
 /* Physical parameters of a step. */
 typedef struct {

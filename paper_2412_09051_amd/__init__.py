@@ -90,7 +90,7 @@ _lib.sllbm_last_error.restype = ctypes.c_char_p
 for _name in ("sllbm_mesh_build", "sllbm_mesh_nodes", "sllbm_mesh_volumes", "sllbm_velset_gauss_hermite",
               "sllbm_interp_plan", "sllbm_plan_info", "sllbm_plan_select_kernel", "sllbm_init_equilibrium",
               "sllbm_step", "sllbm_moments", "sllbm_plan_profile", "sllbm_plan_profile_read",
-              "sllbm_force_reset", "sllbm_force_update", "sllbm_force_read"):
+              "sllbm_force_reset", "sllbm_force_update", "sllbm_force_read", "sllbm_set_allocator"):
     getattr(_lib, _name).restype = ctypes.c_int
 _lib.sllbm_mesh_destroy.restype = None
 _lib.sllbm_plan_destroy.restype = None
@@ -352,6 +352,29 @@ def sllbm_moments(plan: Plan, params: Params, pop, rho=None, u=None, T=None, tot
     return tot
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_allocator_refs = []      # the callbacks must outlive every object created with them
+
+
+def sllbm_set_allocator(alloc=None, release=None):
+    """alloc(nbytes) -> int device pointer (0 on failure), release(ptr); both None restores
+    hipMalloc / hipFree.  Objects created afterwards allocate through them."""
+    if alloc is None and release is None:
+        _check(_lib.sllbm_set_allocator(None, None, None), "sllbm_set_allocator")
+        return
+    a = _ALLOC_FN(lambda n, ctx: alloc(int(n)) or None)
+    r = _RELEASE_FN(lambda p, ctx: release(int(p)))
+    _allocator_refs.append((a, r))
+    _check(_lib.sllbm_set_allocator(a, r, None), "sllbm_set_allocator")
+
+
+def use_torch_allocator():
+    """Device memory of objects created afterwards comes from torch's caching allocator."""
+    import torch
+    sllbm_set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n), torch.cuda.caching_allocator_delete)
+
+
 def sllbm_force_reset(plan: Plan, force0, stream=None):
     f = np.zeros(3)
     f[:len(force0)] = force0
@@ -488,7 +511,8 @@ def sllbm_mlp_train_step(m: Mlp, x, t, lr: float, want_loss: bool = True, stream
 
 __all__ = ["sllbm_velset_gauss_hermite", "sllbm_mesh_build", "sllbm_mesh_nodes", "sllbm_mesh_volumes",
            "sllbm_interp_plan", "sllbm_plan_info", "sllbm_plan_select_kernel", "sllbm_init_equilibrium", "sllbm_step", "sllbm_moments",
-           "sllbm_force_reset", "sllbm_force_update", "sllbm_force_read", "Params", "Plan", "Mesh", "SllbmError", "SLLBM_F64", "SLLBM_F32", "LIB_PATH",
+           "sllbm_force_reset", "sllbm_force_update", "sllbm_force_read", "sllbm_set_allocator", "use_torch_allocator",
+           "Params", "Plan", "Mesh", "SllbmError", "SLLBM_F64", "SLLBM_F32", "LIB_PATH",
            "Mlp", "sllbm_mlp_create", "sllbm_mlp_get_params", "sllbm_mlp_set_params", "sllbm_features",
            "sllbm_mlp_forward", "sllbm_mlp_correct", "sllbm_learned_targets", "sllbm_restrict", "sllbm_mlp_gradient",
            "sllbm_mlp_train_step", "n_features"]

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <limits>
@@ -26,8 +27,8 @@ int upload(sllbm_plan_s *P, const std::vector<V> &h, const V **dptr) {
   if (h.empty()) { *dptr = nullptr; return SLLBM_OK; }
   void *d = nullptr;
   size_t bytes = sizeof(V) * h.size();
-  hipError_t e = hipMalloc(&d, bytes);
-  if (e != hipSuccess) return fail(SLLBM_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  hipError_t e = P->dalloc.get(&d, bytes);
+  if (e != hipSuccess) return fail(SLLBM_ENOMEM, "device allocation of %zu bytes: %s", bytes, hipGetErrorString(e));
   P->dev_allocs.push_back(d);
   e = hipMemcpy(d, h.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(SLLBM_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
@@ -100,6 +101,28 @@ int require_device(const sllbm_plan_s *P) {
 
 }  // namespace
 
+namespace sllbm {
+namespace {
+std::mutex g_alloc_mu;
+DevAllocator g_alloc;
+}  // namespace
+DevAllocator current_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc;
+}
+}  // namespace sllbm
+
+extern "C" int sllbm_set_allocator(void *(*alloc)(size_t bytes, void *ctx), void (*release)(void *ptr, void *ctx),
+                                   void *ctx) {
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(SLLBM_EINVAL, "set_allocator: give both functions, or neither (back to hipMalloc/hipFree)");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc.alloc = alloc;
+  g_alloc.release = release;
+  g_alloc.ctx = alloc ? ctx : nullptr;
+  return SLLBM_OK;
+}
+
 // ------------------------------------------------------------------ plan
 
 extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt, int prec, sllbm_plan *out) {
@@ -117,6 +140,7 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
 
   sllbm_plan_s *P = new (std::nothrow) sllbm_plan_s();
   if (!P) return fail(SLLBM_ENOMEM, "interp_plan: out of host memory");
+  P->dalloc = current_allocator();
   P->mesh = m;
   P->dt = dt;
   P->prec = prec;
@@ -242,16 +266,16 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
 #undef UP
   int64_t nblk = (m.n_nodes + kBlock - 1) / kBlock;
   P->scratch_len = kScratchHead + kRedWidth * nblk;
-  hipError_t e = hipMalloc((void **)&P->scratch, sizeof(double) * P->scratch_len);
+  hipError_t e = P->dalloc.get((void **)&P->scratch, sizeof(double) * P->scratch_len);
   if (e != hipSuccess) {
     sllbm_plan_destroy(P);
-    return fail(SLLBM_ENOMEM, "hipMalloc scratch: %s", hipGetErrorString(e));
+    return fail(SLLBM_ENOMEM, "device allocation (scratch): %s", hipGetErrorString(e));
   }
   if (P->tile_ok) {
-    e = hipMalloc((void **)&P->nstate, sizeof(double) * 6 * (size_t)m.n_nodes);
+    e = P->dalloc.get((void **)&P->nstate, sizeof(double) * 6 * (size_t)m.n_nodes);
     if (e != hipSuccess) {
       sllbm_plan_destroy(P);
-      return fail(SLLBM_ENOMEM, "hipMalloc node state: %s", hipGetErrorString(e));
+      return fail(SLLBM_ENOMEM, "device allocation (node state): %s", hipGetErrorString(e));
     }
   }
   *out = P;
@@ -377,9 +401,9 @@ extern "C" void sllbm_plan_destroy(sllbm_plan P) {
     (void)hipSetDevice(P->device);
     prof_flush(P->prof);
     for (hipEvent_t e : P->prof.pool) (void)hipEventDestroy(e);
-    for (void *d : P->dev_allocs) (void)hipFree(d);
-    if (P->scratch) (void)hipFree(P->scratch);
-    if (P->nstate) (void)hipFree(P->nstate);
+    for (void *d : P->dev_allocs) P->dalloc.put(d);
+    P->dalloc.put(P->scratch);
+    P->dalloc.put(P->nstate);
   }
   delete P;
 }

@@ -145,7 +145,29 @@ struct Profiler {
 };
 }  // namespace sllbm
 
+namespace sllbm {
+// Device memory of library-owned objects: hipMalloc/hipFree, or the caller's functions set
+// by sllbm_set_allocator.  Each object keeps the allocator it was created with.
+struct DevAllocator {
+  void *(*alloc)(size_t bytes, void *ctx) = nullptr;
+  void (*release)(void *ptr, void *ctx) = nullptr;
+  void *ctx = nullptr;
+  hipError_t get(void **p, size_t bytes) const {
+    if (!alloc) return hipMalloc(p, bytes);
+    *p = alloc(bytes, ctx);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  void put(void *p) const {
+    if (!p) return;
+    if (release) release(p, ctx);
+    else (void)hipFree(p);
+  }
+};
+DevAllocator current_allocator();
+}  // namespace sllbm
+
 struct sllbm_plan_s {
+  sllbm::DevAllocator dalloc;   // allocator of this plan's device memory
   sllbm::Mesh mesh;
   sllbm::VelSet vel;
   double dt = 0;

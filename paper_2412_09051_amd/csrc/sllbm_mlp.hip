@@ -584,6 +584,7 @@ __global__ void k_restrict(int64_t Nc, int Q2, int Ncx, int Ncy, int Nfx, int Nf
 // ================================================================== host side
 
 struct sllbm_mlp_s {
+  sllbm::DevAllocator dalloc;   // allocator of this network's device memory
   int n_in = 0, n_out = 0, device = -1;
   int64_t nparam = 0;
   int off[8] = {};
@@ -676,7 +677,7 @@ int learned_ready(sllbm_plan_s *P) {
   if (P->lfield) return SLLBM_OK;
   const Mesh &m = P->mesh;
   const int D = m.dim, p = m.p, P1 = p + 1;
-  HIP_TRY(hipMalloc((void **)&P->lfield, sizeof(double) * (D + 2) * (size_t)m.n_nodes));
+  HIP_TRY(P->dalloc.get((void **)&P->lfield, sizeof(double) * (D + 2) * (size_t)m.n_nodes));
   P->dev_allocs.push_back(P->lfield);
   // per-axis derivative tables
   std::vector<double> dm((size_t)P1 * P1);  // dm[j][mm] = l_mm'(x_j)
@@ -726,9 +727,9 @@ int learned_ready(sllbm_plan_s *P) {
     (void)per;
     int32_t *di = nullptr;
     double *dw = nullptr;
-    HIP_TRY(hipMalloc((void **)&di, idx.size() * sizeof(int32_t)));
+    HIP_TRY(P->dalloc.get((void **)&di, idx.size() * sizeof(int32_t)));
     P->dev_allocs.push_back(di);
-    HIP_TRY(hipMalloc((void **)&dw, w.size() * sizeof(double)));
+    HIP_TRY(P->dalloc.get((void **)&dw, w.size() * sizeof(double)));
     P->dev_allocs.push_back(dw);
     HIP_TRY(hipMemcpy(di, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(dw, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -736,7 +737,7 @@ int learned_ready(sllbm_plan_s *P) {
     P->ldw[a] = dw;
   }
   const int nfeat = (D + 2) * (D + 1);
-  HIP_TRY(hipMalloc((void **)&P->lfeat, sizeof(uint16_t) * nfeat * (size_t)m.n_nodes));
+  HIP_TRY(P->dalloc.get((void **)&P->lfeat, sizeof(uint16_t) * nfeat * (size_t)m.n_nodes));
   P->dev_allocs.push_back(P->lfeat);
   return SLLBM_OK;
 }
@@ -791,9 +792,9 @@ int check_params_basic(const sllbm_params *prm) {
 
 int ensure_partials(sllbm_mlp m, int nblk) {
   if (m->part) return SLLBM_OK;
-  HIP_TRY(hipMalloc((void **)&m->part, sizeof(float) * (size_t)kMaxPartialBlocks * m->nparam));
-  HIP_TRY(hipMalloc((void **)&m->lpart, sizeof(double) * kMaxPartialBlocks));
-  HIP_TRY(hipMalloc((void **)&m->loss, sizeof(double)));
+  HIP_TRY(m->dalloc.get((void **)&m->part, sizeof(float) * (size_t)kMaxPartialBlocks * m->nparam));
+  HIP_TRY(m->dalloc.get((void **)&m->lpart, sizeof(double) * kMaxPartialBlocks));
+  HIP_TRY(m->dalloc.get((void **)&m->loss, sizeof(double)));
   (void)nblk;
   return SLLBM_OK;
 }
@@ -842,6 +843,7 @@ extern "C" int sllbm_mlp_create(int n_in, int width, int depth, int n_out, uint6
   m->n_in = n_in;
   m->n_out = n_out;
   m->device = dev;
+  m->dalloc = sllbm::current_allocator();
   const int64_t sizes[8] = {(int64_t)n_in * HW, HW, HW * HW, HW, HW * HW, HW, (int64_t)HW * n_out, n_out};
   int64_t o = 0;
   for (int k = 0; k < 8; k++) {
@@ -859,7 +861,7 @@ extern "C" int sllbm_mlp_create(int n_in, int width, int depth, int n_out, uint6
       th[idx] = (float)((2.0 * u - 1.0) * bound);
     }
   }
-  auto alloc = [&](void **p, size_t b) { return hipMalloc(p, b) == hipSuccess; };
+  auto alloc = [&](void **p, size_t b) { return m->dalloc.get(p, b) == hipSuccess; };
   if (!alloc((void **)&m->theta, o * 4) || !alloc((void **)&m->m, o * 4) || !alloc((void **)&m->v, o * 4) ||
       !alloc((void **)&m->grad, o * 4) || !alloc((void **)&m->wbf, WBF_N * 2)) {
     sllbm_mlp_destroy(m);
@@ -878,8 +880,7 @@ extern "C" void sllbm_mlp_destroy(sllbm_mlp m) {
   if (!m) return;
   (void)hipSetDevice(m->device);
   void *ptrs[] = {m->theta, m->m, m->v, m->grad, m->wbf, m->part, m->lpart, m->loss};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+  for (void *p : ptrs) m->dalloc.put(p);
   delete m;
 }
 

@@ -223,3 +223,26 @@ def test_profiling_needs_a_device_plan():
         S.sllbm_plan_profile(plan, True)
     assert e.value.code == S.SLLBM_EHIP
     assert S.sllbm_plan_profile_read(plan) == {}
+
+
+def test_header_compiles_as_c(tmp_path):
+    """include/sllbm.h is a C header: it compiles on its own with a C compiler."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text('#include "sllbm.h"\nint main(void) { return sllbm_last_error() == 0; }\n')
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    r = subprocess.run([gcc, "-std=c11", "-Wall", "-Werror", "-I", inc, "-c", str(src), "-o", str(tmp_path / "use.o")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_set_allocator_needs_both_functions():
+    lib = S._lib
+    fn = S._ALLOC_FN(lambda n, ctx: None)
+    assert lib.sllbm_set_allocator(fn, None, None) == S.SLLBM_EINVAL
+    assert "both" in lib.sllbm_last_error().decode()
+    assert lib.sllbm_set_allocator(None, None, None) == S.SLLBM_OK
