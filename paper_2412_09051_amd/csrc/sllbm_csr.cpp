@@ -464,7 +464,7 @@ int build_csr_tables(const Mesh &m, const VelSet &v, double dt, HostTables &t, i
   Geo g(m);
   g.build_buckets();
   g.build_node_cells();
-  const int Q = v.Q, npc = g.npc;
+  const int Q = v.Q;
   const int64_t N = m.n_nodes;
   t.row_cell.assign((size_t)Q * N, -1);
   t.row_src.assign((size_t)Q * N, 0);
