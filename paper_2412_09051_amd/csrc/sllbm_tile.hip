@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
   // and walks the rows of the committed region
   auto xpass = [&]() __attribute__((always_inline)) {
     constexpr int NRX = BS / TX;          // rows in flight per sweep of the workgroup
-    const int Ry = cg[1].R, Rz = cg[2].R;
+    const int Ry = cg[1].R;   // one plane in 2D: the row counter is ry itself
     const int len = cg[0].ident ? 1 : P + 1;
     const int tx = tid % TX, r0 = tid / TX;
     if (r0 < NRX && tx < vx) {
@@ -292,14 +292,12 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
       T w[P + 1];
 #pragma unroll
       for (int j = 0; j <= P; j++) w[j] = WT[row * (P + 1) + j];
-      const int nrows = Ry * Rz;
       constexpr int MR = (RY * RZ + NRX - 1) / NRX;   // rows per thread at most
 #pragma unroll 4
       for (int q = 0; q < MR; q++) {
         const int rr = r0 + q * NRX;
-        if (rr >= nrows) break;
-        const int ry = rr % Ry, rz = rr / Ry;
-        const T *sf = S + (rz * RY + ry) * RX + off;
+        if (rr >= Ry) break;
+        const T *sf = S + rr * RX + off;
         T a = 0, b = 0;
 #pragma unroll
         for (int j = 0; j <= P; j++) {
@@ -307,7 +305,7 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
           a += w[j] * sf[j];
           b += w[j] * sf[SS + j];
         }
-        const int l = (rz * RY + ry) * TX + tx;
+        const int l = rr * TX + tx;
         X[l] = a;
         X[XS + l] = b;
       }
@@ -588,12 +586,14 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
         T w[P + 1];
 #pragma unroll
         for (int j = 0; j <= P; j++) w[j] = WT[tx * (P + 1) + j];
-        const int nrows = Ry * Rz;
+        // rows rz RY + ry of the staging grid: the compile-time stride RY splits the counter
+        // (a runtime divisor would cost an emulated division per row); rows beyond the
+        // region's Ry are skipped
+        const int nrows = RY * Rz;
 #pragma unroll 1
-        for (int rr = r0; rr < RY * RZ; rr += NRX) {
-          int ry = rr % Ry, rz = rr / Ry;
-          if (rr >= nrows) break;
-          const T *sf = S + (rz * RY + ry) * RX + off;
+        for (int rr = r0; rr < nrows; rr += NRX) {
+          if (rr % RY >= Ry) continue;
+          const T *sf = S + rr * RX + off;
           T a = 0, b = 0;
 #pragma unroll
           for (int j = 0; j <= P; j++) {
@@ -601,7 +601,7 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
             a += w[j] * sf[j];
             b += w[j] * sf[SS + j];
           }
-          int l = (rz * RY + ry) * TX + tx;
+          const int l = rr * TX + tx;
           X[l] = a;
           X[XS + l] = b;
         }
