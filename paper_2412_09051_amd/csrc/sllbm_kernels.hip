@@ -4,8 +4,9 @@
 //   k_step_gather   fused stream + boundary + moments + thermal wall + BGK + force, one
 //                   node per lane; per-axis interpolation tables on tensor meshes,
 //                   sum-factorised in registers (two sweeps over the velocities: the
-//                   first accumulates the conserved moments, the second re-streams and
-//                   relaxes, so no per-node stash is needed)
+//                   first streams, stores the streamed values in the node's output slots
+//                   and sums the conserved moments; the second reads them back and
+//                   relaxes them in place)
 //   k_moments       nodal rho, u, T and block partials of the totals
 //   k_reduce_final  deterministic second pass of every FP64 reduction
 //
@@ -117,12 +118,14 @@ __global__ void __launch_bounds__(kBlock) k_step_gather(const DevTensorPlan pl, 
   }
   const double scale = sa.scale ? *sa.scale : 1.0;
 
-  // sweep 1: conserved moments of the streamed populations (eq:density, eq:momentum,
-  // total energy)
+  // sweep 1: stream every velocity, store the streamed value in this node's output slot
+  // and sum the conserved moments (eq:density, eq:momentum, total energy)
   double rho = 0, j0 = 0, j1 = 0, j2 = 0, E = 0;
   for (int i = 0; i < Q; i++) {
     double fv, gv;
     stream_tp<T, D, P>(pl, sa, pin, n, i, er[0], er[1], fax[0], fax[1], scale, fv, gv);
+    pout[(size_t)i * pl.N + k] = (T)fv;
+    pout[((size_t)Q + i) * pl.N + k] = (T)gv;
     const double *vi = pl.vel + 8 * i;
     rho += fv;
     j0 += vi[0] * fv;
@@ -147,11 +150,11 @@ __global__ void __launch_bounds__(kBlock) k_step_gather(const DevTensorPlan pl, 
   }
   const double gT = Tn * sa.gbase;
 
-  // sweep 2: re-stream, isothermal-wall correction (eq:thermalBC), BGK relaxation,
-  // Kupershtokh forcing, store
+  // sweep 2: read the stored streamed values back (this thread wrote them), isothermal-wall
+  // correction (eq:thermalBC), BGK relaxation, Kupershtokh forcing, store
   for (int i = 0; i < Q; i++) {
-    double fv, gv;
-    stream_tp<T, D, P>(pl, sa, pin, n, i, er[0], er[1], fax[0], fax[1], scale, fv, gv);
+    double fv = (double)pout[(size_t)i * pl.N + k];
+    double gv = (double)pout[((size_t)Q + i) * pl.N + k];
     const double *vi = pl.vel + 8 * i;
     double fe = eq_f(eq, vi);
     if (thermal) {
