@@ -776,6 +776,10 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
     if (sa.has_force) ef[v] = eq_forced(rho, u0, u1, u2, Tn, sa, D);
     gT[v] = Tn * sa.gbase;
   }
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < V; v++) any = any || act[v];
+  if (!any) return;   // all in a boundary layer (or past N): nothing to read or write
   const int Q = pl.Q;
   for (int i = 0; i < Q; i++) {
     const double *vi = pl.vel + 8 * i;
