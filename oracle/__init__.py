@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE.  Only tests/, the smoke check and the benchmark's CPU
 baseline may import this package.  It shares no code with the HIP library:
 
 * velocity set: 1D Gauss-Hermite rule from numpy (Sec. 3.2; 5 points give
-  quadrature degree 9), tensor product over dimensions;
+  quadrature degree 9), tensor product over dimensions; or the reduced degree-9
+  sets D2Q19 / D3Q45, solved from their moment conditions (cubature_set);
 * support points: GLL from numpy's Legendre roots, GLC, equidistant (eq:intf);
 * nodal volumes: integrals of the nodal Lagrange functions by Gauss-Legendre;
 * the step itself: oracle/sllbm_oracle.c (tensor-product meshes),
@@ -77,6 +78,102 @@ def velocity_set(dim: int, n: int = 5, T0: float = 1.0):
             j = j * n + (n - 1 - a[d])
         opp[i] = j
     return zeta, wq, opp
+
+
+def _orbit_unit_vectors(kind: str) -> np.ndarray:
+    """Unit directions of one orbit, in a fixed order.
+
+    hex0 / hex30: regular hexagon, vertex k at angle k pi/3 (hex0) or pi/6 + k pi/3 (hex30),
+    k = 0..5.  ico: the 12 vertices of an icosahedron, the cyclic shifts of (0, +-1, +-phi)
+    (shift c puts the 0 on axis c, +-1 on axis c+1, +-phi on axis c+2; c = 0, 1, 2 outer,
+    then the sign of the 1, then the sign of phi, + before -).  dod: the dual dodecahedron,
+    first the cube vertices (+-1, +-1, +-1) with x's sign changing fastest, then the cyclic
+    shifts of (0, +-phi, +-1/phi) in the icosahedron's order."""
+    if kind in ("hex0", "hex30"):
+        # cos and sin of the six angles written out, so that zero components are exact
+        h = math.sqrt(3.0) / 2.0
+        if kind == "hex0":
+            return np.array([(1.0, 0.0), (0.5, h), (-0.5, h), (-1.0, 0.0), (-0.5, -h), (0.5, -h)])
+        return np.array([(h, 0.5), (0.0, 1.0), (-h, 0.5), (-h, -0.5), (0.0, -1.0), (h, -0.5)])
+    phi = (1.0 + math.sqrt(5.0)) / 2.0
+    out = []
+    if kind == "dod":
+        for j in range(8):
+            out.append([-1.0 if (j >> b) & 1 else 1.0 for b in range(3)])
+        big, small = phi, 1.0 / phi
+    else:
+        big, small = 1.0, phi  # (0, 1, phi): the entry on axis c+1 is 1, on c+2 phi
+    for c in range(3):
+        for s1 in (1.0, -1.0):
+            for s2 in (1.0, -1.0):
+                v = [0.0, 0.0, 0.0]
+                v[(c + 1) % 3] = s1 * big
+                v[(c + 2) % 3] = s2 * small
+                out.append(v)
+    v = np.array(out)
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def cubature_set(dim: int, T0: float = 1.0):
+    """Reduced velocity sets D2Q19 and D3Q45 of quadrature degree 9 (Sec. 3.2).
+
+    The paper names these point counts (the smallest known degree-9 cubatures for the
+    Gaussian weight in 2D and 3D) but prints no abscissae, so the rules are fixed here
+    from their defining conditions, for the weight exp(-|x|^2/2)/(2 pi)^(D/2):
+
+    * 2D: the origin and three regular hexagons, two in the orientation hex0 and one in
+      hex30; 3D: the origin, two icosahedra and the dual dodecahedron.  Each rule is
+      invariant under the hexagon's (icosahedron's) symmetry group, which includes -1, so
+      every odd moment vanishes, and every orbit reproduces the sphere's averages of the
+      harmonics of degree 2 and 4 (and 8); what is left of exactness up to degree 9 is
+      (i) the radial moments sum_k W_k s_k^m = E|x|^(2m), m = 0..4 (W_k: an orbit's total
+      weight, s_k its squared radius) and (ii) the orbit averages y_k of the invariant
+      harmonic of degree 6, alone and times |x|^2: sum_k W_k s_k^m y_k = 0, m = 3, 4.
+    * The single orbit of the other orientation (hex30 / dod) follows from (ii) and the
+      radial moments m = 3, 4; the two remaining orbits are then a two-node Gauss rule in s
+      for the moments left over.
+    * y_k is read off as the orbit's mean of x^6 minus the sphere's mean of x^6.
+
+    Order: index 0 the origin, then the inner and the outer hex0 (ico) orbit, then the
+    hex30 (dod) orbit, each in the order of _orbit_unit_vectors.  zeta = sqrt(T0) x.
+    Returns (zeta [Q][dim], w [Q], opposite [Q])."""
+    if dim == 2:
+        main, other = _orbit_unit_vectors("hex0"), _orbit_unit_vectors("hex30")
+    elif dim == 3:
+        main, other = _orbit_unit_vectors("ico"), _orbit_unit_vectors("dod")
+    else:
+        raise ValueError("reduced cubature sets exist for dim 2 and 3")
+    # E|x|^(2m) for the standard Gaussian in dim dimensions
+    c = [float(np.prod([dim + 2 * j for j in range(m)])) for m in range(5)]
+    # sphere mean of x^6: E[x^6] / E[|x|^6]
+    sph6 = 15.0 / c[3]
+    y_main = float(np.mean(main[:, 0] ** 6)) - sph6
+    y_other = float(np.mean(other[:, 0] ** 6)) - sph6
+    kappa = -y_other / y_main
+    # (ii) with the radial moments 3 and 4: the other orbit's s and total weight
+    B3, B4 = c[3] / (1.0 + kappa), c[4] / (1.0 + kappa)
+    s_o = B4 / B3
+    W_o = B3 / s_o ** 3
+    # the main orbits carry the rest: moments A_m = sum W s^m, m = 1..4
+    A = [None, c[1] - W_o * s_o, c[2] - W_o * s_o ** 2, kappa * B3, kappa * B4]
+    # two-node Gauss rule for the measure s dW: nodes are the roots of s^2 + a s + b with
+    # [A1 A2; A2 A3] [b; a] = -[A3; A4]
+    b, a = np.linalg.solve(np.array([[A[1], A[2]], [A[2], A[3]]]), -np.array([A[3], A[4]]))
+    s_in, s_out = np.sort(np.roots([1.0, a, b]).real)
+    W_in, W_out = np.linalg.solve(np.array([[s_in, s_out], [s_in ** 2, s_out ** 2]]), np.array([A[1], A[2]]))
+    W_0 = 1.0 - W_in - W_out - W_o
+    pts = [np.zeros((1, dim)), main * math.sqrt(s_in), main * math.sqrt(s_out), other * math.sqrt(s_o)]
+    ws = [np.array([W_0]), np.full(len(main), W_in / len(main)), np.full(len(main), W_out / len(main)),
+          np.full(len(other), W_o / len(other))]
+    zeta = math.sqrt(T0) * np.vstack(pts)
+    w = np.concatenate(ws)
+    Q = len(w)
+    opp = np.zeros(Q, dtype=np.int32)
+    for i in range(Q):
+        d = np.max(np.abs(zeta + zeta[i]), axis=1)
+        opp[i] = int(np.argmin(d))
+        assert d[opp[i]] < 1e-12 * max(1.0, math.sqrt(T0))
+    return zeta, w, opp
 
 
 def stroud_bound(degree: int, dim: int) -> int:
@@ -325,9 +422,12 @@ class ForceController:
         return self.force.copy()
 
 
-def equilibrium(dim: int, rho: float, u, T: float, gamma: float = 1.4, T0: float = 1.0, n_gh: int = 5):
-    """f^eq and g^eq of one state for every velocity of the D{dim}V{n^dim} set."""
-    zeta, w, _ = velocity_set(dim, n_gh, T0)
+def equilibrium(dim: int, rho: float, u, T: float, gamma: float = 1.4, T0: float = 1.0, n_gh: int = 5, vel=None):
+    """f^eq and g^eq of one state for every velocity of the D{dim}V{n^dim} set, or of an
+    explicit set vel = (zeta, w, opposite) built for the same T0."""
+    zeta, w, _ = velocity_set(dim, n_gh, T0) if vel is None else vel
+    zeta = np.ascontiguousarray(zeta, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
     Q = zeta.shape[0]
     feq = np.zeros(Q)
     geq = np.zeros(Q)
@@ -380,11 +480,17 @@ def _lagrange_table(xref, pts):
 class CurvOracle:
     """FP64 reference of the SLLBM on a 2D curvilinear mesh (workloads.CurvMesh)."""
 
-    def __init__(self, mesh, phys, n_gh: int = 5, geometry: bool = True):
-        """geometry=False skips the departure-point table (for tests of locate/exit)."""
+    def __init__(self, mesh, phys, n_gh: int = 5, geometry: bool = True, vel=None):
+        """geometry=False skips the departure-point table (for tests of locate/exit);
+        vel = (zeta, w, opposite) replaces the D2V{n_gh^2} set."""
         self.mesh, self.phys = mesh, phys
         self.dim = 2
-        self.zeta, self.w, self.opp = velocity_set(2, n_gh, phys.T0)
+        if vel is None:
+            self.zeta, self.w, self.opp = velocity_set(2, n_gh, phys.T0)
+        else:
+            self.zeta = np.ascontiguousarray(vel[0], dtype=np.float64)
+            self.w = np.ascontiguousarray(vel[1], dtype=np.float64)
+            self.opp = np.ascontiguousarray(vel[2], dtype=np.int32)
         self.Q = self.zeta.shape[0]
         self.xref = support_points(mesh.p, mesh.nodes)
         self.xyz = np.ascontiguousarray(mesh.node_xyz, dtype=np.float64)
