@@ -54,6 +54,10 @@ def parse():
                     help="convective Mach numbers of the learned-correction legs, comma separated (first one is 'learned')")
     ap.add_argument("--no-extra", action="store_true", help="skip the C1-R (2D roofline-scale) and C4 (channel) lines")
     ap.add_argument("--kernel", choices=["auto", "gather", "tiled"], default="auto")
+    ap.add_argument("--velocity-set", choices=["d3v125", "d3q45"], default="d3v125",
+                    help="velocity set of the headline TGV legs (D3V125 product rule or the reduced D3Q45)")
+    ap.add_argument("--no-cubature", action="store_true",
+                    help="skip the TGV legs on the reduced D3Q45 set beside the D3V125 headline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for byte counters)")
     return ap.parse_args()
@@ -114,14 +118,14 @@ def timed_steps(S, plan, prm, a, b, steps, warmup, torch):
     return a, t0.elapsed_time(t1), wall, prof
 
 
-def gpu_leg(prec, steps, warmup, ncell, kernel="auto"):
+def gpu_leg(prec, steps, warmup, ncell, kernel="auto", vel="d3v125"):
     import torch
     import numpy as np
     import paper_2412_09051_amd as S
     import workloads as W
     mesh, phys = W.tgv_case(ncell=ncell)
     m = S.sllbm_mesh_build(mesh)
-    vs = S.sllbm_velset_gauss_hermite(3, 5, phys.T0)
+    vs = S.sllbm_velset_cubature(3, phys.T0) if vel == "d3q45" else S.sllbm_velset_gauss_hermite(3, 5, phys.T0)
     plan = S.sllbm_interp_plan(m, vs, phys.dt, S.SLLBM_F32 if prec == "f32" else S.SLLBM_F64)
     if kernel != "auto":
         S.sllbm_plan_select_kernel(plan, {"gather": 1, "tiled": 2}[kernel])
@@ -297,13 +301,13 @@ def summarize(prof, total_ms, wall, steps, updates, bytes_per_update, **extra):
     return out
 
 
-def ogrid_leg(prec, steps, warmup):
+def ogrid_leg(prec, steps, warmup, vel="d2v25"):
     import torch
     import paper_2412_09051_amd as S
     import workloads as W
     mesh, phys = W.naca_ogrid()
     m = S.sllbm_mesh_build(mesh)
-    vs = S.sllbm_velset_gauss_hermite(2, 5, phys.T0)
+    vs = S.sllbm_velset_cubature(2, phys.T0) if vel == "d2q19" else S.sllbm_velset_gauss_hermite(2, 5, phys.T0)
     t0 = time.perf_counter()
     plan = S.sllbm_interp_plan(m, vs, phys.dt, S.SLLBM_F32 if prec == "f32" else S.SLLBM_F64)
     plan_s = time.perf_counter() - t0
@@ -577,14 +581,26 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    r64 = gpu_leg("f64", args.steps, args.warmup, args.ncell, args.kernel)
-    print(f"# tgv f64 done: {r64['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
-    r32 = None if args.no_fp32 else gpu_leg("f32", args.steps, args.warmup, args.ncell, args.kernel)
+    vset = args.velocity_set
+    tkey = "tgv45" if vset == "d3q45" else "tgv"
+    r64 = gpu_leg("f64", args.steps, args.warmup, args.ncell, args.kernel, vset)
+    print(f"# tgv {vset} f64 done: {r64['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
+    r32 = None if args.no_fp32 else gpu_leg("f32", args.steps, args.warmup, args.ncell, args.kernel, vset)
+    cub = {}
+    if vset == "d3v125" and not args.no_cubature:
+        for prec in ("f64", "f32"):
+            cub[prec] = gpu_leg(prec, args.steps, args.warmup, args.ncell, args.kernel, "d3q45")
+            print(f"# tgv d3q45 {prec} done: {cub[prec]['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
     og = {}
     if not args.no_ogrid:
         for prec in ("f32", "f64"):
             og[prec] = ogrid_leg(prec, args.steps, args.warmup)
             print(f"# ogrid {prec} done: {og[prec]['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
+        if not args.no_cubature:
+            for prec in ("f32", "f64"):
+                og["d2q19_" + prec] = ogrid_leg(prec, args.steps, args.warmup, "d2q19")
+                print(f"# ogrid d2q19 {prec} done: {og['d2q19_' + prec]['gqups']:.2f} GQUPS", file=sys.stderr,
+                      flush=True)
     extra = {}
     if not args.no_extra:
         for case, precs in (("c1r", ("f64", "f32")), ("c4", ("f32",))):
@@ -626,23 +642,44 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"3D periodic compressible Taylor-Green vortex Ma 0.8 Re 400, "
-                               f"{args.ncell}^3 cells p=3 GLL ({r64['N']} nodes), D3V125 Gauss-Hermite, FP64",
-                   "nodes": r64["N"], "Q": r64["Q"], "order_p": 3, "velocity_set": "D3V125"},
-        "roofline": roofline(r64, traffic_from_profiles("tgv_f64")),
+                               f"{args.ncell}^3 cells p=3 GLL ({r64['N']} nodes), "
+                               f"{'D3Q45 reduced cubature' if vset == 'd3q45' else 'D3V125 Gauss-Hermite'}, FP64",
+                   "nodes": r64["N"], "Q": r64["Q"], "order_p": 3, "velocity_set": vset.upper()},
+        "roofline": roofline(r64, traffic_from_profiles(tkey + "_f64")),
         "cpu_baseline": cpu,
         "kernels": r64["kernels"],
     }
     if r32:
         out["fp32"] = {"value": round(r32["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(r32["ms_per_step"], 4),
-                       "roofline": roofline(r32, traffic_from_profiles("tgv_f32")), "kernels": r32["kernels"]}
+                       "roofline": roofline(r32, traffic_from_profiles(tkey + "_f32")), "kernels": r32["kernels"]}
+    if cub:
+        # same workload and time step on the reduced set: Q = 45 instead of 125, so a step
+        # costs fewer updates; the per-update rate is comparable, the per-step time is not
+        out["d3q45"] = {
+            "workload": f"the same Taylor-Green vortex ({cub['f64']['N']} nodes, same time step) on the reduced "
+                        f"degree-9 velocity set D3Q45",
+            **{prec: {"value": round(v["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(v["ms_per_step"], 4),
+                      "node_updates_per_s": round(v["N"] / (v["ms_per_step"] * 1e-3), 1),
+                      "step_time_vs_d3v125": round(v["ms_per_step"] / (r64 if prec == "f64" else r32)["ms_per_step"], 4)
+                      if (prec == "f64" or r32) else None,
+                      "roofline": roofline(v, traffic_from_profiles("tgv45_" + prec)), "kernels": v["kernels"],
+                      "finite": v["finite"]}
+               for prec, v in cub.items()}}
     if og:
+        def og_line(key, v):
+            return {"value": round(v["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(v["ms_per_step"], 4),
+                    "bytes_per_update": v["bpu"], "plan_build_s": round(v["plan_build_s"], 2),
+                    "roofline": roofline(v, traffic_from_profiles(key)), "finite": v["finite"]}
         out["ogrid"] = {
             "workload": "supersonic NACA 0012 O-grid Ma 1.5 Re 1e4, 256x128 cells p=4 GLL (525312 nodes), D2V25, "
                         "curvilinear CSR plan",
-            **{prec: {"value": round(v["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(v["ms_per_step"], 4),
-                      "bytes_per_update": v["bpu"], "plan_build_s": round(v["plan_build_s"], 2),
-                      "roofline": roofline(v, traffic_from_profiles("ogrid_" + prec)), "finite": v["finite"]}
-               for prec, v in og.items()}}
+            **{prec: og_line("ogrid_" + prec, v) for prec, v in og.items() if not prec.startswith("d2q19")}}
+        if "d2q19_f32" in og:
+            out["ogrid"]["d2q19"] = {
+                "workload": "the same O-grid on the reduced degree-9 set D2Q19 (the paper's set for this case)",
+                **{prec: dict(og_line("ogrid19_" + prec, og["d2q19_" + prec]),
+                              step_time_vs_d2v25=round(og["d2q19_" + prec]["ms_per_step"] / og[prec]["ms_per_step"], 4))
+                   for prec in ("f32", "f64")}}
     names = {"c1r": "2D periodic shear wave, 1024^2 cells p=4 GLL (16.8M nodes), D2V25",
              "c4": "3D supersonic channel Ma_b 1.5 Re_b 3000, 128x96x64 cells p=2 (6.3M nodes), D3V125, "
                    "isothermal walls, forcing held by the PI force controller and mass rescaling, both every 10 steps"}

@@ -126,6 +126,20 @@ typedef struct {
  * degree 2n-1; n = 5 gives degree 9).  Index i = a_x + n a_y + n^2 a_z over ascending
  * abscissae.  Host outputs: zeta [Q*dim], w [Q], opp [Q] with Q = n^dim. */
 int sllbm_velset_gauss_hermite(int dim, int n_per_dim, double T0, double *zeta, double *w, int32_t *opp);
+/* Reduced cubature sets of quadrature degree 9 (Sec. 3.2: the smallest known such rules
+ * for the Gaussian weight have 19 points in 2D and 45 in 3D, named D2Q19 and D3Q45 there;
+ * the paper prints no abscissae).  The rules returned are fixed by the degree-9 moment
+ * conditions under a symmetry group that contains -1:
+ *   dim 2 (Q = 19): the origin, two regular hexagons with a vertex on +x (|x|^2 =
+ *     (48 -+ 8 sqrt 15)/7) and one turned by 30 degrees (|x|^2 = 8, total weight 3/64);
+ *   dim 3 (Q = 45): the origin (weight 28/135), icosahedra with the vertices (0, +-1, +-phi)
+ *     and their cyclic shifts at |x|^2 = 3 (25/432 each) and 15 (1/2160 each), and the dual
+ *     dodecahedron at |x|^2 = 9 (1/216 each).
+ * zeta = sqrt(T0) x.  Index 0 is the origin, then the inner and outer hexagon (icosahedron)
+ * orbit, then the turned hexagon (dodecahedron).  *Q receives 19 or 45; with zeta, w and
+ * opp all NULL nothing else is written (size query), otherwise all three are host outputs
+ * of Q*dim, Q and Q elements.  EINVAL for another dim, T0 <= 0 or a partial set of outputs. */
+int sllbm_velset_cubature(int dim, double T0, int *Q, double *zeta, double *w, int32_t *opp);
 
 /* Interpolation plan for (mesh, velocity set, dt, precision): for every node and
  * velocity the departure point x_k - dt zeta_i, the boundary case that the backward

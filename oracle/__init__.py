@@ -159,7 +159,9 @@ def cubature_set(dim: int, T0: float = 1.0):
     # two-node Gauss rule for the measure s dW: nodes are the roots of s^2 + a s + b with
     # [A1 A2; A2 A3] [b; a] = -[A3; A4]
     b, a = np.linalg.solve(np.array([[A[1], A[2]], [A[2], A[3]]]), -np.array([A[3], A[4]]))
-    s_in, s_out = np.sort(np.roots([1.0, a, b]).real)
+    # roots without cancellation: q = -(a + sign(a) sqrt(a^2 - 4b)) / 2, then q and b / q
+    q = -0.5 * (a + math.copysign(math.sqrt(a * a - 4.0 * b), a))
+    s_in, s_out = sorted((q, b / q))
     W_in, W_out = np.linalg.solve(np.array([[s_in, s_out], [s_in ** 2, s_out ** 2]]), np.array([A[1], A[2]]))
     W_0 = 1.0 - W_in - W_out - W_o
     pts = [np.zeros((1, dim)), main * math.sqrt(s_in), main * math.sqrt(s_out), other * math.sqrt(s_o)]

@@ -88,6 +88,7 @@ class sllbm_force_ctl(ctypes.Structure):
 
 _lib.sllbm_last_error.restype = ctypes.c_char_p
 for _name in ("sllbm_mesh_build", "sllbm_mesh_nodes", "sllbm_mesh_volumes", "sllbm_velset_gauss_hermite",
+              "sllbm_velset_cubature",
               "sllbm_interp_plan", "sllbm_plan_info", "sllbm_plan_select_kernel", "sllbm_init_equilibrium",
               "sllbm_step", "sllbm_moments", "sllbm_plan_profile", "sllbm_plan_profile_read",
               "sllbm_force_reset", "sllbm_force_update", "sllbm_force_read", "sllbm_set_allocator"):
@@ -191,6 +192,20 @@ def sllbm_velset_gauss_hermite(dim: int, n_per_dim: int = 5, T0: float = 1.0):
     _check(_lib.sllbm_velset_gauss_hermite(dim, n_per_dim, ctypes.c_double(T0), _np_ptr(zeta), _np_ptr(w),
                                            _np_ptr(opp, ctypes.POINTER(ctypes.c_int32))), "sllbm_velset_gauss_hermite")
     return {"dim": dim, "Q": Q, "zeta": zeta.reshape(Q, dim), "w": w, "opposite": opp, "T0": T0}
+
+
+def sllbm_velset_cubature(dim: int, T0: float = 1.0):
+    """Reduced degree-9 set D2Q19 (dim 2) or D3Q45 (dim 3), same dict as the product rule's."""
+    Q = ctypes.c_int(0)
+    _check(_lib.sllbm_velset_cubature(dim, ctypes.c_double(T0), ctypes.byref(Q), None, None, None),
+           "sllbm_velset_cubature")
+    q = Q.value
+    zeta = np.zeros(q * dim)
+    w = np.zeros(q)
+    opp = np.zeros(q, dtype=np.int32)
+    _check(_lib.sllbm_velset_cubature(dim, ctypes.c_double(T0), ctypes.byref(Q), _np_ptr(zeta), _np_ptr(w),
+                                      _np_ptr(opp, ctypes.POINTER(ctypes.c_int32))), "sllbm_velset_cubature")
+    return {"dim": dim, "Q": q, "zeta": zeta.reshape(q, dim), "w": w, "opposite": opp, "T0": T0}
 
 
 def _bcs_array(bcs):
@@ -509,7 +524,7 @@ def sllbm_mlp_train_step(m: Mlp, x, t, lr: float, want_loss: bool = True, stream
     return loss.value if want_loss else None
 
 
-__all__ = ["sllbm_velset_gauss_hermite", "sllbm_mesh_build", "sllbm_mesh_nodes", "sllbm_mesh_volumes",
+__all__ = ["sllbm_velset_gauss_hermite", "sllbm_velset_cubature", "sllbm_mesh_build", "sllbm_mesh_nodes", "sllbm_mesh_volumes",
            "sllbm_interp_plan", "sllbm_plan_info", "sllbm_plan_select_kernel", "sllbm_init_equilibrium", "sllbm_step", "sllbm_moments",
            "sllbm_force_reset", "sllbm_force_update", "sllbm_force_read", "sllbm_set_allocator", "use_torch_allocator",
            "Params", "Plan", "Mesh", "SllbmError", "SLLBM_F64", "SLLBM_F32", "LIB_PATH",

@@ -171,8 +171,11 @@ template <typename T, int P>
 void launch_csr_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
   dim3 grid((unsigned)((Pl->cp.N + kBlock - 1) / kBlock));
   ProfScope ps(Pl, "k_step_csr", s);
+  // D2V25 and D2Q19 keep a node's streamed values in registers between moments and relaxation
   if (Pl->cp.Q == 25)
     hipLaunchKernelGGL((k_step_csr<T, P, 25>), grid, dim3(kBlock), 0, s, Pl->cp, a, (const T *)pin, (T *)pout);
+  else if (Pl->cp.Q == 19)
+    hipLaunchKernelGGL((k_step_csr<T, P, 19>), grid, dim3(kBlock), 0, s, Pl->cp, a, (const T *)pin, (T *)pout);
   else
     hipLaunchKernelGGL((k_step_csr<T, P, 0>), grid, dim3(kBlock), 0, s, Pl->cp, a, (const T *)pin, (T *)pout);
 }

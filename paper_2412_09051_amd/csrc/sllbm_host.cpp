@@ -518,6 +518,91 @@ extern "C" int sllbm_velset_gauss_hermite(int dim, int n, double T0, double *zet
   return SLLBM_OK;
 }
 
+extern "C" int sllbm_velset_cubature(int dim, double T0, int *Q, double *zeta, double *w, int32_t *opp) {
+  const bool none = !zeta && !w && !opp, all = zeta && w && opp;
+  if ((dim != 2 && dim != 3) || !(T0 > 0) || !Q || !(none || all))
+    return fail(SLLBM_EINVAL, "velset_cubature: need dim 2 or 3, T0 > 0, non-NULL Q and either all or none "
+                              "of zeta, w, opp");
+  // Degree-9 rules for the weight exp(-|x|^2/2)/(2 pi)^(D/2) with 19 / 45 points, each an
+  // origin plus three orbits of a finite rotation group (hexagonal / icosahedral), in
+  // closed form.  Radii^2 s and total orbit weights W:
+  //   2D: hexagon at 0 deg (a vertex on +x) with s = (48 - 8 sqrt15)/7 and (48 + 8 sqrt15)/7,
+  //       hexagon at 30 deg with s = 8, W = 3/64; the two inner weights solve
+  //       W1 s1 + W2 s2 = 13/8, W1 s1^2 + W2 s2^2 = 5.
+  //   3D: icosahedra with s = 3 (W = 25/36) and s = 15 (W = 1/180), the dual dodecahedron
+  //       with s = 9 (W = 5/54), origin 28/135.
+  // Index order: origin; inner, outer hexagon-0 (icosahedron); hexagon-30 (dodecahedron).
+  const int q = dim == 2 ? 19 : 45;
+  *Q = q;
+  if (none) return SLLBM_OK;
+  std::vector<double> v;  // q * dim unit-scale abscissae (T0 = 1)
+  std::vector<double> wt;
+  auto orbit = [&](const std::vector<double> &dirs, double s, double Wtot) {
+    const int n = (int)dirs.size() / dim;
+    const double r = std::sqrt(s);
+    for (int k = 0; k < n; k++) {
+      double nrm = 0.0;
+      for (int d = 0; d < dim; d++) nrm += dirs[k * dim + d] * dirs[k * dim + d];
+      nrm = std::sqrt(nrm);
+      for (int d = 0; d < dim; d++) v.push_back(r * dirs[k * dim + d] / nrm);
+      wt.push_back(Wtot / n);
+    }
+  };
+  for (int d = 0; d < dim; d++) v.push_back(0.0);
+  if (dim == 2) {
+    const double h = std::sqrt(3.0) / 2.0;
+    // vertex k at angle k pi/3 (hex0) and pi/6 + k pi/3 (hex30), k = 0..5
+    const std::vector<double> hex0 = {1, 0, 0.5, h, -0.5, h, -1, 0, -0.5, -h, 0.5, -h};
+    const std::vector<double> hex30 = {h, 0.5, 0, 1, -h, 0.5, -h, -0.5, 0, -1, h, -0.5};
+    const double r15 = std::sqrt(15.0);
+    const double s1 = (48.0 - 8.0 * r15) / 7.0, s2 = (48.0 + 8.0 * r15) / 7.0;
+    const double W1 = (5.0 - 1.625 * s2) / (s1 * (s1 - s2)), W2 = (5.0 - 1.625 * s1) / (s2 * (s2 - s1));
+    const double W3 = 3.0 / 64.0;
+    wt.push_back(1.0 - W1 - W2 - W3);
+    orbit(hex0, s1, W1);
+    orbit(hex0, s2, W2);
+    orbit(hex30, 8.0, W3);
+  } else {
+    const double ph = 0.5 * (1.0 + std::sqrt(5.0));
+    // cyclic shifts c = 0, 1, 2 of (0, a, b): 0 on axis c, +-a on axis c+1, +-b on axis c+2,
+    // sign of a outer, + before -
+    auto shifts = [](double a, double b, std::vector<double> &o) {
+      for (int c = 0; c < 3; c++)
+        for (int sa = 0; sa < 2; sa++)
+          for (int sb = 0; sb < 2; sb++) {
+            double e[3] = {0, 0, 0};
+            e[(c + 1) % 3] = sa ? -a : a;
+            e[(c + 2) % 3] = sb ? -b : b;
+            o.insert(o.end(), e, e + 3);
+          }
+    };
+    std::vector<double> ico, dod;
+    shifts(1.0, ph, ico);
+    for (int j = 0; j < 8; j++)  // cube vertices, x's sign fastest
+      for (int b = 0; b < 3; b++) dod.push_back((j >> b) & 1 ? -1.0 : 1.0);
+    shifts(ph, 1.0 / ph, dod);
+    wt.push_back(28.0 / 135.0);
+    orbit(ico, 3.0, 25.0 / 36.0);
+    orbit(ico, 15.0, 1.0 / 180.0);
+    orbit(dod, 9.0, 5.0 / 54.0);
+  }
+  const double st = std::sqrt(T0);
+  for (int i = 0; i < q; i++) {
+    w[i] = wt[i];
+    for (int d = 0; d < dim; d++) zeta[i * dim + d] = st * v[i * dim + d];
+  }
+  for (int i = 0; i < q; i++) {
+    opp[i] = -1;
+    for (int j = 0; j < q && opp[i] < 0; j++) {
+      bool neg = true;
+      for (int d = 0; d < dim; d++) neg = neg && zeta[j * dim + d] == -zeta[i * dim + d];
+      if (neg) opp[i] = j;
+    }
+    if (opp[i] < 0) return fail(SLLBM_EINVAL, "velset_cubature: no opposite for velocity %d", i);
+  }
+  return SLLBM_OK;
+}
+
 extern "C" int sllbm_mesh_build(const sllbm_mesh_desc *d, sllbm_mesh *out) {
   if (!d || !out) return fail(SLLBM_EINVAL, "mesh_build: NULL argument");
   *out = nullptr;
@@ -655,10 +740,12 @@ bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]) {
   const int64_t span = m.dim == 3 ? (int64_t)m.N[0] * m.N[1] * (c[2] * P + P + 1)
                                   : (int64_t)m.N[0] * (c[1] * P + P + 1);
   if (span * (int64_t)sizeof(double) >= ((int64_t)1 << 31)) return false;
-  // the tile keeps the tables of the regular departure points in LDS (boundary entries
-  // may add more tables; the gather kernel reads those)
-  for (size_t q = 0; q < t.tab_reg.size(); q++)
-    if (t.tab_reg[q] >= kTileTabs) return false;
+  // the 2D tile keeps the tables of the regular departure points in LDS (boundary entries
+  // may add more tables; the gather kernel reads those); the 3D tile reads each velocity's
+  // weight rows from the tables in device memory, so any number of tables will do
+  if (m.dim == 2)
+    for (size_t q = 0; q < t.tab_reg.size(); q++)
+      if (t.tab_reg[q] >= kTileTabs) return false;
   for (int a = 0; a < m.dim; a++) {
     int T = c[a] * P, N = m.N[a];
     if (m.periodic(a) && N <= T + P) return false;

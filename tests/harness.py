@@ -22,13 +22,17 @@ def field_errors(got, ref):
 class GpuRun:
     """A workload on the GPU through the C-ABI (paper_2412_09051_amd)."""
 
-    def __init__(self, mesh, phys, prec="f64", kernel=0):
+    def __init__(self, mesh, phys, prec="f64", kernel=0, vel="gh"):
+        """vel: "gh" the product rule D{dim}V{5^dim}, "cub" the reduced set D2Q19 / D3Q45."""
         import torch
         import paper_2412_09051_amd as S
         self.S, self.torch = S, torch
         self.mesh, self.phys = mesh, phys
         self.m = S.sllbm_mesh_build(mesh)
-        self.vs = S.sllbm_velset_gauss_hermite(mesh.dim, 5, phys.T0)
+        if vel == "cub":
+            self.vs = S.sllbm_velset_cubature(mesh.dim, phys.T0)
+        else:
+            self.vs = S.sllbm_velset_gauss_hermite(mesh.dim, 5, phys.T0)
         self.prec = S.SLLBM_F32 if prec == "f32" else S.SLLBM_F64
         self.plan = S.sllbm_interp_plan(self.m, self.vs, phys.dt, self.prec)
         if kernel:

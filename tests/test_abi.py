@@ -39,6 +39,31 @@ def test_velocity_set_matches_oracle(dim):
     assert np.array_equal(v["opposite"], o)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("T0", [1.0, 1.3])
+def test_cubature_set_matches_oracle(dim, T0):
+    """The library's closed forms against the oracle's rule solved from the moment conditions,
+    index by index (the oracle's solve carries ~1e-14 relative error in the outer radius: its
+    degree-6 orbit averages are small differences of O(0.1) numbers)."""
+    v = S.sllbm_velset_cubature(dim, T0)
+    z, w, o = oracle.cubature_set(dim, T0)
+    assert v["Q"] == len(w) == (19 if dim == 2 else 45)
+    assert np.max(np.abs(v["zeta"] - z)) < 5e-14 and np.max(np.abs(v["w"] - w)) < 1e-15
+    assert np.array_equal(v["opposite"], o)
+    assert np.array_equal(v["zeta"][v["opposite"]], -v["zeta"])
+
+
+def test_cubature_set_arguments():
+    lib = ctypes.CDLL(S.LIB_PATH)
+    q = ctypes.c_int(0)
+    z = (ctypes.c_double * 135)()
+    assert lib.sllbm_velset_cubature(3, ctypes.c_double(1.0), ctypes.byref(q), None, None, None) == 0 and q.value == 45
+    assert lib.sllbm_velset_cubature(1, ctypes.c_double(1.0), ctypes.byref(q), None, None, None) == S.SLLBM_EINVAL
+    assert lib.sllbm_velset_cubature(2, ctypes.c_double(0.0), ctypes.byref(q), None, None, None) == S.SLLBM_EINVAL
+    assert lib.sllbm_velset_cubature(2, ctypes.c_double(1.0), None, None, None, None) == S.SLLBM_EINVAL
+    assert lib.sllbm_velset_cubature(3, ctypes.c_double(1.0), ctypes.byref(q), z, None, None) == S.SLLBM_EINVAL
+
+
 @pytest.mark.parametrize("n", [3, 4, 5, 7])
 def test_gauss_hermite_roots_match_numpy_rule(n):
     v = S.sllbm_velset_gauss_hermite(1 + 1, n, 1.0)
