@@ -230,7 +230,7 @@ class OrTensor(ctypes.Structure):
         ("T_ref", ctypes.c_double), ("mu_exp", ctypes.c_double),
         ("force", ctypes.c_double * 3),
         ("mass_fix", ctypes.c_int), ("mass_ref", ctypes.c_double),
-        ("node_vol", _dp),
+        ("node_vol", _dp), ("Pr", ctypes.c_double),
     ]
 
 
@@ -289,6 +289,7 @@ class TensorOracle:
             s.force[a] = f[a] if a < mesh.dim else 0.0
         s.mass_fix, s.mass_ref = 0, 0.0
         s.node_vol = _ptr(self.node_vol)
+        s.Pr = getattr(phys, "Pr", 1.0)
         self._s = s
         L = lib()
         L.or_tensor_num_nodes.restype = ctypes.c_size_t
@@ -453,7 +454,7 @@ class OrCurv(ctypes.Structure):
         ("bc_val", _dp), ("gamma", ctypes.c_double), ("dt", ctypes.c_double), ("relax_mode", ctypes.c_int),
         ("tau_bar", ctypes.c_double), ("mu_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
         ("mu_exp", ctypes.c_double), ("force", ctypes.c_double * 2), ("mass_fix", ctypes.c_int),
-        ("mass_ref", ctypes.c_double), ("node_vol", _dp),
+        ("mass_ref", ctypes.c_double), ("node_vol", _dp), ("Pr", ctypes.c_double),
         ("bx0", ctypes.c_double), ("by0", ctypes.c_double), ("bh", ctypes.c_double), ("bnx", ctypes.c_int),
         ("bny", ctypes.c_int), ("bstart", ctypes.POINTER(ctypes.c_int64)), ("bcells", ctypes.POINTER(ctypes.c_int64)),
     ]
@@ -520,6 +521,7 @@ class CurvOracle:
         f = list(phys.force) + [0.0, 0.0]
         s.force[0], s.force[1] = f[0], f[1]
         s.mass_fix, s.mass_ref, s.node_vol = 0, 0.0, _ptr(self.node_vol)
+        s.Pr = getattr(phys, "Pr", 1.0)
         self._s = s
         # bucket width: the median cell extent, capped at ~4M buckets
         ext = np.ptp(self.xyz[self.cells], axis=1).max(axis=1)

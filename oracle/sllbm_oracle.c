@@ -19,7 +19,8 @@
  *   3. conserved moments (eq:density, eq:momentum, energy display; total-energy
  *      reading), isothermal-wall correction (eq:thermalBC);
  *   4. BGK relaxation against the 4th-order Hermite equilibrium (f^eq and g^eq
- *      displays), optional Kupershtokh forcing (Sec. 4.3 forcing displays).
+ *      displays), the quasi-equilibrium term for Pr != 1 (add_quasi_eq), optional
+ *      Kupershtokh forcing (Sec. 4.3 forcing displays).
  * The state stored between steps is the post-collision population set.
  * Collision happens at the nodes and the post-collision field is interpolated; by
  * linearity this is the update display read with nodal equilibria interpolated.
@@ -62,6 +63,7 @@ typedef struct {
   int mass_fix;          /* 1: rescale populations to mass_ref before streaming */
   double mass_ref;
   const double *node_vol;/* [N] integral of each nodal Lagrange function */
+  double Pr;             /* Prandtl number (1: no quasi-equilibrium term) */
 } or_tensor;
 
 /* ------------------------------------------------------------------------- */
@@ -381,6 +383,47 @@ static void node_moments(int D, int Q, const double *zeta, double cv, const doub
   *T = (E - r * uu) / (2.0 * r * cv);
 }
 
+/* Quasi-equilibrium term of the collision (Sec. 3.1 update display: h gains
+ * (1/tau - 1/tau_Pr) h*, tau_Pr = (tau - 1/2)/Pr + 1/2).  The paper defers h* to its
+ * references; reading: the lowest-order Hermite terms that carry the node's heat flux and
+ * no moment of order <= 2, so that the heat flux relaxes with tau_Pr and the stress with
+ * tau.  With c = zeta - u, q_f = 1/2 sum_i c |c|^2 f_i and q_g = 1/2 sum_i c g_i (the
+ * equilibria carry none):
+ *   f*_i = w_i (q_f . zeta_i)(|zeta_i|^2 - (D+2) T0) / ((D+2) T0^3),
+ *   g*_i = 2 w_i (q_g . zeta_i) / T0.
+ * Adds coef * f*_i to fo[i] and coef * g*_i to go[i]. */
+static void add_quasi_eq(int D, int Q, const double *zeta, const double *w, double T0, const double *u,
+                         const double *fs, const double *gs, double coef, double *fo, double *go) {
+  double qf[3] = {0.0, 0.0, 0.0}, qg[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < Q; i++) {
+    double c[3] = {0.0, 0.0, 0.0}, c2 = 0.0;
+    for (int a = 0; a < D; a++) {
+      c[a] = zeta[i * D + a] - u[a];
+      c2 += c[a] * c[a];
+    }
+    for (int a = 0; a < D; a++) {
+      qf[a] += 0.5 * c[a] * c2 * fs[i];
+      qg[a] += 0.5 * c[a] * gs[i];
+    }
+  }
+  for (int i = 0; i < Q; i++) {
+    double z2 = 0.0, qfz = 0.0, qgz = 0.0;
+    for (int a = 0; a < D; a++) {
+      double z = zeta[i * D + a];
+      z2 += z * z;
+      qfz += qf[a] * z;
+      qgz += qg[a] * z;
+    }
+    fo[i] += coef * w[i] * qfz * (z2 - (D + 2) * T0) / ((D + 2) * T0 * T0 * T0);
+    go[i] += coef * 2.0 * w[i] * qgz / T0;
+  }
+}
+
+/* 1/tau_bar - 1/tau_bar_Pr with tau_bar_Pr = (tau_bar - 1/2)/Pr + 1/2 (Sec. 3.1). */
+static double pr_coef(double tb, double Pr) {
+  return 1.0 / tb - 1.0 / ((tb - 0.5) / Pr + 0.5);
+}
+
 /* Post-collision populations of one node k (f into fo[Q], g into go[Q]) from the
  * (already rescaled) input set src. */
 static int node_update(const or_tensor *m, const double *H, const int *Nax, const double *src,
@@ -436,6 +479,7 @@ static int node_update(const or_tensor *m, const double *H, const int *Nax, cons
     fo[i] = fs[i] - (fs[i] - fe[i]) / tb;
     go[i] = gs[i] - (gs[i] - gfac * fe[i]) / tb;
   }
+  if (m->Pr != 1.0) add_quasi_eq(D, Q, m->zeta, m->w, m->T0, u, fs, gs, pr_coef(tb, m->Pr), fo, go);
   int has_force = 0;
   for (int a = 0; a < D; a++) if (m->force[a] != 0.0) has_force = 1;
   if (has_force) {
@@ -610,6 +654,7 @@ typedef struct {
   int mass_fix;
   double mass_ref;
   const double *node_vol;
+  double Pr;
   /* bucket grid over cell bounding boxes (built by or_curv_prepare) */
   double bx0, by0, bh;
   int bnx, bny;
@@ -1146,15 +1191,19 @@ static void curv_node_update(const or_curv *m, const double *H, const double *in
     double u2[3] = {u[0] + m->force[0] * m->dt / rho, u[1] + m->force[1] * m->dt / rho, 0.0};
     feq_all(D, Q, m->w, H, m->T0, rho, u2, T, fe2);
   }
+  double fo[OR_MAXQ], go[OR_MAXQ];
   for (int i = 0; i < Q; i++) {
-    double fo = fs[i] - (fs[i] - fe[i]) / tb;
-    double go = gs[i] - (gs[i] - gfac * fe[i]) / tb;
+    fo[i] = fs[i] - (fs[i] - fe[i]) / tb;
+    go[i] = gs[i] - (gs[i] - gfac * fe[i]) / tb;
+  }
+  if (m->Pr != 1.0) add_quasi_eq(D, Q, m->zeta, m->w, m->T0, u, fs, gs, pr_coef(tb, m->Pr), fo, go);
+  for (int i = 0; i < Q; i++) {
     if (has_force) {
-      fo += fe2[i] - fe[i];
-      go += gfac * (fe2[i] - fe[i]);
+      fo[i] += fe2[i] - fe[i];
+      go[i] += gfac * (fe2[i] - fe[i]);
     }
-    out[(size_t)i * ostride] = fo;
-    out[((size_t)Q + i) * ostride] = go;
+    out[(size_t)i * ostride] = fo[i];
+    out[((size_t)Q + i) * ostride] = go[i];
   }
 }
 

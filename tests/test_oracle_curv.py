@@ -160,13 +160,13 @@ def _box_tensor(p=3, ncell=(5, 4)):
                         face_bc=[[0, 1], [2, 2]], bcs=bcs)
 
 
-@pytest.mark.parametrize("relax_mode", [0, 1])
-def test_axis_aligned_curvilinear_box_matches_tensor_oracle(relax_mode):
+@pytest.mark.parametrize("relax_mode,Pr", [(0, 1.0), (1, 1.0), (1, 0.71)])
+def test_axis_aligned_curvilinear_box_matches_tensor_oracle(relax_mode, Pr):
     """With straight cells the curvilinear oracle (point location, path-face crossing,
     reflection, outlet projection) and the tensor oracle (per-axis tracing) compute the
     same step; 6 steps from a seeded random state."""
     tm = _box_tensor()
-    phys = W.Physics(dt=0.012, relax_mode=relax_mode, tau_bar=0.9, mu_ref=0.01)
+    phys = W.Physics(dt=0.012, relax_mode=relax_mode, tau_bar=0.9, mu_ref=0.01, Pr=Pr)
     cm = W.curv_box(tm)
     ot = oracle.TensorOracle(tm, phys)
     oc = oracle.CurvOracle(cm, phys)

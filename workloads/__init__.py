@@ -67,6 +67,7 @@ class Physics:
     mu_exp: float = 0.0
     force: Sequence[float] = (0.0, 0.0, 0.0)
     T0: float = 1.0
+    Pr: float = 1.0
 
 
 def uniform_edges(n: int, lo: float, hi: float) -> np.ndarray:
