@@ -197,7 +197,15 @@ typedef struct {
                           mu = mu_ref (T/T_ref)^mu_exp (tau = mu/p, Sec. 3.1; power law of
                           Sec. 4.3); 2: streaming and boundary schemes only, no collision */
   double tau_bar, mu_ref, T_ref, mu_exp;
-  double Pr;           /* must be 1 (the quasi-equilibrium term then vanishes): else EUNSUPPORTED */
+  double Pr;           /* Prandtl number, > 0 (EINVAL otherwise).  Pr != 1 adds the collision's
+                          quasi-equilibrium term (Sec. 3.1 update display): (1/tau_bar - 1/tau_Pr) h*,
+                          tau_Pr = (tau_bar - 1/2)/Pr + 1/2, with h* the lowest-order Hermite part that
+                          carries the node's heat flux q (c = zeta - u; q_f = 1/2 sum c|c|^2 f,
+                          q_g = 1/2 sum c g): f*_i = w_i (q_f.zeta_i)(|zeta_i|^2 - (D+2)T0)/((D+2)T0^3),
+                          g*_i = 2 w_i (q_g.zeta_i)/T0.  The paper defers h* to its references; this
+                          form relaxes the heat flux with tau_Pr and leaves rho, j, E and the stress
+                          to the BGK term.  On the two-launch tensor path the relaxation then reads
+                          the populations twice. */
   double force[3];     /* body force per unit volume, Kupershtokh exact difference (Sec. 4.3) */
   int mass_fix;        /* 1: scale all populations by mass_ref/M before streaming (Sec. 4.3) */
   double mass_ref;

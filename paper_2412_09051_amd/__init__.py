@@ -176,7 +176,7 @@ class Params:
     def from_physics(phys, **kw):
         """Marshal a workloads.Physics description."""
         p = Params(gamma=phys.gamma, relax_mode=phys.relax_mode, tau_bar=phys.tau_bar, mu_ref=phys.mu_ref,
-                   T_ref=phys.T_ref, mu_exp=phys.mu_exp, force=tuple(phys.force))
+                   T_ref=phys.T_ref, mu_exp=phys.mu_exp, force=tuple(phys.force), Pr=getattr(phys, "Pr", 1.0))
         for k, v in kw.items():
             setattr(p, k, v)
         return p

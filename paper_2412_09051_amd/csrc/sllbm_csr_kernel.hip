@@ -74,13 +74,16 @@ __device__ __forceinline__ void stream_csr(const DevCsrPlan &pl, const StepArgs 
 struct NodeRelax {
   EqNode eq, eqp, eqf;
   bool thermal, force;
-  double Tpre, gT, itau;
+  double Tpre, gT, itau, u0, u1;
+  PrTerm pt;   // the quasi-equilibrium term (kernels instantiated for Pr != 1)
 };
 
 __device__ __forceinline__ NodeRelax node_relax(const StepArgs &sa, double rho, double j0, double j1, double E,
                                                 double Tw) {
   NodeRelax s;
   double u0 = j0 / rho, u1 = j1 / rho;
+  s.u0 = u0;
+  s.u1 = u1;
   s.Tpre = (E - rho * (u0 * u0 + u1 * u1)) / (2.0 * rho * sa.cv);
   s.thermal = (Tw == Tw);
   double Tn = s.thermal ? Tw : s.Tpre;
@@ -95,6 +98,7 @@ __device__ __forceinline__ NodeRelax node_relax(const StepArgs &sa, double rho, 
   return s;
 }
 
+template <int PR>
 __device__ __forceinline__ void relax_one(const NodeRelax &s, const StepArgs &sa, const double *vi, double f, double g,
                                           double &fo, double &go) {
   double fe = eq_f(s.eq, vi);
@@ -108,6 +112,7 @@ __device__ __forceinline__ void relax_one(const NodeRelax &s, const StepArgs &sa
   if (sa.relax_mode != 2) {
     fo = f - (f - fe) * s.itau;
     go = g - (g - s.gT * fe) * s.itau;
+    if constexpr (PR) pr_add(s.pt, vi, fo, go);
     if (s.force) {
       double df = eq_f(s.eqf, vi) - fe;
       fo += df;
@@ -116,7 +121,7 @@ __device__ __forceinline__ void relax_one(const NodeRelax &s, const StepArgs &sa
   }
 }
 
-template <typename T, int P, int QS>
+template <typename T, int P, int QS, int PR>
 __global__ void __launch_bounds__(kBlock) k_step_csr(const DevCsrPlan pl, const StepArgs sa, const T *__restrict__ pin,
                                                       T *__restrict__ pout) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -137,10 +142,16 @@ __global__ void __launch_bounds__(kBlock) k_step_csr(const DevCsrPlan pl, const 
       E += (vi[0] * vi[0] + vi[1] * vi[1]) * fs[i] + gs[i];
     }
     NodeRelax s = node_relax(sa, rho, j0, j1, E, Tw);
+    if constexpr (PR) {
+      HeatFlux q = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < QS; i++) heat_flux_add(q, pl.vel + 8 * i, s.u0, s.u1, 0.0, fs[i], gs[i]);
+      s.pt = pr_term(q, s.itau, sa, 2);
+    }
 #pragma unroll
     for (int i = 0; i < QS; i++) {
       double fo, go;
-      relax_one(s, sa, pl.vel + 8 * i, fs[i], gs[i], fo, go);
+      relax_one<PR>(s, sa, pl.vel + 8 * i, fs[i], gs[i], fo, go);
       pout[(size_t)i * N + k] = (T)fo;
       pout[((size_t)QS + i) * N + k] = (T)go;
     }
@@ -156,10 +167,19 @@ __global__ void __launch_bounds__(kBlock) k_step_csr(const DevCsrPlan pl, const 
       E += (vi[0] * vi[0] + vi[1] * vi[1]) * f + g;
     }
     NodeRelax s = node_relax(sa, rho, j0, j1, E, Tw);
+    if constexpr (PR) {  // the heat flux needs u: one more streaming pass
+      HeatFlux q = {0, 0, 0, 0, 0, 0};
+      for (int i = 0; i < Q; i++) {
+        double f, g;
+        stream_csr<T, P>(pl, sa, pin, k, i, scale, f, g);
+        heat_flux_add(q, pl.vel + 8 * i, s.u0, s.u1, 0.0, f, g);
+      }
+      s.pt = pr_term(q, s.itau, sa, 2);
+    }
     for (int i = 0; i < Q; i++) {
       double f, g, fo, go;
       stream_csr<T, P>(pl, sa, pin, k, i, scale, f, g);
-      relax_one(s, sa, pl.vel + 8 * i, f, g, fo, go);
+      relax_one<PR>(s, sa, pl.vel + 8 * i, f, g, fo, go);
       pout[(size_t)i * N + k] = (T)fo;
       pout[((size_t)Q + i) * N + k] = (T)go;
     }
@@ -167,17 +187,27 @@ __global__ void __launch_bounds__(kBlock) k_step_csr(const DevCsrPlan pl, const 
 }
 
 namespace {
+// D2V25 and D2Q19 keep a node's streamed values in registers between moments and relaxation;
+// PR = 1 instantiates the Prandtl-number term (Pr != 1), PR = 0 leaves it out
+template <typename T, int P, int PR>
+void launch_csr_q(sllbm_plan_s *Pl, dim3 grid, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
+  if (Pl->cp.Q == 25)
+    hipLaunchKernelGGL((k_step_csr<T, P, 25, PR>), grid, dim3(kBlock), 0, s, Pl->cp, a, (const T *)pin, (T *)pout);
+  else if (Pl->cp.Q == 19)
+    hipLaunchKernelGGL((k_step_csr<T, P, 19, PR>), grid, dim3(kBlock), 0, s, Pl->cp, a, (const T *)pin, (T *)pout);
+  else
+    hipLaunchKernelGGL((k_step_csr<T, P, 0, PR>), grid, dim3(kBlock), 0, s, Pl->cp, a, (const T *)pin, (T *)pout);
+}
+
 template <typename T, int P>
 void launch_csr_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
   dim3 grid((unsigned)((Pl->cp.N + kBlock - 1) / kBlock));
   ProfScope ps(Pl, "k_step_csr", s);
-  // D2V25 and D2Q19 keep a node's streamed values in registers between moments and relaxation
-  if (Pl->cp.Q == 25)
-    hipLaunchKernelGGL((k_step_csr<T, P, 25>), grid, dim3(kBlock), 0, s, Pl->cp, a, (const T *)pin, (T *)pout);
-  else if (Pl->cp.Q == 19)
-    hipLaunchKernelGGL((k_step_csr<T, P, 19>), grid, dim3(kBlock), 0, s, Pl->cp, a, (const T *)pin, (T *)pout);
-  else
-    hipLaunchKernelGGL((k_step_csr<T, P, 0>), grid, dim3(kBlock), 0, s, Pl->cp, a, (const T *)pin, (T *)pout);
+  if (a.pr_on) {
+    launch_csr_q<T, P, 1>(Pl, grid, a, pin, pout, s);
+  } else {
+    launch_csr_q<T, P, 0>(Pl, grid, a, pin, pout, s);
+  }
 }
 }  // namespace
 

@@ -40,8 +40,8 @@ int upload(sllbm_plan_s *P, const std::vector<V> &h, const V **dptr) {
 int check_params(const sllbm_plan_s *P, const sllbm_params *prm) {
   if (!prm) return fail(SLLBM_EINVAL, "params is NULL");
   if (!(prm->gamma > 1.0)) return fail(SLLBM_EINVAL, "gamma must be > 1");
-  if (prm->Pr != 1.0)
-    return fail(SLLBM_EUNSUPPORTED, "Pr = %g: only Pr = 1 (no quasi-equilibrium term) is implemented", prm->Pr);
+  if (!(prm->Pr > 0.0) || !std::isfinite(prm->Pr))
+    return fail(SLLBM_EINVAL, "Pr must be a positive finite number (got %g)", prm->Pr);
   if (prm->relax_mode < 0 || prm->relax_mode > 2) return fail(SLLBM_EINVAL, "relax_mode must be 0, 1 or 2");
   if (prm->relax_mode == 0 && !(prm->tau_bar > 0.5))
     return fail(SLLBM_EINVAL, "tau_bar must be > 1/2 (got %g)", prm->tau_bar);
@@ -75,6 +75,8 @@ StepArgs make_args(const sllbm_plan_s *P, const sllbm_params *prm) {
     a.force[d] = d < D ? prm->force[d] : 0.0;
     if (a.force[d] != 0.0) a.has_force = 1;
   }
+  a.Pr = prm->Pr;
+  a.pr_on = (prm->Pr != 1.0 && prm->relax_mode != 2) ? 1 : 0;
   a.force_dev = nullptr;
   if (prm->force_device) {
     a.force_dev = P->scratch + kSlotForce;

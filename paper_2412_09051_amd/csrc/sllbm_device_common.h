@@ -63,6 +63,58 @@ __device__ __forceinline__ double eq_f(const EqNode &e, const double *vel) {
   return vel[7] * e.rho * poly;
 }
 
+// ------------------------------------------------------------------ Prandtl-number term
+// The collision of Sec. 3.1 adds (1/tau - 1/tau_Pr) h*_i with tau_Pr = (tau - 1/2)/Pr + 1/2.
+// h* (deferred to the paper's references; this library's reading) is the lowest-order
+// Hermite part that carries the node's heat flux and no moment of order <= 2:
+//   f*_i = w_i (q_f . zeta_i)(|zeta_i|^2 - (D+2) T0) / ((D+2) T0^3),  g*_i = 2 w_i (q_g . zeta_i) / T0,
+// with c = zeta - u, q_f = 1/2 sum_i c |c|^2 f_i, q_g = 1/2 sum_i c g_i over the streamed
+// values.  The equilibria carry no heat flux, so the isothermal-wall correction leaves q as it is.
+struct HeatFlux {
+  double f0, f1, f2, g0, g1, g2;
+};
+
+__device__ __forceinline__ void heat_flux_add(HeatFlux &q, const double *vel, double u0, double u1, double u2,
+                                              double f, double g) {
+  const double c0 = vel[0] - u0, c1 = vel[1] - u1, c2 = vel[2] - u2;
+  const double hf = 0.5 * (c0 * c0 + c1 * c1 + c2 * c2) * f, hg = 0.5 * g;
+  q.f0 += c0 * hf;
+  q.f1 += c1 * hf;
+  q.f2 += c2 * hf;
+  q.g0 += c0 * hg;
+  q.g1 += c1 * hg;
+  q.g2 += c2 * hg;
+}
+
+// Per-node coefficients of the term: af = coef q_f / ((D+2) T0^2), ag = 2 coef q_g / T0, so
+// that coef f*_i = w_i (af . zeta_i)(|xi_i|^2 - (D+2)) and coef g*_i = w_i (ag . zeta_i).
+struct PrTerm {
+  double af0, af1, af2, ag0, ag1, ag2, dp2;
+};
+
+__device__ __forceinline__ PrTerm pr_term(const HeatFlux &q, double inv_tau, const StepArgs &a, int D) {
+  const double tpr = (1.0 / inv_tau - 0.5) / a.Pr + 0.5;
+  const double coef = inv_tau - 1.0 / tpr;
+  const double cf = coef / ((D + 2) * a.T0 * a.T0), cg = 2.0 * coef / a.T0;
+  PrTerm p;
+  p.af0 = cf * q.f0;
+  p.af1 = cf * q.f1;
+  p.af2 = cf * q.f2;
+  p.ag0 = cg * q.g0;
+  p.ag1 = cg * q.g1;
+  p.ag2 = cg * q.g2;
+  p.dp2 = (double)(D + 2);
+  return p;
+}
+
+// vel: [zeta x,y,z, xi x,y,z, |xi|^2, w] of one velocity
+__device__ __forceinline__ void pr_add(const PrTerm &p, const double *vel, double &fo, double &go) {
+  const double zf = p.af0 * vel[0] + p.af1 * vel[1] + p.af2 * vel[2];
+  const double zg = p.ag0 * vel[0] + p.ag1 * vel[1] + p.ag2 * vel[2];
+  fo += vel[7] * zf * (vel[6] - p.dp2);
+  go += vel[7] * zg;
+}
+
 // ------------------------------------------------------------------ tensor streaming
 template <typename T> struct WeightSel;
 template <> struct WeightSel<double> {

@@ -25,6 +25,8 @@ struct StepArgs {
   double tau_bar, mu_ref, T_ref, mu_exp;
   double force[3];
   int has_force;
+  double Pr;                       // Prandtl number
+  int pr_on;                       // 1: Pr != 1 and a collision: add the quasi-equilibrium term
   const double *force_dev;         // device force [3] of the plan's controller, or nullptr
   const double *scale;             // device mass-rescale factor, or nullptr
   const double *inlet;             // device [n_bc][5] inlet states

@@ -85,7 +85,7 @@ struct Slab {
   int64_t total;   // nodes in the slab
 };
 
-template <typename T, int D, int P>
+template <typename T, int D, int P, int PR>
 __global__ void __launch_bounds__(kBlock) k_step_gather(const DevTensorPlan pl, const StepArgs sa, const Slab sl,
                                                          const T *__restrict__ pin, T *__restrict__ pout) {
   const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -149,9 +149,18 @@ __global__ void __launch_bounds__(kBlock) k_step_gather(const DevTensorPlan pl, 
     inv_tau = 1.0 / (mu / (rho * Tn * sa.dt) + 0.5);
   }
   const double gT = Tn * sa.gbase;
+  PrTerm pt;
+  if constexpr (PR) {  // Pr != 1: the heat flux of the stored streamed values (it needs u)
+    HeatFlux hq = {0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < Q; i++)
+      heat_flux_add(hq, pl.vel + 8 * i, u0, u1, u2, (double)pout[(size_t)i * pl.N + k],
+                    (double)pout[((size_t)Q + i) * pl.N + k]);
+    pt = pr_term(hq, inv_tau, sa, D);
+  }
 
   // sweep 2: read the stored streamed values back (this thread wrote them), isothermal-wall
-  // correction (eq:thermalBC), BGK relaxation, Kupershtokh forcing, store
+  // correction (eq:thermalBC), BGK relaxation, quasi-equilibrium term, Kupershtokh forcing,
+  // store
   for (int i = 0; i < Q; i++) {
     double fv = (double)pout[(size_t)i * pl.N + k];
     double gv = (double)pout[((size_t)Q + i) * pl.N + k];
@@ -166,6 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_step_gather(const DevTensorPlan pl, 
     if (sa.relax_mode != 2) {
       fo = fv - (fv - fe) * inv_tau;
       go = gv - (gv - gT * fe) * inv_tau;
+      if constexpr (PR) pr_add(pt, vi, fo, go);
       if (sa.has_force) {
         double df = eq_f(eqf, vi) - fe;
         fo += df;
@@ -308,8 +318,12 @@ void launch_gather_t(sllbm_plan_s *Pl, const StepArgs &a, const Slab &sl, const 
                      hipStream_t s) {
   if (sl.total <= 0) return;
   ProfScope ps(Pl, "k_step_gather", s);
-  hipLaunchKernelGGL((k_step_gather<T, D, P>), dim3((unsigned)nblocks(sl.total)), dim3(kBlock), 0, s, Pl->tp, a, sl,
-                     (const T *)pin, (T *)pout);
+  if (a.pr_on)
+    hipLaunchKernelGGL((k_step_gather<T, D, P, 1>), dim3((unsigned)nblocks(sl.total)), dim3(kBlock), 0, s, Pl->tp, a,
+                       sl, (const T *)pin, (T *)pout);
+  else
+    hipLaunchKernelGGL((k_step_gather<T, D, P, 0>), dim3((unsigned)nblocks(sl.total)), dim3(kBlock), 0, s, Pl->tp, a,
+                       sl, (const T *)pin, (T *)pout);
 }
 
 template <typename T>

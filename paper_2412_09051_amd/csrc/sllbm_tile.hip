@@ -129,7 +129,7 @@ __device__ __forceinline__ int wrap_idx(int g, int N) {
 //   node straight out of X; store; moments.
 // So the loads of a velocity are in flight for a whole iteration, and the y work of
 // velocity i overlaps the staging of i+1.
-template <typename T, int D, int P, int CX, int CY, int CZ, int BS, int WPE, int QR>
+template <typename T, int D, int P, int CX, int CY, int CZ, int BS, int WPE, int QR, int PR>
 __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl, const StepArgs sa, const TileGrid tg,
                                                     const T *__restrict__ pin, T *__restrict__ pout,
                                                     double *__restrict__ nstate) {
@@ -420,6 +420,13 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
       EqNode ef = e;
       if (sa.has_force) ef = eq_forced(r, u0, u1, u2, Tn, sa, D);
       const double gT = Tn * sa.gbase;
+      PrTerm pt;
+      if constexpr (PR) {  // Pr != 1
+        HeatFlux hq = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < QR; i++) heat_flux_add(hq, pl.vel + 8 * i, u0, u1, u2, (double)fs[m][i], (double)gs[m][i]);
+        pt = pr_term(hq, it, sa, D);
+      }
 #pragma unroll
       for (int i = 0; i < QR; i++) {
         const double *vi = pl.vel + 8 * i;
@@ -427,6 +434,7 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
         const double fe = eq_f(e, vi);
         double fo = f - (f - fe) * it;
         double go = g - (g - gT * fe) * it;
+        if constexpr (PR) pr_add(pt, vi, fo, go);
         if (sa.has_force) {
           const double df = eq_f(ef, vi) - fe;
           fo += df;
@@ -745,7 +753,7 @@ template <typename T> struct VecOf<T, 1> { typedef T type; };
 template <> struct VecOf<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
 template <> struct VecOf<float, 2> { typedef float type __attribute__((ext_vector_type(2))); };
 
-template <typename T, int D, int V>
+template <typename T, int D, int V, int PR>
 __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, const StepArgs sa,
                                                         T *__restrict__ pop, const double *__restrict__ nstate) {
   typedef typename VecOf<T, V>::type VT;
@@ -781,6 +789,28 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
   for (int v = 0; v < V; v++) any = any || act[v];
   if (!any) return;   // all in a boundary layer (or past N): nothing to read or write
   const int Q = pl.Q;
+  PrTerm pt[V];
+  if constexpr (PR) {  // Pr != 1: a first pass over the populations for the heat flux
+    HeatFlux hq[V];
+    double uu[V][3];
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+      hq[v] = {0, 0, 0, 0, 0, 0};
+      const int64_t kk = act[v] ? k0 + v : k0;
+      uu[v][0] = nstate[N + kk];
+      uu[v][1] = nstate[2 * N + kk];
+      uu[v][2] = nstate[3 * N + kk];
+    }
+    for (int i = 0; i < Q; i++) {
+      const double *vi = pl.vel + 8 * i;
+      VT fvec = *(const VT *)(pop + (size_t)i * N + k0), gvec = *(const VT *)(pop + ((size_t)Q + i) * N + k0);
+#pragma unroll
+      for (int v = 0; v < V; v++)
+        if (act[v]) heat_flux_add(hq[v], vi, uu[v][0], uu[v][1], uu[v][2], (double)((T *)&fvec)[v], (double)((T *)&gvec)[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < V; v++) pt[v] = pr_term(hq[v], itau[v], sa, D);
+  }
   for (int i = 0; i < Q; i++) {
     const double *vi = pl.vel + 8 * i;
     VT *pf = (VT *)(pop + (size_t)i * N + k0);
@@ -795,6 +825,7 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
       const double fe = eq_f(e[v], vi);
       double fo = f - (f - fe) * itau[v];
       double go = g - (g - gT[v] * fe) * itau[v];
+      if constexpr (PR) pr_add(pt[v], vi, fo, go);
       if (sa.has_force) {
         const double df = eq_f(ef[v], vi) - fe;
         fo += df;
@@ -830,8 +861,12 @@ int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *po
       // single pass: the 2Q streamed values of a node stay in registers
       constexpr int WPES = 3;
       ProfScope ps(Pl, "k_step_tile", s);
-      hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPES, kStashQ>), dim3(ntiles), dim3(BS), 0, s, tp, a,
-                         tg, (const T *)pin, (T *)pout, Pl->nstate);
+      if (a.pr_on)
+        hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPES, kStashQ, 1>), dim3(ntiles), dim3(BS), 0, s, tp,
+                           a, tg, (const T *)pin, (T *)pout, Pl->nstate);
+      else
+        hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPES, kStashQ, 0>), dim3(ntiles), dim3(BS), 0, s, tp,
+                           a, tg, (const T *)pin, (T *)pout, Pl->nstate);
       return SLLBM_OK;
     }
   }
@@ -841,20 +876,31 @@ int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *po
       hipLaunchKernelGGL((k_step_tile3d<T, D, P, CX, CY, CZ, BS, WPE>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
                          (const T *)pin, (T *)pout, Pl->nstate);
     else
-      hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPE, 0>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
+      hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPE, 0, 0>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
                          (const T *)pin, (T *)pout, Pl->nstate);
   }
   {
     ProfScope ps(Pl, "k_relax_nodes", s);
     // FP64 with even N (rows keep 2-node groups aligned): 16-byte vector accesses, 4 % faster;
     // in FP32 the 8-byte pairs gain nothing
+    // (Pr != 1: the instantiation with the quasi-equilibrium term, which reads the populations
+    // twice)
     if (sizeof(T) == 8 && tp.N % 2 == 0) {
-      const int64_t nthreads = tp.N / 2;
-      hipLaunchKernelGGL((k_relax_nodes<T, D, 2>), dim3((unsigned)((nthreads + kBlock - 1) / kBlock)), dim3(kBlock),
-                         0, s, tp, a, (T *)pout, (const double *)Pl->nstate);
+      const dim3 grid((unsigned)((tp.N / 2 + kBlock - 1) / kBlock));
+      if (a.pr_on)
+        hipLaunchKernelGGL((k_relax_nodes<T, D, 2, 1>), grid, dim3(kBlock), 0, s, tp, a, (T *)pout,
+                           (const double *)Pl->nstate);
+      else
+        hipLaunchKernelGGL((k_relax_nodes<T, D, 2, 0>), grid, dim3(kBlock), 0, s, tp, a, (T *)pout,
+                           (const double *)Pl->nstate);
     } else {
-      hipLaunchKernelGGL((k_relax_nodes<T, D, 1>), dim3((unsigned)((tp.N + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                         s, tp, a, (T *)pout, (const double *)Pl->nstate);
+      const dim3 grid((unsigned)((tp.N + kBlock - 1) / kBlock));
+      if (a.pr_on)
+        hipLaunchKernelGGL((k_relax_nodes<T, D, 1, 1>), grid, dim3(kBlock), 0, s, tp, a, (T *)pout,
+                           (const double *)Pl->nstate);
+      else
+        hipLaunchKernelGGL((k_relax_nodes<T, D, 1, 0>), grid, dim3(kBlock), 0, s, tp, a, (T *)pout,
+                           (const double *)Pl->nstate);
     }
   }
   return SLLBM_OK;

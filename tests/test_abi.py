@@ -200,9 +200,10 @@ def test_step_argument_validation_before_any_launch():
     prm = S.Params.from_physics(phys)
     n_bytes = 2 * plan.Q * plan.N * 8
     a, b = 1 << 20, (1 << 20) + 4 * n_bytes   # never dereferenced: validation fails first
-    bad = S.Params.from_physics(phys, Pr=0.71)
-    assert lib.sllbm_step(plan.handle, ctypes.byref(bad.c()), _fake_ptr(a), _fake_ptr(b), None) == S.SLLBM_EUNSUPPORTED
-    assert "Pr" in lib.sllbm_last_error().decode()
+    for pr in (0.0, -0.7, float("inf"), float("nan")):
+        bad = S.Params.from_physics(phys, Pr=pr)
+        assert lib.sllbm_step(plan.handle, ctypes.byref(bad.c()), _fake_ptr(a), _fake_ptr(b), None) == S.SLLBM_EINVAL
+        assert "Pr" in lib.sllbm_last_error().decode()
     assert lib.sllbm_step(plan.handle, ctypes.byref(prm.c()), _fake_ptr(a), _fake_ptr(a + 64), None) == S.SLLBM_EINVAL
     assert "overlap" in lib.sllbm_last_error().decode()
     assert lib.sllbm_step(plan.handle, ctypes.byref(prm.c()), _fake_ptr(a + 4), _fake_ptr(b), None) == S.SLLBM_EINVAL
