@@ -210,9 +210,11 @@ def precision_leg(ncell, steps=1000, every=100):
             "history": {k: [round(x, 10) for x in v] for k, v in hist.items()}}
 
 
-def tensor_case_leg(case, prec, steps, warmup, Pr=1.0):
+def tensor_case_leg(case, prec, steps, warmup, Pr=1.0, vel="gh"):
     """Another tensor-product workload: C1-R (2D shear wave at roofline scale) or C4 (the
-    supersonic channel, with the mass rescaling every 10 steps), at Prandtl number Pr."""
+    supersonic channel, with the mass rescaling every 10 steps), at Prandtl number Pr, on the
+    product rule (vel "gh") or the reduced set ("cub": the time step keeps CFL 0.9 on the
+    set's largest component)."""
     import dataclasses
     import torch
     import paper_2412_09051_amd as S
@@ -225,9 +227,13 @@ def tensor_case_leg(case, prec, steps, warmup, Pr=1.0):
         mesh, phys = W.channel_case()
         fields = W.channel_fields
         fix_every = 10
+    if vel == "cub":
+        vs = S.sllbm_velset_cubature(mesh.dim, phys.T0)
+        phys = dataclasses.replace(phys, dt=phys.dt * W.ZETA_MAX_GH5 / float(np.max(np.abs(vs["zeta"]))))
+    else:
+        vs = S.sllbm_velset_gauss_hermite(mesh.dim, 5, phys.T0)
     m = S.sllbm_mesh_build(mesh)
-    plan = S.sllbm_interp_plan(m, S.sllbm_velset_gauss_hermite(mesh.dim, 5, phys.T0), phys.dt,
-                               S.SLLBM_F32 if prec == "f32" else S.SLLBM_F64)
+    plan = S.sllbm_interp_plan(m, vs, phys.dt, S.SLLBM_F32 if prec == "f32" else S.SLLBM_F64)
     prm = S.Params.from_physics(phys, Pr=Pr)
     N, Q = plan.N, plan.Q
     rho, u, T = fields(S.sllbm_mesh_nodes(m))
@@ -603,10 +609,17 @@ def main():
                       flush=True)
     extra = {}
     if not args.no_extra:
-        for case, precs in (("c1r", ("f64", "f32")), ("c4", ("f32",)), ("c4pr", ("f32",))):
+        # (case, precisions, Prandtl number, velocity set); the paper's channel set-up (D3Q45,
+        # Pr 0.7) belongs to the reduced-set legs
+        cases = [("c1r", ("f64", "f32"), 1.0, "gh"), ("c4", ("f32",), 1.0, "gh"), ("c4pr", ("f32",), 0.7, "gh")]
+        if vset == "d3q45":
+            cases = []
+        if not args.no_cubature:
+            cases += [("c1rq19", ("f64", "f32"), 1.0, "cub"), ("c4paper", ("f32",), 0.7, "cub")]
+        for case, precs, Pr, vel in cases:
             for prec in precs:
-                extra[f"{case}_{prec}"] = tensor_case_leg(case.replace("pr", ""), prec, max(10, args.steps // 5), 3,
-                                                          Pr=0.7 if case == "c4pr" else 1.0)
+                extra[f"{case}_{prec}"] = tensor_case_leg("c1r" if case.startswith("c1r") else "c4", prec,
+                                                          max(10, args.steps // 5), 3, Pr=Pr, vel=vel)
                 print(f"# {case} {prec} done: {extra[f'{case}_{prec}']['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
     prec_cmp = None
     if not args.no_fp32 and args.precision_steps > 0:
@@ -685,7 +698,11 @@ def main():
              "c4": "3D supersonic channel Ma_b 1.5 Re_b 3000, 128x96x64 cells p=2 (6.3M nodes), D3V125, "
                    "isothermal walls, forcing held by the PI force controller and mass rescaling, both every 10 steps",
              "c4pr": "the same channel at the paper's Prandtl number 0.7 (the collision's quasi-equilibrium term; "
-                     "the relaxation launch reads the populations twice)"}
+                     "the relaxation launch reads the populations twice)",
+             "c1rq19": "the same 2D shear wave on the reduced velocity set D2Q19 (CFL 0.5 on its largest component; "
+                       "single-pass tile with the wide weight-table count)",
+             "c4paper": "the same channel with the paper's set-up: reduced velocity set D3Q45 (CFL 0.9 on its largest "
+                        "component) and Prandtl number 0.7"}
     for key, v in extra.items():
         case, prec = key.split("_")
         out[key] = {"workload": names[case], "dtype": prec, "value": round(v["gqups"], 4), "unit": "GQUPS",

@@ -2,6 +2,7 @@
 // equilibrium initialisation, moments and deterministic FP64 reductions.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <cstdio>
@@ -168,6 +169,7 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
   if (P->kernel == 0) {
     int c[3];
     P->tile_ok = tile_cells(m.dim, m.p, c) && tile_eligible(m, t, c) ? 1 : 0;
+    for (int id : t.tab_reg) P->tile_tabs = std::max(P->tile_tabs, id + 1);
   }
 
   // velocity constants: zeta x,y,z, xi = zeta/sqrt(T0), |xi|^2, w

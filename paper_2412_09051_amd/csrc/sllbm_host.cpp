@@ -745,7 +745,7 @@ bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]) {
   // weight rows from the tables in device memory, so any number of tables will do
   if (m.dim == 2)
     for (size_t q = 0; q < t.tab_reg.size(); q++)
-      if (t.tab_reg[q] >= kTileTabs) return false;
+      if (t.tab_reg[q] >= kTileTabsMax) return false;
   for (int a = 0; a < m.dim; a++) {
     int T = c[a] * P, N = m.N[a];
     if (m.periodic(a) && N <= T + P) return false;

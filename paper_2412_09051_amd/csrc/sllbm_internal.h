@@ -177,6 +177,7 @@ struct sllbm_plan_s {
   int has_device = 0;
   int device = -1;
   int tile_ok = 0;              // the LDS-tiled kernel applies to this plan
+  int tile_tabs = 0;            // 1 + the largest table id of a regular departure point
   int kernel_choice = 0;        // 0 auto, 1 baseline gather, 2 tiled
   sllbm::DevTensorPlan tp{};
   sllbm::DevCsrPlan cp{};

@@ -32,10 +32,12 @@ struct StepArgs {
   const double *inlet;             // device [n_bc][5] inlet states
 };
 
-// The tiled kernel keeps the weight rows of the interpolation tables of the regular
+// The 2D tiled kernel keeps the weight rows of the interpolation tables of the regular
 // departure points in LDS: their table ids (one per distinct velocity component along
-// an axis) must be below this bound.
+// an axis) must be below the kernel's table count, kTileTabs (the product rule D2V25: five
+// components per axis) or kTileTabsMax (the reduced set D2Q19 needs eleven along x).
 constexpr int kTileTabs = 5;
+constexpr int kTileTabsMax = 16;
 
 // Cell-aligned tile (cells per axis) of the LDS-tiled step kernel for (dim, order).
 template <int D, int P> struct TileShape;

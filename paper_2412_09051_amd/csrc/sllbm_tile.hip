@@ -30,8 +30,10 @@ namespace sllbm {
 #endif
 
 // 2D plans with this many velocities (D2V25) run the single-pass tile kernel, at 3 waves
-// per SIMD (FP64: 168 VGPRs and a 36-byte spill, which beats 2 waves without one)
+// per SIMD (FP64: 168 VGPRs and a 36-byte spill, which beats 2 waves without one); so do
+// plans on the reduced set D2Q19 (with the wide table count)
 constexpr int kStashQ = 25;
+constexpr int kStashQ19 = 19;
 
 struct TileGrid {
   int nt[3];   // tiles per axis
@@ -129,7 +131,7 @@ __device__ __forceinline__ int wrap_idx(int g, int N) {
 //   node straight out of X; store; moments.
 // So the loads of a velocity are in flight for a whole iteration, and the y work of
 // velocity i overlaps the staging of i+1.
-template <typename T, int D, int P, int CX, int CY, int CZ, int BS, int WPE, int QR, int PR>
+template <typename T, int D, int P, int CX, int CY, int CZ, int BS, int WPE, int QR, int PR, int NTAB>
 __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl, const StepArgs sa, const TileGrid tg,
                                                     const T *__restrict__ pin, T *__restrict__ pout,
                                                     double *__restrict__ nstate) {
@@ -144,8 +146,8 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
   constexpr int NW = TX + TY + TZ;           // weight rows of one table: one per tile position and axis
   __shared__ T S[2 * SS];
   __shared__ T X[2 * XS];
-  __shared__ T WT[kTileTabs * NW * (P + 1)];   // row tb * NW + (axis base) + t
-  __shared__ int OT[kTileTabs * NW];           // stencil start relative to the table's region
+  __shared__ T WT[NTAB * NW * (P + 1)];   // row tb * NW + (axis base) + t
+  __shared__ int OT[NTAB * NW];           // stencil start relative to the table's region
 
   const int Q = pl.Q;
   const int tid = threadIdx.x;
@@ -190,7 +192,7 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
 
   // weight rows and stencil offsets of every table of every axis, for this tile (read
   // by the passes of all velocities; the loop's first barrier publishes them)
-  for (int r = tid; r < kTileTabs * NW; r += BS) {
+  for (int r = tid; r < NTAB * NW; r += BS) {
     const int tb = r / NW, q0 = r % NW;
     const int ax = q0 < TX ? 0 : (q0 < TX + TY ? 1 : 2);
     const int t = q0 - (ax == 0 ? 0 : (ax == 1 ? TX : TX + TY));
@@ -842,6 +844,20 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
 // ------------------------------------------------------------------ launcher
 
 namespace {
+// single pass: the 2Q streamed values of a node stay in registers (3 waves per SIMD);
+// PR = 1 instantiates the Prandtl-number term
+template <typename T, int P, int CX, int CY, int BS, int QR, int NTAB>
+void launch_tile2d_single(const DevTensorPlan &tp, const StepArgs &a, const TileGrid &tg, int ntiles, const void *pin,
+                          void *pout, double *nstate, hipStream_t s) {
+  constexpr int WPES = 3;
+  if (a.pr_on)
+    hipLaunchKernelGGL((k_step_tile2d<T, 2, P, CX, CY, 1, BS, WPES, QR, 1, NTAB>), dim3(ntiles), dim3(BS), 0, s, tp, a,
+                       tg, (const T *)pin, (T *)pout, nstate);
+  else
+    hipLaunchKernelGGL((k_step_tile2d<T, 2, P, CX, CY, 1, BS, WPES, QR, 0, NTAB>), dim3(ntiles), dim3(BS), 0, s, tp, a,
+                       tg, (const T *)pin, (T *)pout, nstate);
+}
+
 template <typename T, int D, int P, int CX, int CY, int CZ>
 int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
   constexpr int BS = D == 3 ? 512 : 256;   // threads per workgroup
@@ -856,17 +872,18 @@ int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *po
   int ntiles = tg.nt[0] * tg.nt[1] * tg.nt[2];
   tg.q = ntiles / 8;
   tg.r = ntiles % 8;
+  // 2D: the tables of the regular departure points fit the narrow table count (D2V25) or
+  // the wide one (D2Q19); plans with a stash-sized Q run single-pass
+  const bool wide = Pl->tile_tabs > kTileTabs;
   if constexpr (D == 2) {
-    if (tp.Q == kStashQ) {
-      // single pass: the 2Q streamed values of a node stay in registers
-      constexpr int WPES = 3;
+    if (tp.Q == kStashQ && !wide) {
       ProfScope ps(Pl, "k_step_tile", s);
-      if (a.pr_on)
-        hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPES, kStashQ, 1>), dim3(ntiles), dim3(BS), 0, s, tp,
-                           a, tg, (const T *)pin, (T *)pout, Pl->nstate);
-      else
-        hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPES, kStashQ, 0>), dim3(ntiles), dim3(BS), 0, s, tp,
-                           a, tg, (const T *)pin, (T *)pout, Pl->nstate);
+      launch_tile2d_single<T, P, CX, CY, BS, kStashQ, kTileTabs>(tp, a, tg, ntiles, pin, pout, Pl->nstate, s);
+      return SLLBM_OK;
+    }
+    if (tp.Q == kStashQ19 && wide) {
+      ProfScope ps(Pl, "k_step_tile", s);
+      launch_tile2d_single<T, P, CX, CY, BS, kStashQ19, kTileTabsMax>(tp, a, tg, ntiles, pin, pout, Pl->nstate, s);
       return SLLBM_OK;
     }
   }
@@ -875,9 +892,12 @@ int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *po
     if constexpr (D == 3)
       hipLaunchKernelGGL((k_step_tile3d<T, D, P, CX, CY, CZ, BS, WPE>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
                          (const T *)pin, (T *)pout, Pl->nstate);
+    else if (wide)
+      hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPE, 0, 0, kTileTabsMax>), dim3(ntiles), dim3(BS), 0, s,
+                         tp, a, tg, (const T *)pin, (T *)pout, Pl->nstate);
     else
-      hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPE, 0, 0>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
-                         (const T *)pin, (T *)pout, Pl->nstate);
+      hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPE, 0, 0, kTileTabs>), dim3(ntiles), dim3(BS), 0, s,
+                         tp, a, tg, (const T *)pin, (T *)pout, Pl->nstate);
   }
   {
     ProfScope ps(Pl, "k_relax_nodes", s);

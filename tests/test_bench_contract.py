@@ -31,7 +31,8 @@ def test_traffic_summary_matches_the_kernel_sources():
     d = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
     h = b.kernel_source_hash()
     for key in ("tgv_f64", "tgv_f32", "tgv45_f64", "tgv45_f32", "ogrid_f64", "ogrid_f32", "ogrid19_f64", "ogrid19_f32",
-                "c1r_f64", "c1r_f32", "c4_f32", "c4pr_f32"):
+                "c1r_f64", "c1r_f32", "c4_f32", "c4pr_f32", "c4paper_f32",
+                "c1rq19_f64", "c1rq19_f32"):
         e = d[key]
         assert e["kernel_source_hash"] == h, (key, "counters taken on other kernel sources: re-profile")
         assert e["bytes_per_launch"] == e["read_bytes"] + e["write_bytes"] > 0

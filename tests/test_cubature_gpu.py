@@ -107,26 +107,34 @@ def test_d3q45_channel_thermal_walls_forcing(prec, tol, kernel):
 
 # ------------------------------------------------------------------ D2Q19
 
-def test_d2q19_shear_wave_fp64_100_steps():
-    """2D tensor meshes with D2Q19 run the gather kernel: the 2D tile keeps at most five
-    tables per axis in LDS and D2Q19 needs eleven along x."""
-    say("D2Q19 shear wave fp64 16^2 p4 100 steps")
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_d2q19_shear_wave_100_steps(prec, tol, kernel):
+    """2D tensor meshes on D2Q19: the single-pass tile with the wide table count (eleven
+    displacements along x), and the gather kernel."""
+    say("D2Q19 shear wave 16^2 p4 100 steps", prec, kernel)
     mesh, phys = W.shear_wave_case(ncell=16, p=4)
-    o, g = _tensor(mesh, phys, "f64")
-    assert g.kernel == 0
-    import paper_2412_09051_amd as S
-    with pytest.raises(S.SllbmError):
-        S.sllbm_plan_select_kernel(g.plan, TILED)
-    _compare(o, g, lambda x: W.shear_wave_fields(x, noise=1e-3, seed=2), 100, TOL64)
+    o, g = _tensor(mesh, phys, prec, kernel)
+    assert g.kernel == (2 if kernel == TILED else 0)
+    _compare(o, g, lambda x: W.shear_wave_fields(x, noise=1e-3, seed=2), 100, tol, compare_pops=(prec == "f64"))
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_d2q19_tiled_lower_orders_fp64(p):
+    say("D2Q19 vortex tiled p", p)
+    mesh, phys = W.vortex_case(ncell=16, p=p)
+    o, g = _tensor(mesh, phys, "f64", TILED)
+    _compare(o, g, lambda x: W.vortex_fields(x), 20, TOL64)
 
 
 def test_d2q19_bounce_back_stretched_fp64():
     say("D2Q19 stretched channel with bounce-back walls")
-    tm = W.TensorMesh(dim=2, p=3, nodes="gll", ncell=(8, 6),
-                      edges=[W.uniform_edges(8, 0.0, 2.0), W.tanh_edges(6, 1.5)],
+    tm = W.TensorMesh(dim=2, p=3, nodes="gll", ncell=(12, 6),
+                      edges=[W.uniform_edges(12, 0.0, 3.0), W.tanh_edges(6, 1.5)],
                       face_bc=[[-1, -1], [0, 0]], bcs=[W.BC(kind=W.BC_WALL)])
     phys = W.Physics(dt=0.02, relax_mode=0, tau_bar=0.9)
     o, g = _tensor(tm, phys, "f64")
+    assert g.kernel == 2   # wall slabs by the gather kernel, the interior by the tile
     _compare(o, g, lambda x: W.random_fields(x.shape[0], 2, seed=41, u_mean=(0.3, 0.0)), 20, TOL64)
 
 

@@ -83,6 +83,15 @@ def test_2d_single_pass_tile(prec, tol, relax_mode):
              expect_kernel=2)
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_2d_single_pass_tile_d2q19(prec, tol):
+    say("Pr 0.71 2D single-pass tile on D2Q19", prec)
+    mesh, phys = W.shear_wave_case(ncell=16, p=4)
+    phys = dataclasses.replace(phys, Pr=0.71)
+    _compare(mesh, phys, prec, _thermal_shear, 30, tol, kernel=TILED, vel="cub", compare_pops=(prec == "f64"),
+             expect_kernel=2)
+
+
 def test_2d_gather_fp64():
     say("Pr 0.71 2D gather")
     mesh, phys = W.shear_wave_case(ncell=8, p=4)
