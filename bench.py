@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-ogrid", action="store_true", help="skip the curvilinear O-grid workload")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction (mixing layer) workload")
+    ap.add_argument("--learned-steps", type=int, default=None,
+                    help="coarse steps of each mixing-layer run (default: to the end of the self-similar window)")
     ap.add_argument("--learned-mach", default="0.7",
                     help="convective Mach numbers of the learned-correction legs, comma separated (first one is 'learned')")
     ap.add_argument("--no-extra", action="store_true", help="skip the C1-R (2D roofline-scale) and C4 (channel) lines")
@@ -356,8 +358,13 @@ def mixing_dtheta(S, torch, plan, prm, pop, shape, du, V, box):
     return float((wy * rbar * (0.5 * du - ut) * (0.5 * du + ut)).sum() / du ** 2)
 
 
-def learned_leg(ncell=16, ratio=4, steps=300, n_train=8, train_iters=1500, Ma_c=0.7, alphas=(0.0, 0.25, 0.5, 1.0),
-                targets="injected"):
+# extent of the self-similar stage of the temporal mixing layer, tau = t du / dtheta0
+# (Tab. 3, tau_min and tau_max per convective Mach number)
+MIX_WINDOW = {0.3: (350.0, 550.0), 0.7: (450.0, 700.0), 0.9: (800.0, 1100.0), 1.2: (1400.0, 2000.0)}
+
+
+def learned_leg(ncell=16, ratio=4, steps=None, n_train=8, train_iters=1500, Ma_c=0.7, alphas=(0.0, 0.25, 0.5, 1.0),
+                targets="injected", vel="gh", Pr=1.0):
     """C5: temporal mixing layer on a coarse mesh, plain and with the learned correction,
     against the 4x finer mesh; FP32 populations.  The network is trained by the library's
     kernels on restricted one-step samples of a fine run (seed 5); a gain alpha on its
@@ -366,7 +373,11 @@ def learned_leg(ncell=16, ratio=4, steps=300, n_train=8, train_iters=1500, Ma_c=
     and time per coarse step.  targets="injected": a sample starts the plain coarse step
     from the restricted fine state; "trajectory": from the plain coarse run started at the
     restricted initial state, so that the features come from coarse-evolved states as in
-    use and the target includes the drift accumulated so far."""
+    use and the target includes the drift accumulated so far.  vel "cub" runs the reduced set
+    D3Q45 (at the same time step) and Pr the Prandtl number (the paper's mixing layer: D3Q45,
+    Pr 0.71).  steps = None runs to the end of the self-similar window; the growth rate of
+    the momentum thickness is fitted inside the window (else over the run's second half)."""
+    import dataclasses
     import torch
     import paper_2412_09051_amd as S
     import workloads as W
@@ -374,11 +385,18 @@ def learned_leg(ncell=16, ratio=4, steps=300, n_train=8, train_iters=1500, Ma_c=
     box = tuple(ncell * c * d0 for c in MIX_BOX_CELLS)
     mesh, phys = W.mixing_layer_case(ncell=(ncell,) * 3, box=box, Ma_c=Ma_c)
     fmesh, fphys = W.mixing_layer_case(ncell=(ncell,) * 3, refine=ratio, box=box, Ma_c=Ma_c)
+    phys, fphys = dataclasses.replace(phys, Pr=Pr), dataclasses.replace(fphys, Pr=Pr)
+    vname = "D3Q45" if vel == "cub" else "D3V125"
     du = 2.0 * Ma_c * math.sqrt(1.4)
+    tau_step = phys.dt * du / d0                      # tau per coarse step
+    window = MIX_WINDOW.get(round(Ma_c, 2))
+    if steps is None:
+        steps = int(math.ceil(window[1] / tau_step)) if window else 1000
     mats = {}
     for name, (me, ph) in (("c", (mesh, phys)), ("f", (fmesh, fphys))):
         mm = S.sllbm_mesh_build(me)
-        pl = S.sllbm_interp_plan(mm, S.sllbm_velset_gauss_hermite(3, 5, ph.T0), ph.dt, S.SLLBM_F32)
+        vs = S.sllbm_velset_cubature(3, ph.T0) if vel == "cub" else S.sllbm_velset_gauss_hermite(3, 5, ph.T0)
+        pl = S.sllbm_interp_plan(mm, vs, ph.dt, S.SLLBM_F32)
         shape = tuple(me.ncell[a] * me.p + (0 if me.face_bc[a][0] < 0 else 1) for a in range(3))
         V = torch.tensor(S.sllbm_mesh_volumes(mm), device="cuda").view(shape[2], shape[1], shape[0])
         mats[name] = (mm, pl, S.Params.from_physics(ph), shape, V)
@@ -467,6 +485,19 @@ def learned_leg(ncell=16, ratio=4, steps=300, n_train=8, train_iters=1500, Ma_c=
         gr = [v - ref[0] for v in ref]
         return max(abs(a - b) / abs(b) for a, b in zip(g[1:], gr[1:]))
 
+    tau_h = tau_step * every_h * np.arange(steps // every_h + 1)      # tau of each history sample
+    in_window = (tau_h >= window[0]) & (tau_h <= window[1]) if window else np.zeros(len(tau_h), bool)
+    if in_window.sum() < 3:
+        in_window = np.arange(len(tau_h)) >= len(tau_h) // 2
+
+    def late_rate(h):
+        """Growth rate d(dtheta)/d(tau) of the momentum thickness in the self-similar window
+        (least squares over the samples inside it)."""
+        return float(np.polyfit(tau_h[in_window], np.asarray(h)[in_window], 1)[0])
+
+    def rate_err(h, ref):
+        return abs(late_rate(h) - late_rate(ref)) / abs(late_rate(ref))
+
     # ---- training on seed 5
     t0 = time.perf_counter()
     c5, f5, X, T, _ = fine_history(5, samples=True)
@@ -483,17 +514,21 @@ def learned_leg(ncell=16, ratio=4, steps=300, n_train=8, train_iters=1500, Ma_c=
         if want:
             losses.append(l_)
     del X, T
+    print(f"# learned Ma_c {Ma_c} {vname}: fine run and training done ({steps} coarse steps, loss {losses})",
+          file=sys.stderr, flush=True)
     # ---- output gain chosen on the training run's momentum thickness
     theta = S.sllbm_mlp_get_params(net)
     o4 = nf * 64 + 64 + 2 * (64 * 64 + 64)           # W4, b4 follow
-    sel = {}
+    sel, sel_growth = {}, {}
     for a in alphas:
         th = theta.copy()
         th[o4:] *= a
         S.sllbm_mlp_set_params(net, th)
         h, _ = coarse_rollout(c5, None if a == 0.0 else net)
-        sel[a] = growth_err(h, f5)
+        sel[a] = rate_err(h, f5)
+        sel_growth[a] = growth_err(h, f5)
     alpha = min(sel, key=sel.get)
+    print(f"# learned Ma_c {Ma_c} {vname}: gain {alpha} selected ({sel})", file=sys.stderr, flush=True)
     th = theta.copy()
     th[o4:] *= alpha
     S.sllbm_mlp_set_params(net, th)
@@ -507,15 +542,25 @@ def learned_leg(ncell=16, ratio=4, steps=300, n_train=8, train_iters=1500, Ma_c=
     hist = {"fine": f6, "plain": hp, "learned": hl}
     return {
         "workload": f"3D temporal mixing layer Ma_c {Ma_c}, coarse {ncell}^3 cells p=2 ({Nc} nodes) vs "
-                    f"{ratio}x finer ({Nf} nodes), D3V125, FP32; trained on seed 5, evaluated on seed 6",
+                    f"{ratio}x finer ({Nf} nodes), {vname}, Pr {Pr}, FP32; trained on seed 5, evaluated on seed 6",
         "steps": steps, "targets": targets, "train_samples": n_train, "train_iters": train_iters, "train_loss": losses,
-        "train_s": round(train_s, 2), "alpha_selection_growth_err": {str(k): round(v, 4) for k, v in sel.items()},
+        "train_s": round(train_s, 2),
+        "alpha_selection_window_rate_err": {str(k): round(v, 4) for k, v in sel.items()},
+        "alpha_selection_growth_err": {str(k): round(v, 4) for k, v in sel_growth.items()},
         "alpha": alpha,
         "ms_per_coarse_step": {"fine": round(t_f / steps, 4), "plain": round(t_p / steps, 4),
                                "learned": round(t_l / steps, 4)},
         "time_to_solution_ratio": {"fine_vs_learned": round(t_f / t_l, 2), "fine_vs_plain": round(t_f / t_p, 2)},
         "dtheta": {k: [round(v, 6) for v in h] for k, h in hist.items()},
         "dtheta_growth_max_rel_err": {"plain": round(growth_err(hp, f6), 4), "learned": round(growth_err(hl, f6), 4)},
+        "tau_per_step": round(tau_step, 5),
+        "self_similar_window_tau": list(window) if window else None,
+        "window_samples": int(in_window.sum()),
+        "dtheta_rate_in_window": {"fine": late_rate(f6), "plain": late_rate(hp), "learned": late_rate(hl),
+                                  "plain_rel_err": round(rate_err(hp, f6), 4),
+                                  "learned_rel_err": round(rate_err(hl, f6), 4)},
+        "dtheta_final_rel_err": {"plain": round(abs(hp[-1] - f6[-1]) / f6[-1], 4),
+                                 "learned": round(abs(hl[-1] - f6[-1]) / f6[-1], 4)},
         "finite": {k: all(math.isfinite(v) for v in h) for k, h in hist.items()},
     }
 
@@ -631,13 +676,18 @@ def main():
     if not args.no_learned:
         machs = [float(x) for x in args.learned_mach.split(",")]
         for i, mc in enumerate(machs):
-            r = learned_leg(Ma_c=mc)
+            r = learned_leg(Ma_c=mc, steps=args.learned_steps)
             print(f"# learned Ma_c {mc} done: time-to-solution ratio {r['time_to_solution_ratio']}", file=sys.stderr,
                   flush=True)
             if i == 0:
                 lrn = r
             else:
                 lrn_more[str(mc)] = r
+    lrn_paper = None
+    if not args.no_learned and not args.no_cubature:
+        lrn_paper = learned_leg(Ma_c=0.7, vel="cub", Pr=0.71, steps=args.learned_steps)
+        print(f"# learned, the paper's mixing-layer set-up (D3Q45, Pr 0.71) done: time-to-solution ratio "
+              f"{lrn_paper['time_to_solution_ratio']}", file=sys.stderr, flush=True)
     cal = copy_calibration() if args.copy_calibration else None
     ceil = copy_ceiling()
     print(f"# device copy: {ceil['GBs']} GB/s", file=sys.stderr, flush=True)
@@ -715,6 +765,8 @@ def main():
         out["learned"] = lrn
         if lrn_more:
             out["learned_other_mach"] = lrn_more
+    if lrn_paper:
+        out["learned_paper_setup"] = lrn_paper
     out["copy_ceiling"] = dict(ceil, note="1 GiB device-to-device copy, read + written bytes per second: the "
                                           "practical HBM peak; step_frac and frac are against 8 TB/s")
     if cal:

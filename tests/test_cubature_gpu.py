@@ -193,3 +193,54 @@ def test_d3q45_tgv_full_size_one_step_sampled(prec):
     e = rel_err(gq, ref)
     say("sampled pop error", e)
     assert e <= (TOL64 if prec == "f64" else 2e-6)
+
+
+# ------------------------------------------------------------------ boundaries and modes
+
+def test_d3q45_inlet_outlet_3d():
+    say("D3Q45 3D inlet + outlet")
+    mesh = W.TensorMesh(dim=3, p=2, nodes="glc", ncell=(3, 4, 3),
+                        edges=[W.uniform_edges(3, 0, 1.5), W.uniform_edges(4, 0, 2.0), W.uniform_edges(3, 0, 1.5)],
+                        face_bc=[[-1, -1], [0, 1], [-1, -1]],
+                        bcs=[W.BC(kind=W.BC_INLET, rho=1.0, u=(0, 0.4, 0), T=1.0), W.BC(kind=W.BC_OUTLET)])
+    phys = W.Physics(dt=0.04, relax_mode=0, tau_bar=0.9)
+    o, g = _tensor(mesh, phys, "f64")
+    _compare(o, g, lambda x: W.random_fields(x.shape[0], 3, seed=7, u_amp=0.2, u_mean=(0, 0.4, 0)), 10, TOL64)
+
+
+def test_d2q19_moving_equilibrium_walls():
+    say("D2Q19 moving equilibrium walls")
+    mesh = W.TensorMesh(dim=2, p=2, nodes="gll", ncell=(6, 5), edges=[W.uniform_edges(6, 0, 3.0),
+                                                                    W.uniform_edges(5, -1.0, 1.0)],
+                        face_bc=[[-1, -1], [0, 1]],
+                        bcs=[W.BC(kind=W.BC_INLET, rho=1.0, u=(-0.5, 0, 0), T=1.0),
+                             W.BC(kind=W.BC_INLET, rho=1.0, u=(0.5, 0, 0), T=1.0)])
+    phys = W.Physics(dt=0.04, relax_mode=0, tau_bar=0.9)
+    o, g = _tensor(mesh, phys, "f64")
+    _compare(o, g, lambda x: W.random_fields(x.shape[0], 2, seed=6, u_amp=0.2), 15, TOL64)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_reduced_sets_linear_elements_gather(dim):
+    """p = 1 (no tile kernel for it): the gather kernel on both reduced sets."""
+    say("reduced set p=1 gather, dim", dim)
+    if dim == 2:
+        mesh, phys = W.shear_wave_case(ncell=24, p=1)
+        fields = lambda x: W.shear_wave_fields(x, noise=1e-3, seed=2)
+    else:
+        mesh, phys = W.tgv_case(ncell=10, p=1, dt=W.TGV_DT)
+        fields = W.tgv_fields
+    o, g = _tensor(mesh, phys, "f64")
+    assert g.kernel == 0
+    _compare(o, g, fields, 10, TOL64)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_d3q45_pure_streaming_and_mass_fix(kernel):
+    import dataclasses
+    say("D3Q45 streaming only, then mass fix", kernel)
+    mesh, phys = W.tgv_case(ncell=6, p=3)
+    o, g = _tensor(mesh, dataclasses.replace(phys, relax_mode=2), "f64", kernel)
+    _compare(o, g, W.tgv_fields, 5, TOL64)
+    o, g = _tensor(mesh, phys, "f64", kernel)
+    _compare(o, g, W.tgv_fields, 9, TOL64, mass_fix_every=3)

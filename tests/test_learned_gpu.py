@@ -39,11 +39,12 @@ def _S():
     return S
 
 
-def _plan(mesh, phys, prec="f64"):
+def _plan(mesh, phys, prec="f64", vel="gh"):
     S = _S()
     m = S.sllbm_mesh_build(mesh)
-    plan = S.sllbm_interp_plan(m, S.sllbm_velset_gauss_hermite(mesh.dim, 5, phys.T0), phys.dt,
-                               S.SLLBM_F32 if prec == "f32" else S.SLLBM_F64)
+    vs = S.sllbm_velset_cubature(mesh.dim, phys.T0) if vel == "cub" else S.sllbm_velset_gauss_hermite(mesh.dim, 5,
+                                                                                                       phys.T0)
+    plan = S.sllbm_interp_plan(m, vs, phys.dt, S.SLLBM_F32 if prec == "f32" else S.SLLBM_F64)
     return m, plan
 
 
@@ -212,6 +213,50 @@ def test_correction_matches_oracle_and_keeps_moments(prec):
     d = M @ (got - popin).reshape(2 * o.Q, o.N)
     scale = np.max(np.abs(M @ popin.reshape(2 * o.Q, o.N)))
     assert np.max(np.abs(d)) <= (1e-12 if prec == "f64" else 1e-5) * scale
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_correction_and_targets_on_d3q45(prec):
+    """The learned part on the reduced set D3Q45 at the paper's mixing-layer Prandtl number
+    0.71: 2Q = 90 network outputs (padded to the 16-wide MFMA tiles), targets and the
+    projected correction against the oracle, conserved moments untouched."""
+    import dataclasses
+    torch, S = _torch(), _S()
+    mesh, phys = W.mixing_layer_case(ncell=(4, 4, 4), box=BOX)
+    phys = dataclasses.replace(phys, Pr=0.71)
+    vel = oracle.cubature_set(3, phys.T0)
+    o = oracle.TensorOracle(mesh, phys, vel=vel)
+    _, plan = _plan(mesh, phys, prec, vel="cub")
+    assert plan.Q == 45
+    net = S.sllbm_mlp_create(20, 2 * o.Q, seed=23)
+    theta = S.sllbm_mlp_get_params(net)
+    rho, u, T = W.mixing_layer_fields(o.coords(), box=BOX, amp=0.2)
+    pop = o.run(o.init(rho, u, T), 2)
+    dt = torch.float32 if prec == "f32" else torch.float64
+    pt = torch.tensor(pop, dtype=dt, device="cuda")
+    popin = pt.double().cpu().numpy()
+    prm = S.Params.from_physics(phys)
+    # targets: a plain step against a perturbed "truth"
+    plain = o.step(popin)
+    truth = plain * (1 + 0.01 * np.sin(np.arange(plain.size)))
+    t = torch.zeros(o.N, 2 * o.Q, dtype=torch.float32, device="cuda")
+    S.sllbm_learned_targets(plan, torch.tensor(plain, dtype=dt, device="cuda"), torch.tensor(truth, dtype=dt, device="cuda"), t)
+    S.sllbm_mlp_correct(plan, prm, net, pt)
+    torch.cuda.synchronize()
+    pin, tin = (plain, truth) if prec == "f64" else (plain.astype(np.float32).astype(np.float64),
+                                                      truth.astype(np.float32).astype(np.float64))
+    et = _rel(t.cpu().numpy(), L.targets(o.zeta, o.w, pin, tin))
+    got = pt.double().cpu().numpy()
+    ref = L.correct(mesh, o.zeta, o.w, phys.gamma, popin, _params_list(theta, 20, 2 * o.Q))
+    dg = (got - popin).reshape(2 * o.Q, o.N)
+    dr = (ref - popin).reshape(2 * o.Q, o.N)
+    per_node = np.linalg.norm(dg - dr, axis=0) / np.linalg.norm(dr, axis=0)
+    say("D3Q45 targets rel error", et, "correction per-node median", np.median(per_node), "max", per_node.max())
+    assert et <= (1e-6 if prec == "f64" else 1e-5)
+    assert np.median(per_node) <= (1e-6 if prec == "f64" else 1e-4) and (per_node > 1e-4).mean() <= 0.02
+    M = L.invariants(o.zeta)
+    d = M @ dg
+    assert np.max(np.abs(d)) <= (1e-12 if prec == "f64" else 1e-5) * np.max(np.abs(M @ popin.reshape(2 * o.Q, o.N)))
 
 
 def test_trained_network_beats_the_plain_coarse_step():
