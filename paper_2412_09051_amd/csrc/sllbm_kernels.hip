@@ -14,6 +14,8 @@
 // moments, the temperature solve, the equilibrium and all reductions are FP64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 
 #include "sllbm_device_common.h"
@@ -79,9 +81,10 @@ __global__ void __launch_bounds__(kBlock) k_reduce_final(const double *__restric
   }
 }
 
-// Nodes with n[axis] in [lo, lo + cnt) (the whole mesh: axis 0, lo 0, cnt N_x).
+// Nodes with n[axis] < lo_cnt or n[axis] >= N_axis - hi_cnt: the boundary layers of both
+// faces of the bounded axis in one launch (the whole mesh: axis 0, lo_cnt N_x, hi_cnt 0).
 struct Slab {
-  int axis, lo, cnt;
+  int axis, lo_cnt, hi_cnt;
   int64_t total;   // nodes in the slab
 };
 
@@ -93,9 +96,11 @@ __global__ void __launch_bounds__(kBlock) k_step_gather(const DevTensorPlan pl, 
   const int Q = pl.Q;
   int n[3];
   {
-    // slab axis fastest, then the remaining axes in x, y, z order
-    int64_t r = q / sl.cnt;
-    n[sl.axis] = sl.lo + (int)(q % sl.cnt);
+    // slab axis fastest (low layers, then high layers), then the remaining axes in x, y, z order
+    const int span = sl.lo_cnt + sl.hi_cnt;
+    int64_t r = q / span;
+    const int l = (int)(q % span);
+    n[sl.axis] = l < sl.lo_cnt ? l : pl.ax[sl.axis].N - sl.hi_cnt + (l - sl.lo_cnt);
     for (int a = 0; a < 3; a++) {
       if (a == sl.axis) continue;
       n[a] = (int)(r % pl.ax[a].N);
@@ -354,18 +359,25 @@ int launch_step(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout
     // interior nodes: LDS-tiled kernel; boundary-layer slabs: per-node gather
     rc = launch_step_tile(Pl, a, pin, pout, s);
     if (rc) return rc;
+    // the faces with boundary layers all lie on the one bounded axis: one launch covers both
+    Slab sl{-1, 0, 0, 0};
     for (int f = 0; f < tp.nfaces; f++) {
       const DevFace &F = tp.face[f];
       if (F.depth <= 0) continue;
-      Slab sl;
+      if (sl.axis >= 0 && sl.axis != F.axis)
+        return fail(SLLBM_EUNSUPPORTED, "boundary layers on two axes of a tensor plan");
       sl.axis = F.axis;
-      sl.cnt = F.depth;
-      sl.lo = F.side == 0 ? 0 : tp.ax[F.axis].N - F.depth;
-      sl.total = (int64_t)F.depth * (tp.N / tp.ax[F.axis].N);
+      (F.side == 0 ? sl.lo_cnt : sl.hi_cnt) = F.depth;
+    }
+    if (sl.axis >= 0) {
+      const int Na = tp.ax[sl.axis].N;
+      sl.lo_cnt = std::min(sl.lo_cnt, Na);
+      sl.hi_cnt = std::min(sl.hi_cnt, Na - sl.lo_cnt);   // layers of both faces overlap on a thin mesh
+      sl.total = (int64_t)(sl.lo_cnt + sl.hi_cnt) * (tp.N / Na);
       if ((rc = gather(sl))) return rc;
     }
   } else {
-    Slab sl{0, 0, tp.ax[0].N, tp.N};
+    Slab sl{0, tp.ax[0].N, 0, tp.N};
     rc = gather(sl);
   }
   if (rc) return rc;
