@@ -86,14 +86,31 @@ __global__ void __launch_bounds__(kBlock) k_reduce_final(const double *__restric
 struct Slab {
   int axis, lo_cnt, hi_cnt;
   int64_t total;   // nodes in the slab
+  int lanes;       // lanes per node: 1, 2 or 4 (set by the launcher)
 };
+
+// Lanes per node of the gather kernel (Slab::lanes, at most kGatherLanes): a node's
+// velocities are dealt round-robin to an aligned group of lanes, whose partial moments are
+// summed by shuffles within the group (a group is either all inside the slab or all past it,
+// so the lanes a shuffle reads are active).  Small slabs take 4 lanes per node so that the
+// launch still fills the chip; large ones 1, so that a load instruction covers 64 nodes of
+// one population rather than 16 nodes of four.
+constexpr int kGatherLanes = 4;
 
 template <typename T, int D, int P, int PR>
 __global__ void __launch_bounds__(kBlock) k_step_gather(const DevTensorPlan pl, const StepArgs sa, const Slab sl,
                                                          const T *__restrict__ pin, T *__restrict__ pout) {
-  const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  static_assert(kBlock % kGatherLanes == 0 && 64 % kGatherLanes == 0, "lane groups must not straddle a wave");
+  const int lanes = sl.lanes;
+  const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t q = gt / lanes;
+  const int sub = (int)(gt % lanes);
   if (q >= sl.total) return;
   const int Q = pl.Q;
+  auto group_sum = [lanes](double v) __attribute__((always_inline)) {
+    for (int o = 1; o < lanes; o <<= 1) v += __shfl_xor(v, o, lanes);
+    return v;
+  };
   int n[3];
   {
     // slab axis fastest (low layers, then high layers), then the remaining axes in x, y, z order
@@ -126,7 +143,7 @@ __global__ void __launch_bounds__(kBlock) k_step_gather(const DevTensorPlan pl, 
   // sweep 1: stream every velocity, store the streamed value in this node's output slot
   // and sum the conserved moments (eq:density, eq:momentum, total energy)
   double rho = 0, j0 = 0, j1 = 0, j2 = 0, E = 0;
-  for (int i = 0; i < Q; i++) {
+  for (int i = sub; i < Q; i += lanes) {
     double fv, gv;
     stream_tp<T, D, P>(pl, sa, pin, n, i, er[0], er[1], fax[0], fax[1], scale, fv, gv);
     pout[(size_t)i * pl.N + k] = (T)fv;
@@ -138,6 +155,11 @@ __global__ void __launch_bounds__(kBlock) k_step_gather(const DevTensorPlan pl, 
     j2 += vi[2] * fv;
     E += (vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2]) * fv + gv;
   }
+  rho = group_sum(rho);
+  j0 = group_sum(j0);
+  j1 = group_sum(j1);
+  j2 = group_sum(j2);
+  E = group_sum(E);
   const double u0 = j0 / rho, u1 = j1 / rho, u2 = j2 / rho;
   const double Tpre = (E - rho * (u0 * u0 + u1 * u1 + u2 * u2)) / (2.0 * rho * sa.cv);
   const bool thermal = (Tw == Tw);
@@ -157,16 +179,22 @@ __global__ void __launch_bounds__(kBlock) k_step_gather(const DevTensorPlan pl, 
   PrTerm pt;
   if constexpr (PR) {  // Pr != 1: the heat flux of the stored streamed values (it needs u)
     HeatFlux hq = {0, 0, 0, 0, 0, 0};
-    for (int i = 0; i < Q; i++)
+    for (int i = sub; i < Q; i += lanes)
       heat_flux_add(hq, pl.vel + 8 * i, u0, u1, u2, (double)pout[(size_t)i * pl.N + k],
                     (double)pout[((size_t)Q + i) * pl.N + k]);
+    hq.f0 = group_sum(hq.f0);
+    hq.f1 = group_sum(hq.f1);
+    hq.f2 = group_sum(hq.f2);
+    hq.g0 = group_sum(hq.g0);
+    hq.g1 = group_sum(hq.g1);
+    hq.g2 = group_sum(hq.g2);
     pt = pr_term(hq, inv_tau, sa, D);
   }
 
   // sweep 2: read the stored streamed values back (this thread wrote them), isothermal-wall
   // correction (eq:thermalBC), BGK relaxation, quasi-equilibrium term, Kupershtokh forcing,
   // store
-  for (int i = 0; i < Q; i++) {
+  for (int i = sub; i < Q; i += lanes) {
     double fv = (double)pout[(size_t)i * pl.N + k];
     double gv = (double)pout[((size_t)Q + i) * pl.N + k];
     const double *vi = pl.vel + 8 * i;
@@ -318,17 +346,26 @@ __global__ void k_force_reset(double *__restrict__ force, double *__restrict__ f
 namespace {
 int64_t nblocks(int64_t N) { return (N + kBlock - 1) / kBlock; }
 
+// lanes per node for a gather launch over `nodes` nodes: enough lanes for about 4096 waves
+// (256 CUs at 4 waves per SIMD), at most kGatherLanes
+int gather_lanes(int64_t nodes) {
+  int lanes = 1;
+  while (lanes < kGatherLanes && nodes * lanes < 4096 * 64) lanes *= 2;
+  return lanes;
+}
+
 template <typename T, int D, int P>
 void launch_gather_t(sllbm_plan_s *Pl, const StepArgs &a, const Slab &sl, const void *pin, void *pout,
                      hipStream_t s) {
   if (sl.total <= 0) return;
   ProfScope ps(Pl, "k_step_gather", s);
+  const dim3 grid((unsigned)nblocks(sl.total * sl.lanes));
   if (a.pr_on)
-    hipLaunchKernelGGL((k_step_gather<T, D, P, 1>), dim3((unsigned)nblocks(sl.total)), dim3(kBlock), 0, s, Pl->tp, a,
-                       sl, (const T *)pin, (T *)pout);
+    hipLaunchKernelGGL((k_step_gather<T, D, P, 1>), grid, dim3(kBlock), 0, s, Pl->tp, a, sl, (const T *)pin,
+                       (T *)pout);
   else
-    hipLaunchKernelGGL((k_step_gather<T, D, P, 0>), dim3((unsigned)nblocks(sl.total)), dim3(kBlock), 0, s, Pl->tp, a,
-                       sl, (const T *)pin, (T *)pout);
+    hipLaunchKernelGGL((k_step_gather<T, D, P, 0>), grid, dim3(kBlock), 0, s, Pl->tp, a, sl, (const T *)pin,
+                       (T *)pout);
 }
 
 template <typename T>
@@ -360,7 +397,7 @@ int launch_step(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout
     rc = launch_step_tile(Pl, a, pin, pout, s);
     if (rc) return rc;
     // the faces with boundary layers all lie on the one bounded axis: one launch covers both
-    Slab sl{-1, 0, 0, 0};
+    Slab sl{-1, 0, 0, 0, 1};
     for (int f = 0; f < tp.nfaces; f++) {
       const DevFace &F = tp.face[f];
       if (F.depth <= 0) continue;
@@ -374,10 +411,11 @@ int launch_step(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout
       sl.lo_cnt = std::min(sl.lo_cnt, Na);
       sl.hi_cnt = std::min(sl.hi_cnt, Na - sl.lo_cnt);   // layers of both faces overlap on a thin mesh
       sl.total = (int64_t)(sl.lo_cnt + sl.hi_cnt) * (tp.N / Na);
+      sl.lanes = gather_lanes(sl.total);
       if ((rc = gather(sl))) return rc;
     }
   } else {
-    Slab sl{0, tp.ax[0].N, 0, tp.N};
+    Slab sl{0, tp.ax[0].N, 0, tp.N, gather_lanes(tp.N)};
     rc = gather(sl);
   }
   if (rc) return rc;
