@@ -332,3 +332,14 @@ def test_2d_single_pass_controlled_force():
     e = rel_err(g.pop(), pop)
     say("pop error", e)
     assert e <= TOL64
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_gather_two_lanes_per_node(prec, tol):
+    """A gather launch of 131,072-262,143 nodes deals each node's velocities over two lanes
+    (smaller launches four, larger one): 96 x 96 cells p = 4 (147,456 nodes) on the gather
+    kernel, 5 steps, the whole field against the oracle."""
+    say("gather, two lanes per node: shear wave 96^2 p4", prec)
+    mesh, phys = W.shear_wave_case(ncell=96, p=4)
+    _run_compare(mesh, phys, prec, lambda x: W.shear_wave_fields(x, noise=1e-3, seed=4), 5, tol,
+                 compare_pops=(prec == "f64"), kernel=GATHER)
