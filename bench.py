@@ -17,6 +17,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -620,8 +621,37 @@ def cpu_leg(ncell, steps):
         pop = o.step(pop)
     el = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    # one thread: the oracle's step at a seeded sample of nodes, in a child process started
+    # with OMP_NUM_THREADS=1 (it imports the oracle and numpy only)
+    code = ("import time, numpy as np, oracle, workloads as W\n"
+            f"mesh, phys = W.tgv_case(ncell={ncell})\n"
+            "o = oracle.TensorOracle(mesh, phys)\n"
+            "rho, u, T = W.tgv_fields(o.coords())\n"
+            "pop = o.init(rho, u, T)\n"
+            "nodes = np.sort(np.random.Generator(np.random.PCG64(3)).choice(o.N, 8192, replace=False)).astype(np.int64)\n"
+            "t0 = time.perf_counter()\n"
+            "o.step_nodes(pop, nodes)\n"
+            "el = time.perf_counter() - t0\n"
+            "print(len(nodes) * o.Q / el / 1e9, el)\n")
+    one = None
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=dict(os.environ, OMP_NUM_THREADS="1"), cwd=ROOT,
+                           capture_output=True, text=True, timeout=900)
+        v, t1 = (float(x) for x in r.stdout.split()[-2:])
+        one = {"value": v, "unit": "GQUPS", "cores": 1, "sample": f"the step at 8192 seeded nodes, FP64, {t1:.1f} s"}
+    except (subprocess.SubprocessError, ValueError):
+        one = None
     return {"value": o.N * o.Q * steps / el / 1e9, "unit": "GQUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} full step(s) of the {o.N}-node mesh, FP64, {el:.1f} s"}
+            "sample": f"{steps} full step(s) of the {o.N}-node mesh, FP64, {el:.1f} s", "cpu_model": model,
+            "one_thread": one}
 
 
 def roofline(r, traffic=None):
