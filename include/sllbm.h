@@ -162,7 +162,9 @@ typedef struct {
                                 1 CSR (curvilinear), 2 tensor-product LDS-tiled */
 } sllbm_plan_info_t;
 int sllbm_plan_info(sllbm_plan p, sllbm_plan_info_t *info);
-/* Choose the step kernel of a tensor-product plan: 0 automatic (tiled when it applies),
+/* Choose the step kernel of a tensor-product plan: 0 automatic (tiled when it applies and the
+ * mesh has at least 256 tiles, one per compute unit; smaller meshes step faster on the gather
+ * kernel),
  * 1 the per-node gather kernel, 2 the LDS-tiled kernel (SLLBM_EUNSUPPORTED when a
  * departure stencil leaves the one-cell halo the tile stages, e.g. CFL > 1).  Both
  * compute the same step; the choice exists for testing and measurement. */

@@ -169,6 +169,11 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
   if (P->kernel == 0) {
     int c[3];
     P->tile_ok = tile_cells(m.dim, m.p, c) && tile_eligible(m, t, c) ? 1 : 0;
+    if (P->tile_ok) {
+      int64_t ntiles = 1;
+      for (int a = 0; a < m.dim; a++) ntiles *= (m.N[a] + c[a] * m.p - 1) / (c[a] * m.p);
+      P->tile_auto = ntiles >= kTileMinTiles ? 1 : 0;
+    }
     for (int id : t.tab_reg) P->tile_tabs = std::max(P->tile_tabs, id + 1);
   }
 
@@ -297,7 +302,7 @@ extern "C" int sllbm_plan_info(sllbm_plan P, sllbm_plan_info_t *info) {
   info->n_thermal_nodes = P->n_thermal;
   info->table_bytes = P->table_bytes;
   info->has_device = P->has_device;
-  info->kernel = P->kernel == 1 ? 1 : ((P->tile_ok && P->kernel_choice != 1) ? 2 : 0);
+  info->kernel = P->kernel == 1 ? 1 : (P->use_tile() ? 2 : 0);
   return SLLBM_OK;
 }
 

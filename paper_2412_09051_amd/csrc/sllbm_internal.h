@@ -179,6 +179,9 @@ struct sllbm_plan_s {
   int tile_ok = 0;              // the LDS-tiled kernel applies to this plan
   int tile_tabs = 0;            // 1 + the largest table id of a regular departure point
   int kernel_choice = 0;        // 0 auto, 1 baseline gather, 2 tiled
+  int tile_auto = 0;            // the automatic choice takes the tile: eligible, and at least
+                                // kTileMinTiles tiles (fewer leave most compute units idle)
+  bool use_tile() const { return tile_ok && (kernel_choice == 2 || (kernel_choice == 0 && tile_auto)); }
   sllbm::DevTensorPlan tp{};
   sllbm::DevCsrPlan cp{};
   std::vector<void *> dev_allocs;
@@ -223,6 +226,10 @@ int build_csr_tables(const Mesh &m, const VelSet &v, double dt, HostTables &t, i
 std::vector<double> node_volumes(const Mesh &m);
 // Tile shape (cells per axis) of the LDS-tiled kernel for (dim, p), or false.
 bool tile_cells(int D, int P, int c[3]);
+// below this many tiles (one per compute unit) the per-node gather kernel, with a node's
+// velocities over up to four lanes, steps faster than the tile kernel's sequence of
+// per-velocity stages (measured: 80 tiles, 0.24 against 0.65 ms; 4352 tiles, 9.3 against 4.6 ms)
+constexpr int64_t kTileMinTiles = 256;
 // True if every regular departure stencil of a cell-aligned tile of c[] cells stays in
 // the one-cell halo that the tiled kernel stages.
 bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]);

@@ -392,7 +392,7 @@ int launch_step(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout
                                  : dispatch_gather<double>(Pl, a, sl, pin, pout, s);
   };
   int rc;
-  if (Pl->tile_ok && Pl->kernel_choice != 1) {
+  if (Pl->use_tile()) {
     // interior nodes: LDS-tiled kernel; boundary-layer slabs: per-node gather
     rc = launch_step_tile(Pl, a, pin, pout, s);
     if (rc) return rc;

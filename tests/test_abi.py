@@ -228,16 +228,30 @@ def test_step_argument_validation_before_any_launch():
 
 def test_tiled_kernel_eligibility_follows_the_halo_rule():
     """The LDS-tiled kernel applies when every departure stencil stays within one cell
-    of its node (CFL <= 1 on the cell) and the periodic axes are longer than a tile."""
+    of its node (CFL <= 1 on the cell) and the periodic axes are longer than a tile; the
+    automatic choice takes it from 256 tiles (one per compute unit) on."""
     mesh, phys = W.tgv_case(ncell=8, p=3)
     m = S.sllbm_mesh_build(mesh)
     vs = S.sllbm_velset_gauss_hermite(3)
-    assert S.sllbm_plan_info(S.sllbm_interp_plan(m, vs, phys.dt))["kernel"] == 2
+
+    def tiled(plan):
+        try:
+            S.sllbm_plan_select_kernel(plan, 2)
+        except S.SllbmError as e:
+            assert e.code == S.SLLBM_EUNSUPPORTED
+            return False
+        return S.sllbm_plan_info(plan)["kernel"] == 2
+
+    p8 = S.sllbm_interp_plan(m, vs, phys.dt)
+    assert S.sllbm_plan_info(p8)["kernel"] == 0          # 24^3 nodes: 16 tiles, automatic -> gather
+    assert tiled(p8)
     h = 2 * math.pi / 8
     big = 1.5 * h / W.ZETA_MAX_GH5            # CFL 1.5: stencils two cells away
-    assert S.sllbm_plan_info(S.sllbm_interp_plan(m, vs, big))["kernel"] == 0
+    assert not tiled(S.sllbm_interp_plan(m, vs, big))
     small = W.tgv_case(ncell=5, p=3)[0]       # 15 nodes per axis < tile + halo
-    assert S.sllbm_plan_info(S.sllbm_interp_plan(S.sllbm_mesh_build(small), vs, phys.dt))["kernel"] == 0
+    assert not tiled(S.sllbm_interp_plan(S.sllbm_mesh_build(small), vs, phys.dt))
+    large, physl = W.tgv_case(ncell=24, p=3)  # 72^3 nodes: 432 tiles
+    assert S.sllbm_plan_info(S.sllbm_interp_plan(S.sllbm_mesh_build(large), vs, physl.dt))["kernel"] == 2
 
 
 def test_profiling_needs_a_device_plan():

@@ -133,7 +133,7 @@ def test_d2q19_bounce_back_stretched_fp64():
                       edges=[W.uniform_edges(12, 0.0, 3.0), W.tanh_edges(6, 1.5)],
                       face_bc=[[-1, -1], [0, 0]], bcs=[W.BC(kind=W.BC_WALL)])
     phys = W.Physics(dt=0.02, relax_mode=0, tau_bar=0.9)
-    o, g = _tensor(tm, phys, "f64")
+    o, g = _tensor(tm, phys, "f64", TILED)
     assert g.kernel == 2   # wall slabs by the gather kernel, the interior by the tile
     _compare(o, g, lambda x: W.random_fields(x.shape[0], 2, seed=41, u_mean=(0.3, 0.0)), 20, TOL64)
 

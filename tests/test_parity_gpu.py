@@ -249,10 +249,15 @@ def test_tgv_full_size_one_step_sampled(prec, kernel):
 
 
 def test_kernel_selection_reports_the_kernel_in_use():
+    """Automatic choice: the tile from 256 tiles up (one per compute unit), else the gather
+    kernel; an explicit choice of either where the tile applies."""
     say("case kernel selection")
-    mesh, phys = W.tgv_case(ncell=6, p=3)
-    assert GpuRun(mesh, phys, "f64").kernel == TILED
+    mesh, phys = W.tgv_case(ncell=6, p=3)          # 18^3 nodes: 12 tiles
+    assert GpuRun(mesh, phys, "f64").kernel == 0
+    assert GpuRun(mesh, phys, "f64", TILED).kernel == TILED
     assert GpuRun(mesh, phys, "f64", GATHER).kernel == 0
+    big, physb = W.tgv_case(ncell=24, p=3)         # 72^3 nodes: 6 x 6 x 12 = 432 tiles
+    assert GpuRun(big, physb, "f32").kernel == TILED
     mesh5, phys5 = W.tgv_case(ncell=5, p=3)   # 15 nodes per axis: too few for a tile + halo
     assert GpuRun(mesh5, phys5, "f64").kernel == 0
 
@@ -260,7 +265,7 @@ def test_kernel_selection_reports_the_kernel_in_use():
 def test_plan_profile_counts_every_launch():
     """Per-kernel event timing: one entry per launch of each kernel of the step."""
     mesh, phys = W.tgv_case(ncell=8, p=3)
-    g = GpuRun(mesh, phys, "f64")
+    g = GpuRun(mesh, phys, "f64", TILED)
     rho, u, T = W.tgv_fields(g.coords())
     g.init(rho, u, T)
     g.S.sllbm_plan_profile(g.plan, True)

@@ -128,7 +128,7 @@ def test_channel_walls_force_mass_fix(prec, tol, vel):
     mesh, phys = W.channel_case(ncell=(6, 8, 6), p=2, box=(2.0, 2.0, 1.5), cfl=0.75, T_wall=0.9, Ma_b=0.5)
     phys = dataclasses.replace(phys, Pr=0.7)
     _compare(mesh, phys, prec, lambda x: W.channel_fields(x, box=(2.0, 2.0, 1.5), Ma_b=0.5, T_wall=1.0), 20, tol,
-             vel=vel, compare_pops=(prec == "f64"), mass_fix_every=5, expect_kernel=2)
+             kernel=TILED, vel=vel, compare_pops=(prec == "f64"), mass_fix_every=5, expect_kernel=2)
 
 
 def _warped_box(p=3):
