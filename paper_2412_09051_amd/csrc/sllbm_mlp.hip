@@ -38,6 +38,9 @@ constexpr int NT = 256;      // threads per workgroup (4 waves)
 constexpr int WBF_W1 = 0, WBF_W2 = KIN * HW, WBF_W3 = KIN * HW + HW * HW, WBF_W4 = KIN * HW + 2 * HW * HW;
 constexpr int WBF_N = KIN * HW + 2 * HW * HW + HW * NOUTP;
 constexpr int kMaxPartialBlocks = 512;
+// The correction kernel's LDS (126 KB) admits one workgroup per compute unit: a grid of one
+// workgroup per CU stages the weights once per CU and walks the tiles from there.
+constexpr int64_t kCorrectGrid = 256;
 
 __host__ __device__ inline uint16_t f2bf(float f) {
   uint32_t u;
@@ -946,7 +949,7 @@ extern "C" int sllbm_mlp_correct(sllbm_plan P, const sllbm_params *prm, sllbm_ml
   pa.vel = P->tp.vel;
   const int64_t N = P->mesh.n_nodes;
   // a persistent grid: each workgroup stages the weights once and walks several tiles
-  dim3 grid((unsigned)std::min<int64_t>((N + R - 1) / R, 1024));
+  dim3 grid((unsigned)std::min<int64_t>((N + R - 1) / R, kCorrectGrid));
   {
     ProfScope ps(P, "k_mlp_correct", s);
     if (P->prec == SLLBM_F32)
