@@ -458,28 +458,41 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
 
 // 3D: streams every velocity of one tile through LDS in three 1D passes (x, y, z) and
 // stores the streamed f_i, g_i of the owned nodes and their node state (rho, u0, u1,
-// u2, T, 1/tau_bar as [6][N] doubles).  Per velocity: barrier; commit velocity i from
-// registers to LDS (with its weight rows) and issue the loads of velocity i+1; barrier;
-// x-pass; barrier; y-pass; barrier; z contraction per owned node.
-template <typename T, int D, int P, int CX, int CY, int CZ, int BS, int WPE>
+// u2, T, 1/tau_bar as [6][N] doubles).  Two schedules:
+//  SK = 0: per velocity, barrier; commit velocity i from registers to LDS (with its weight
+//    rows) and issue the loads of i+1; barrier; x-pass (S -> X); barrier; y-pass (X -> Y,
+//    Y aliasing S); barrier; z contraction per owned node.  Four barriers per velocity.
+//  SK = 1: the passes of consecutive velocities are skewed so that a velocity costs two
+//    barriers: phase A contracts velocity i-1 along z (Y -> the owned nodes) and runs the
+//    x-pass of velocity i; phase B runs the y-pass of i and commits velocity i+1 into S,
+//    then issues the loads of i+2.  Every LDS buffer is written in one phase and read in
+//    the other, so Y needs its own buffer and the weight rows are double-buffered (velocity
+//    i's z rows are still read after i+1 is committed).
+template <typename T, int D, int P, int CX, int CY, int CZ, int BS, int WPE, int SK>
 __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl, const StepArgs sa, const TileGrid tg,
                                                     const T *__restrict__ pin, T *__restrict__ pout,
                                                     double *__restrict__ nstate) {
-  constexpr int TX = CX * P, TY = CY * P, TZ = (D == 3) ? CZ * P : 1;
-  constexpr int RX = TX + P + 1, RY = TY + P + 1, RZ = (D == 3) ? TZ + P + 1 : 1;
+  static_assert(D == 3, "the 2D tiles have a kernel of their own");
+  constexpr int TX = CX * P, TY = CY * P, TZ = CZ * P;
+  constexpr int RX = TX + P + 1, RY = TY + P + 1, RZ = TZ + P + 1;
   constexpr int NT = TX * TY * TZ;
   constexpr int NPT = (NT + BS - 1) / BS;
   constexpr int SS = RZ * RY * RX;           // one population's staging size
   constexpr int XS = RZ * RY * TX;           // one population's x-pass output
-  constexpr int YS = RZ * TY * TX;           // one population's y-pass output (3D)
-  constexpr int NST = (SS + BS - 1) / BS;      // staged elements per thread and population
+  constexpr int YS = RZ * TY * TX;           // one population's y-pass output
+  constexpr int NST = (SS + BS - 1) / BS;    // staged elements per thread and population
   constexpr int NW = TX + TY + TZ;           // weight rows: one per tile position and axis
+  constexpr int WS = NW * (P + 1);
   static_assert(NW <= BS, "weight rows exceed the workgroup");
+  static_assert(BS >= TX * TY, "tile cross-section exceeds the workgroup");
+  constexpr int NB = SK ? 2 : 1;             // weight-row buffers
   __shared__ T S[2 * SS];
   __shared__ T X[2 * XS];
-  __shared__ T WT[NW * (P + 1)];
-  __shared__ int OT[NW];
-  T *Yb = S;
+  __shared__ T Ys[SK ? 2 * YS : 1];
+  __shared__ T WT[NB * WS];
+  __shared__ int OT[NB * NW];
+  static_assert(SK || YS <= SS, "the y-pass output must fit the staging buffer it reuses");
+  T *const Y = SK ? Ys : S;
 
   const int Q = pl.Q;
   const int tid = threadIdx.x;
@@ -495,7 +508,7 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
   const int b1 = (tile / tg.nt[0]) % tg.nt[1];
   const int b2 = tile / (tg.nt[0] * tg.nt[1]);
   const int n0x = b0 * TX, n0y = b1 * TY, n0z = b2 * TZ;
-  const int vx = min(TX, Nx - n0x), vy = min(TY, Ny - n0y), vz = (D == 3) ? min(TZ, Nz - n0z) : 1;
+  const int vx = min(TX, Nx - n0x), vy = min(TY, Ny - n0y), vz = min(TZ, Nz - n0z);
 
   // owned nodes: flat tile index tid + BS m, x fastest
   int otx[NPT], oty[NPT], otz[NPT];
@@ -521,8 +534,8 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
   auto node_index = [&](int m) __attribute__((always_inline)) -> int64_t {
     return (int64_t)(n0x + otx[m]) + (int64_t)Nx * ((int64_t)(n0y + oty[m]) + (int64_t)Ny * (n0z + otz[m]));
   };
-  // ---- software pipeline: the departure region of velocity i+1 is loaded into
-  // registers while velocity i is interpolated out of LDS
+  // ---- software pipeline: the departure region of velocity i+2 is loaded into
+  // registers while velocities i and i+1 are interpolated out of LDS
   T pf[NST], pg[NST];
   T pw[P + 1];
   int poff = 0;
@@ -530,11 +543,7 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
   auto prefetch = [&](int i) __attribute__((always_inline)) {
     ng[0] = axis_geo<P>(pl.ax[0], pl.tab_reg[i], n0x, vx, TX);
     ng[1] = axis_geo<P>(pl.ax[1], pl.tab_reg[Q + i], n0y, vy, TY);
-    if (D == 3) {
-      ng[2] = axis_geo<P>(pl.ax[2], pl.tab_reg[2 * Q + i], n0z, vz, TZ);
-    } else {
-      ng[2].tb = 0; ng[2].ident = 1; ng[2].rs = 0; ng[2].R = 1;
-    }
+    ng[2] = axis_geo<P>(pl.ax[2], pl.tab_reg[2 * Q + i], n0z, vz, TZ);
     const T *F = pin + (size_t)i * N;
     const T *G = pin + ((size_t)Q + i) * N;
 #pragma unroll
@@ -544,7 +553,7 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
       if (e < SS && rx < ng[0].R && ry < ng[1].R && rz < ng[2].R) {
         int gxx = wrap_idx(n0x + ng[0].rs + rx, Nx);
         int gyy = wrap_idx(n0y + ng[1].rs + ry, Ny);
-        int gzz = (D == 3) ? wrap_idx(n0z + ng[2].rs + rz, Nz) : 0;
+        int gzz = wrap_idx(n0z + ng[2].rs + rz, Nz);
         size_t k = (size_t)gxx + (size_t)Nx * ((size_t)gyy + (size_t)Ny * gzz);
         pf[s] = F[k];
         pg[s] = G[k];
@@ -559,10 +568,11 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
       int len;
       const AxGeo &ga = ax == 0 ? ng[0] : (ax == 1 ? ng[1] : ng[2]);
       const DevAxis &da = ax == 0 ? pl.ax[0] : (ax == 1 ? pl.ax[1] : pl.ax[2]);
-      if (ax < D && q < vt) axis_weights<T, P>(da, ga, n0a, q, Ta, poff, len, pw);
+      if (q < vt) axis_weights<T, P>(da, ga, n0a, q, Ta, poff, len, pw);
     }
   };
-  auto commit = [&]() __attribute__((always_inline)) {
+  // the prefetched velocity into S and weight buffer wb
+  auto commit = [&](int wb) __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < NST; s++) {
       int e = tid + BS * s;
@@ -574,104 +584,61 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
     }
     if (tid < NW) {
 #pragma unroll
-      for (int j = 0; j <= P; j++) WT[tid * (P + 1) + j] = pw[j];
-      OT[tid] = poff;
+      for (int j = 0; j <= P; j++) WT[wb * WS + tid * (P + 1) + j] = pw[j];
+      OT[wb * NW + tid] = poff;
     }
     cg[0] = ng[0];
     cg[1] = ng[1];
     cg[2] = ng[2];
   };
-
-  // Streamed f_i, g_i of every owned node out of the committed LDS region: three 1D
-  // passes (two in 2D), then the boundary-layer pairs by per-node gather.
-  auto interpolate = [&](double (&fv)[NPT], double (&gv)[NPT]) __attribute__((always_inline)) {
+  // x-pass of the committed velocity: S[rz][ry][*] -> X[rz][ry][tx]; each thread keeps one
+  // tx (and its weights) and walks the rows
+  auto xpass = [&](int wb) __attribute__((always_inline)) {
+    constexpr int NRX = BS / TX;          // rows in flight per sweep of the workgroup
     const int Ry = cg[1].R, Rz = cg[2].R;
-    {  // x-pass: S[rz][ry][*] -> X[rz][ry][tx]; each thread keeps one tx (and its
-       // weights) and walks the rows
-      constexpr int NRX = BS / TX;          // rows in flight per sweep of the workgroup
-      const int len = cg[0].ident ? 1 : P + 1;
-      const int tx = tid % TX, r0 = tid / TX;
-      if (r0 < NRX && tx < vx) {
-        const int off = OT[tx];
-        T w[P + 1];
+    const int len = cg[0].ident ? 1 : P + 1;
+    const int tx = tid % TX, r0 = tid / TX;
+    if (r0 < NRX && tx < vx) {
+      const int off = OT[wb * NW + tx];
+      T w[P + 1];
 #pragma unroll
-        for (int j = 0; j <= P; j++) w[j] = WT[tx * (P + 1) + j];
-        // rows rz RY + ry of the staging grid: the compile-time stride RY splits the counter
-        // (a runtime divisor would cost an emulated division per row); rows beyond the
-        // region's Ry are skipped
-        const int nrows = RY * Rz;
+      for (int j = 0; j <= P; j++) w[j] = WT[wb * WS + tx * (P + 1) + j];
+      // rows rz RY + ry of the staging grid: the compile-time stride RY splits the counter
+      // (a runtime divisor would cost an emulated division per row); rows beyond the
+      // region's Ry are skipped
+      const int nrows = RY * Rz;
 #pragma unroll 1
-        for (int rr = r0; rr < nrows; rr += NRX) {
-          if (rr % RY >= Ry) continue;
-          const T *sf = S + rr * RX + off;
-          T a = 0, b = 0;
-#pragma unroll
-          for (int j = 0; j <= P; j++) {
-            if (j >= len) break;
-            a += w[j] * sf[j];
-            b += w[j] * sf[SS + j];
-          }
-          const int l = rr * TX + tx;
-          X[l] = a;
-          X[XS + l] = b;
-        }
-      }
-    }
-    __syncthreads();
-    if constexpr (D == 3) {
-      {  // y-pass: X[rz][*][tx] -> Yb[rz][ty][tx]; each thread keeps one (tx, ty)
-        constexpr int NRY = BS / (TX * TY);
-        static_assert(NRY >= 1, "tile cross-section exceeds the workgroup");
-        const int len = cg[1].ident ? 1 : P + 1;
-        const int tx = tid % TX, ty = (tid / TX) % TY, z0 = tid / (TX * TY);
-        if (z0 < NRY && tx < vx && ty < vy) {
-          const int off = OT[TX + ty];
-          T w[P + 1];
-#pragma unroll
-          for (int j = 0; j <= P; j++) w[j] = WT[(TX + ty) * (P + 1) + j];
-#pragma unroll 1
-          for (int rz = z0; rz < RZ; rz += NRY) {
-            if (rz >= Rz) break;
-            const T *xf = X + (rz * RY + off) * TX + tx;
-            T a = 0, b = 0;
-#pragma unroll
-            for (int j = 0; j <= P; j++) {
-              if (j >= len) break;
-              a += w[j] * xf[j * TX];
-              b += w[j] * xf[XS + j * TX];
-            }
-            int l = (rz * TY + ty) * TX + tx;
-            Yb[l] = a;
-            Yb[YS + l] = b;
-          }
-        }
-      }
-      __syncthreads();
-      const int len = cg[2].ident ? 1 : P + 1;
-#pragma unroll
-      for (int m = 0; m < NPT; m++) {  // z-pass for the owned nodes
-        fv[m] = gv[m] = 0.0;
-        if (!own[m]) continue;
-        const T *yf = Yb + (OT[TX + TY + otz[m]] * TY + oty[m]) * TX + otx[m];
-        const T *w = WT + (TX + TY + otz[m]) * (P + 1);
+      for (int rr = r0; rr < nrows; rr += NRX) {
+        if (rr % RY >= Ry) continue;
+        const T *sf = S + rr * RX + off;
         T a = 0, b = 0;
 #pragma unroll
         for (int j = 0; j <= P; j++) {
           if (j >= len) break;
-          a += w[j] * yf[j * TY * TX];
-          b += w[j] * yf[YS + j * TY * TX];
+          a += w[j] * sf[j];
+          b += w[j] * sf[SS + j];
         }
-        fv[m] = scale * (double)a;
-        gv[m] = scale * (double)b;
+        const int l = rr * TX + tx;
+        X[l] = a;
+        X[XS + l] = b;
       }
-    } else {
-      const int len = cg[1].ident ? 1 : P + 1;
+    }
+  };
+  // y-pass: X[rz][*][tx] -> Y[rz][ty][tx]; each thread keeps one (tx, ty)
+  auto ypass = [&](int wb) __attribute__((always_inline)) {
+    constexpr int NRY = BS / (TX * TY);
+    const int Rz = cg[2].R;
+    const int len = cg[1].ident ? 1 : P + 1;
+    const int tx = tid % TX, ty = (tid / TX) % TY, z0 = tid / (TX * TY);
+    if (z0 < NRY && tx < vx && ty < vy) {
+      const int off = OT[wb * NW + TX + ty];
+      T w[P + 1];
 #pragma unroll
-      for (int m = 0; m < NPT; m++) {  // y-pass (last in 2D) for the owned nodes
-        fv[m] = gv[m] = 0.0;
-        if (!own[m]) continue;
-        const T *xf = X + OT[TX + oty[m]] * TX + otx[m];
-        const T *w = WT + (TX + oty[m]) * (P + 1);
+      for (int j = 0; j <= P; j++) w[j] = WT[wb * WS + (TX + ty) * (P + 1) + j];
+#pragma unroll 1
+      for (int rz = z0; rz < RZ; rz += NRY) {
+        if (rz >= Rz) break;
+        const T *xf = X + (rz * RY + off) * TX + tx;
         T a = 0, b = 0;
 #pragma unroll
         for (int j = 0; j <= P; j++) {
@@ -679,69 +646,124 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
           a += w[j] * xf[j * TX];
           b += w[j] * xf[XS + j * TX];
         }
-        fv[m] = scale * (double)a;
-        gv[m] = scale * (double)b;
+        int l = (rz * TY + ty) * TX + tx;
+        Y[l] = a;
+        Y[YS + l] = b;
       }
     }
   };
-  // one pipeline stage: velocity i is committed to LDS, velocity `next` (or -1) is
-  // prefetched, and i is interpolated
-  auto stream_velocity = [&](int i, int next, double (&fv)[NPT], double (&gv)[NPT]) __attribute__((always_inline)) {
-    __syncthreads();  // everyone is done reading the previous velocity out of LDS
-    commit();
-    if (next >= 0) prefetch(next);
-    __syncthreads();
-    interpolate(fv, gv);
+  // z contraction for the owned nodes, with the weight buffer and row length of the
+  // velocity the y-pass left in Y
+  auto zpass = [&](int wb, int len, double (&fv)[NPT], double (&gv)[NPT]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int m = 0; m < NPT; m++) {
+      fv[m] = gv[m] = 0.0;
+      if (!own[m]) continue;
+      const T *yf = Y + (OT[wb * NW + TX + TY + otz[m]] * TY + oty[m]) * TX + otx[m];
+      const T *w = WT + wb * WS + (TX + TY + otz[m]) * (P + 1);
+      T a = 0, b = 0;
+#pragma unroll
+      for (int j = 0; j <= P; j++) {
+        if (j >= len) break;
+        a += w[j] * yf[j * TY * TX];
+        b += w[j] * yf[YS + j * TY * TX];
+      }
+      fv[m] = scale * (double)a;
+      gv[m] = scale * (double)b;
+    }
   };
 
-  prefetch(0);
-  {
-    double rho[NPT], j0[NPT], j1[NPT], j2[NPT], E[NPT];
+  double rho[NPT], j0[NPT], j1[NPT], j2[NPT], E[NPT];
 #pragma unroll
-    for (int m = 0; m < NPT; m++) rho[m] = j0[m] = j1[m] = j2[m] = E[m] = 0.0;
-    for (int i = 0; i < Q; i++) {
-      double fv[NPT], gv[NPT];
-      stream_velocity(i, i + 1 < Q ? i + 1 : -1, fv, gv);
-      const double *vi = pl.vel + 8 * i;
-      const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
-#pragma unroll
-      for (int m = 0; m < NPT; m++) {
-        if (!own[m]) continue;
-        const int64_t k = node_index(m);
-        pout[(size_t)i * N + k] = (T)fv[m];
-        pout[((size_t)Q + i) * N + k] = (T)gv[m];
-      }
-#pragma unroll
-      for (int m = 0; m < NPT; m++) {
-        rho[m] += fv[m];
-        j0[m] += vi[0] * fv[m];
-        j1[m] += vi[1] * fv[m];
-        j2[m] += vi[2] * fv[m];
-        E[m] += z2 * fv[m] + gv[m];
-      }
-    }
-    // node state: rho, u, T, 1/tau_bar (isothermal walls act only inside the boundary
-    // layers, which the gather kernel handles)
+  for (int m = 0; m < NPT; m++) rho[m] = j0[m] = j1[m] = j2[m] = E[m] = 0.0;
+  // store the streamed values of velocity i and add them to the moments
+  auto accumulate = [&](int i, const double (&fv)[NPT], const double (&gv)[NPT]) __attribute__((always_inline)) {
+    const double *vi = pl.vel + 8 * i;
+    const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
 #pragma unroll
     for (int m = 0; m < NPT; m++) {
       if (!own[m]) continue;
-      double r = rho[m];
-      double u0 = j0[m] / r, u1 = j1[m] / r, u2 = j2[m] / r;
-      double Tn = (E[m] - r * (u0 * u0 + u1 * u1 + u2 * u2)) / (2.0 * r * sa.cv);
-      double it = 0.0;
-      if (sa.relax_mode == 0) it = 1.0 / sa.tau_bar;
-      if (sa.relax_mode == 1) {
-        double mu = sa.mu_ref * pow(Tn / sa.T_ref, sa.mu_exp);
-        it = 1.0 / (mu / (r * Tn * sa.dt) + 0.5);
-      }
       const int64_t k = node_index(m);
-      nstate[k] = r;
-      nstate[N + k] = u0;
-      nstate[2 * N + k] = u1;
-      nstate[3 * N + k] = u2;
-      nstate[4 * N + k] = Tn;
-      nstate[5 * N + k] = it;
+      pout[(size_t)i * N + k] = (T)fv[m];
+      pout[((size_t)Q + i) * N + k] = (T)gv[m];
     }
+#pragma unroll
+    for (int m = 0; m < NPT; m++) {
+      rho[m] += fv[m];
+      j0[m] += vi[0] * fv[m];
+      j1[m] += vi[1] * fv[m];
+      j2[m] += vi[2] * fv[m];
+      E[m] += z2 * fv[m] + gv[m];
+    }
+  };
+
+  if constexpr (!SK) {
+    prefetch(0);
+    for (int i = 0; i < Q; i++) {
+      __syncthreads();  // everyone is done reading the previous velocity out of LDS
+      commit(0);
+      if (i + 1 < Q) prefetch(i + 1);
+      __syncthreads();
+      xpass(0);
+      __syncthreads();
+      ypass(0);
+      __syncthreads();
+      double fv[NPT], gv[NPT];
+      zpass(0, cg[2].ident ? 1 : P + 1, fv, gv);
+      accumulate(i, fv, gv);
+    }
+  } else {
+  prefetch(0);
+  commit(0);
+  if (Q > 1) prefetch(1);
+  __syncthreads();
+  int zlen = 0;
+  for (int i = 0; i < Q; i++) {
+    const int wb = i & 1;
+    // phase A: z of velocity i-1, x of velocity i
+    if (i > 0) {
+      double fv[NPT], gv[NPT];
+      zpass(wb ^ 1, zlen, fv, gv);
+      accumulate(i - 1, fv, gv);
+    }
+    xpass(wb);
+    __syncthreads();
+    // phase B: y of velocity i, commit of velocity i+1, loads of i+2
+    ypass(wb);
+    zlen = cg[2].ident ? 1 : P + 1;
+    if (i + 1 < Q) {
+      commit(wb ^ 1);
+      if (i + 2 < Q) prefetch(i + 2);
+    }
+    __syncthreads();
+  }
+  {
+    double fv[NPT], gv[NPT];
+    zpass((Q - 1) & 1, zlen, fv, gv);
+    accumulate(Q - 1, fv, gv);
+  }
+  }
+  // node state: rho, u, T, 1/tau_bar (isothermal walls act only inside the boundary
+  // layers, which the gather kernel handles)
+#pragma unroll
+  for (int m = 0; m < NPT; m++) {
+    if (!own[m]) continue;
+    double r = rho[m];
+    double u0 = j0[m] / r, u1 = j1[m] / r, u2 = j2[m] / r;
+    double Tn = (E[m] - r * (u0 * u0 + u1 * u1 + u2 * u2)) / (2.0 * r * sa.cv);
+    double it = 0.0;
+    if (sa.relax_mode == 0) it = 1.0 / sa.tau_bar;
+    if (sa.relax_mode == 1) {
+      double mu = sa.mu_ref * pow(Tn / sa.T_ref, sa.mu_exp);
+      it = 1.0 / (mu / (r * Tn * sa.dt) + 0.5);
+    }
+    const int64_t k = node_index(m);
+    nstate[k] = r;
+    nstate[N + k] = u0;
+    nstate[2 * N + k] = u1;
+    nstate[3 * N + k] = u2;
+    nstate[4 * N + k] = Tn;
+    nstate[5 * N + k] = it;
   }
 }
 
@@ -861,8 +883,17 @@ void launch_tile2d_single(const DevTensorPlan &tp, const StepArgs &a, const Tile
 template <typename T, int D, int P, int CX, int CY, int CZ>
 int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
   constexpr int BS = D == 3 ? 512 : 256;   // threads per workgroup
+  // 3D schedule: the skewed two-barrier one except at p = 3 in FP64, where its separate
+  // y buffer takes the 12 x 12 x 6 tile to 95 KB of LDS and one workgroup per CU.  Tile
+  // kernel on the 96^3-node TGV, skewed against four barriers: p = 2 2.16 / 2.28 ms (FP64),
+  // 1.32 / 1.59 ms (FP32); p = 3 FP32 1.23 / 1.37 ms; p = 4 2.50 / 2.79 ms (FP64), 1.99 /
+  // 2.32 ms (FP32); p = 3 FP64 2.23-2.41 ms skewed (tile shapes and workgroup sizes
+  // tried) against 2.01 ms.
+  constexpr int SK = (D == 3 && (P != 3 || sizeof(T) == 4)) ? 1 : 0;
   // minimum waves per SIMD the register budget must allow, per launch
-  constexpr int WPE = TILE_WPE;
+  // (the p = 2 FP32 kernel is held to 6 waves per SIMD, 3 workgroups per CU: unbounded it
+  // takes 87 VGPRs and 2 workgroups, 11.7 against 7.9 ms on the 128 x 96 x 64 channel)
+  constexpr int WPE = (D == 3 && P == 2 && sizeof(T) == 4) ? 6 : TILE_WPE;
   constexpr int TX = CX * P, TY = CY * P, TZ = (D == 3) ? CZ * P : 1;
   const DevTensorPlan &tp = Pl->tp;
   TileGrid tg;
@@ -890,7 +921,7 @@ int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *po
   {
     ProfScope ps(Pl, "k_step_tile", s);
     if constexpr (D == 3)
-      hipLaunchKernelGGL((k_step_tile3d<T, D, P, CX, CY, CZ, BS, WPE>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
+      hipLaunchKernelGGL((k_step_tile3d<T, D, P, CX, CY, CZ, BS, WPE, SK>), dim3(ntiles), dim3(BS), 0, s, tp, a, tg,
                          (const T *)pin, (T *)pout, Pl->nstate);
     else if (wide)
       hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPE, 0, 0, kTileTabsMax>), dim3(ntiles), dim3(BS), 0, s,
