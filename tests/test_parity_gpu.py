@@ -129,6 +129,19 @@ def test_tgv_fp64_small(kernel):
     _run_compare(mesh, phys, "f64", lambda x: W.tgv_fields(x), 20, TOL64, kernel=kernel)
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+@pytest.mark.parametrize("p,ncell", [(2, 9), (4, 5)])
+def test_tgv_tiled_orders_2_and_4_ragged(p, ncell, prec, tol):
+    """The 3D tile kernel at p = 2 and 4, where it skews the passes of consecutive velocities
+    (two barriers per velocity, double-buffered weight rows), on D3V125 with a ragged last
+    tile on every axis (18 nodes per axis at p = 2, 20 at p = 4, against 8-node tiles)."""
+    say("case C2 TGV tiled", prec, "p", p, "cells", ncell, "10 steps")
+    mesh, phys = W.tgv_case(ncell=ncell, p=p)
+    _, g, _ = _run_compare(mesh, phys, prec, lambda x: W.tgv_fields(x), 10, tol, compare_pops=(prec == "f64"),
+                           kernel=TILED)
+    assert g.kernel == TILED
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_tgv_fp32_small_100_steps(kernel):
     """100 steps at the time step of the 32^3 configuration (t = 3.4, before the
