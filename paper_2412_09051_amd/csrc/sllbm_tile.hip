@@ -891,9 +891,11 @@ int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *po
   // tried) against 2.01 ms.
   constexpr int SK = (D == 3 && (P != 3 || sizeof(T) == 4)) ? 1 : 0;
   // minimum waves per SIMD the register budget must allow, per launch
-  // (the p = 2 FP32 kernel is held to 6 waves per SIMD, 3 workgroups per CU: unbounded it
-  // takes 87 VGPRs and 2 workgroups, 11.7 against 7.9 ms on the 128 x 96 x 64 channel)
-  constexpr int WPE = (D == 3 && P == 2 && sizeof(T) == 4) ? 6 : TILE_WPE;
+  // (the p = 2 and 4 FP32 kernels are held to 6 waves per SIMD, 3 workgroups per CU:
+  // unbounded, p = 2 takes 87 VGPRs and 2 workgroups, 11.7 against 7.9 ms on the
+  // 128 x 96 x 64 channel, and p = 4 2.00 against 1.73 ms on the 96^3 TGV; at p = 3 the bound
+  // spills 112 B per lane and slows the FP32 TGV from 1.23 to 2.17 ms)
+  constexpr int WPE = (D == 3 && P != 3 && sizeof(T) == 4) ? 6 : TILE_WPE;
   constexpr int TX = CX * P, TY = CY * P, TZ = (D == 3) ? CZ * P : 1;
   const DevTensorPlan &tp = Pl->tp;
   TileGrid tg;
