@@ -343,27 +343,15 @@ MIX_BOX_CELLS = (2.5, 2.75, 1.5)      # coarse cell size per axis in initial mom
 
 
 def mixing_dtheta(S, torch, plan, prm, pop, shape, du, V, box):
-    """Momentum thickness (1 / (rho0 du^2)) int <rho> (du/2 - u~)(du/2 + u~) dy of a
-    population field: plane averages over x and z and the y integral with the nodal
-    quadrature weights, u~ = <rho u> / <rho> (rho0 = 1)."""
+    """Momentum thickness of a population field (Sec. 4.4): the moments on the device, the
+    plane averages and the y integral by the package's diagnostic."""
+    from paper_2412_09051_amd import diagnostics as D
     N = plan.N
     rho = torch.empty(N, dtype=torch.float64, device="cuda")
     u = torch.empty(3 * N, dtype=torch.float64, device="cuda")
     S.sllbm_moments(plan, prm, pop, rho, u, None)
     Nx, Ny, Nz = shape
-    r = rho.view(Nz, Ny, Nx)
-    ux = u[:N].view(Nz, Ny, Nx)
-    A = (V * r).sum(dim=(0, 2))
-    B = (V * r * ux).sum(dim=(0, 2))
-    Wj = V.sum(dim=(0, 2))
-    rbar, ut = A / Wj, B / A
-    wy = Wj / (box[0] * box[2])
-    return float((wy * rbar * (0.5 * du - ut) * (0.5 * du + ut)).sum() / du ** 2)
-
-
-# extent of the self-similar stage of the temporal mixing layer, tau = t du / dtheta0
-# (Tab. 3, tau_min and tau_max per convective Mach number)
-MIX_WINDOW = {0.3: (350.0, 550.0), 0.7: (450.0, 700.0), 0.9: (800.0, 1100.0), 1.2: (1400.0, 2000.0)}
+    return D.momentum_thickness(rho.view(Nz, Ny, Nx), u[:N].view(Nz, Ny, Nx), V, du, box[0] * box[2])
 
 
 def learned_leg(ncell=16, ratio=4, steps=None, n_train=8, train_iters=1500, Ma_c=0.7, alphas=(0.0, 0.25, 0.5, 1.0),
@@ -392,6 +380,7 @@ def learned_leg(ncell=16, ratio=4, steps=None, n_train=8, train_iters=1500, Ma_c
     vname = "D3Q45" if vel == "cub" else "D3V125"
     du = 2.0 * Ma_c * math.sqrt(1.4)
     tau_step = phys.dt * du / d0                      # tau per coarse step
+    from paper_2412_09051_amd.diagnostics import MIX_WINDOW
     window = MIX_WINDOW.get(round(Ma_c, 2))
     if steps is None:
         steps = int(math.ceil(window[1] / tau_step)) if window else 1000
