@@ -179,10 +179,13 @@ def test_targets_and_restriction_match_oracle():
         S.sllbm_restrict(fplan, cplan, 3, torch.tensor(pf, device="cuda"), pc)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_correction_matches_oracle_and_keeps_moments(prec):
+@pytest.mark.parametrize("prec,ncell", [("f64", 4), ("f32", 4), ("f64", 14), ("f32", 14)])
+def test_correction_matches_oracle_and_keeps_moments(prec, ncell):
+    """ncell 4: 576 nodes, 18 node tiles of 32; ncell 14: 22,736 nodes, 711 tiles, so that
+    every workgroup of the persistent grid (256) walks two or three tiles."""
     torch, S = _torch(), _S()
-    mesh, phys = W.mixing_layer_case(ncell=(4, 4, 4), box=BOX)
+    say("correction", prec, "cells per axis", ncell)
+    mesh, phys = W.mixing_layer_case(ncell=(ncell,) * 3, box=BOX)
     o = oracle.TensorOracle(mesh, phys)
     _, plan = _plan(mesh, phys, prec)
     net = S.sllbm_mlp_create(20, 2 * o.Q, seed=21)
