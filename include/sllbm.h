@@ -254,6 +254,16 @@ int sllbm_force_read(sllbm_plan p, double *state_host, void *stream);
 int sllbm_moments(sllbm_plan p, const sllbm_params *prm, const void *pop, double *rho, double *u, double *T,
                   double *totals_host, void *stream);
 
+/* sllbm_moments for callers that cannot allocate device memory (code under stream capture,
+ * serving loops, hosts that forbid allocation): same arguments, outputs and errors, but the
+ * block partials and totals of the reduction live in a fixed scratch array that the library
+ * holds on each GPU for the life of the process (8 MiB), so the call allocates nothing.
+ * Limit: plans of at most 2^25 = 33,554,432 nodes; larger plans get SLLBM_EINVAL before any
+ * launch.  All calls on one GPU share that scratch: calls that overlap on one GPU (other
+ * streams or threads) race and must be serialised by the caller. */
+int sllbm_moments_noalloc(sllbm_plan p, const sllbm_params *prm, const void *pop, double *rho, double *u, double *T,
+                          double *totals_host, void *stream);
+
 /* ------------------------------------------------------------------------------------
  * Learned post-collision correction (tensor-product plans)
  *

@@ -90,7 +90,7 @@ _lib.sllbm_last_error.restype = ctypes.c_char_p
 for _name in ("sllbm_mesh_build", "sllbm_mesh_nodes", "sllbm_mesh_volumes", "sllbm_velset_gauss_hermite",
               "sllbm_velset_cubature",
               "sllbm_interp_plan", "sllbm_plan_info", "sllbm_plan_select_kernel", "sllbm_init_equilibrium",
-              "sllbm_step", "sllbm_moments", "sllbm_plan_profile", "sllbm_plan_profile_read",
+              "sllbm_step", "sllbm_moments", "sllbm_moments_noalloc", "sllbm_plan_profile", "sllbm_plan_profile_read",
               "sllbm_force_reset", "sllbm_force_update", "sllbm_force_read", "sllbm_set_allocator"):
     getattr(_lib, _name).restype = ctypes.c_int
 _lib.sllbm_mesh_destroy.restype = None
@@ -367,6 +367,21 @@ def sllbm_moments(plan: Plan, params: Params, pop, rho=None, u=None, T=None, tot
     return tot
 
 
+def sllbm_moments_noalloc(plan: Plan, params: Params, pop, rho=None, u=None, T=None, totals: bool = False,
+                          stream=None):
+    """sllbm_moments with its reduction scratch in the library's fixed per-GPU array (no
+    device allocation; plans of at most 2^25 nodes; overlapping calls on one GPU race)."""
+    import torch
+    N, D = plan.N, plan.dim
+    tot = np.zeros(2 + D) if totals else None
+    _check(_lib.sllbm_moments_noalloc(plan.handle, ctypes.byref(params.c()),
+                                      _dev_ptr(pop, _pop_dtype(plan), 2 * plan.Q * N, "pop"),
+                                      _dev_ptr(rho, torch.float64, N, "rho"), _dev_ptr(u, torch.float64, D * N, "u"),
+                                      _dev_ptr(T, torch.float64, N, "T"),
+                                      _np_ptr(tot) if totals else None, _stream(stream)), "sllbm_moments_noalloc")
+    return tot
+
+
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 _allocator_refs = []      # the callbacks must outlive every object created with them
@@ -526,7 +541,7 @@ def sllbm_mlp_train_step(m: Mlp, x, t, lr: float, want_loss: bool = True, stream
 
 __all__ = ["sllbm_velset_gauss_hermite", "sllbm_velset_cubature", "sllbm_mesh_build", "sllbm_mesh_nodes", "sllbm_mesh_volumes",
            "sllbm_interp_plan", "sllbm_plan_info", "sllbm_plan_select_kernel", "sllbm_init_equilibrium", "sllbm_step", "sllbm_moments",
-           "sllbm_force_reset", "sllbm_force_update", "sllbm_force_read", "sllbm_set_allocator", "use_torch_allocator",
+           "sllbm_moments_noalloc", "sllbm_force_reset", "sllbm_force_update", "sllbm_force_read", "sllbm_set_allocator", "use_torch_allocator",
            "Params", "Plan", "Mesh", "SllbmError", "SLLBM_F64", "SLLBM_F32", "LIB_PATH",
            "Mlp", "sllbm_mlp_create", "sllbm_mlp_get_params", "sllbm_mlp_set_params", "sllbm_features",
            "sllbm_mlp_forward", "sllbm_mlp_correct", "sllbm_learned_targets", "sllbm_restrict", "sllbm_mlp_gradient",

@@ -492,6 +492,74 @@ extern "C" int sllbm_force_read(sllbm_plan P, double *state_host, void *stream) 
   return SLLBM_OK;
 }
 
+namespace {
+// Fixed device scratch of sllbm_moments_noalloc: kRedWidth doubles of final totals, then the
+// block partials of the totals reduction (kRedWidth doubles per block of kBlock nodes) for
+// up to kNoAllocMaxNodes nodes: 8 MiB plus 64 bytes.  Each GPU the library runs on holds its
+// own copy until the process ends; every call on that GPU shares it.
+constexpr int64_t kNoAllocMaxNodes = int64_t(1) << 25;
+constexpr size_t kNoAllocDoubles = (size_t)kRedWidth * (size_t)(1 + kNoAllocMaxNodes / kBlock);
+__device__ __align__(256) double scratch[kNoAllocDoubles];
+
+// Device address of `scratch` on each GPU, looked up once per device (with that device
+// current) on its first call; host code uses only these addresses.
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kNoAllocMaxDevices] = {};
+
+int noalloc_scratch(int device, double **out) {
+  if (device < 0 || device >= kNoAllocMaxDevices)
+    return fail(SLLBM_EUNSUPPORTED, "moments_noalloc: device %d beyond the %d it keeps scratch for", device,
+                kNoAllocMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SLLBM_EHIP, "moments_noalloc: hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_dev[device] = (double *)p;
+  }
+  *out = g_scratch_dev[device];
+  return SLLBM_OK;
+}
+
+// Totals [2 + dim] from the kRedWidth reduced doubles; SLLBM_EUNSTABLE if any node was bad.
+int totals_out(const sllbm_plan_s *P, const double *h, double *totals_host, const char *who) {
+  int D = P->mesh.dim;
+  for (int q = 0; q < 2 + D; q++) totals_host[q] = h[q];
+  if (h[kRedWidth - 1] > 0)
+    return fail(SLLBM_EUNSTABLE, "%s: %.0f nodes with non-finite values, rho <= 0 or T <= 0", who, h[kRedWidth - 1]);
+  return SLLBM_OK;
+}
+}  // namespace
+
+extern "C" int sllbm_moments_noalloc(sllbm_plan P, const sllbm_params *prm, const void *pop, double *rho, double *u,
+                                     double *T, double *totals_host, void *stream) {
+  if (!P) return fail(SLLBM_EINVAL, "moments_noalloc: plan is NULL");
+  if (P->mesh.n_nodes > kNoAllocMaxNodes)
+    return fail(SLLBM_EINVAL, "moments_noalloc: %lld nodes exceed the %lld its fixed scratch holds",
+                (long long)P->mesh.n_nodes, (long long)kNoAllocMaxNodes);
+  int rc = check_params(P, prm);
+  if (rc) return rc;
+  if ((rc = check_pop(P, pop, "pop"))) return rc;
+  if ((rc = require_device(P))) return rc;
+  double *scr = nullptr;
+  if ((rc = noalloc_scratch(P->device, &scr))) return rc;
+  StepArgs a = make_args(P, prm);
+  hipStream_t s = (hipStream_t)stream;
+  // every block writes its partial and the final pass overwrites the totals, so nothing
+  // left in the scratch by an earlier call is read
+  rc = launch_moments_to(P, a, pop, rho, u, T, scr + kRedWidth, totals_host ? scr : nullptr, s);
+  if (rc) return rc;
+  if (totals_host) {
+    double h[kRedWidth];
+    HIP_TRY(hipMemcpyAsync(h, scr, sizeof(double) * kRedWidth, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return totals_out(P, h, totals_host, "moments_noalloc");
+  }
+  return SLLBM_OK;
+}
+
 extern "C" int sllbm_moments(sllbm_plan P, const sllbm_params *prm, const void *pop, double *rho, double *u,
                              double *T, double *totals_host, void *stream) {
   if (!P) return fail(SLLBM_EINVAL, "moments: plan is NULL");
@@ -507,10 +575,7 @@ extern "C" int sllbm_moments(sllbm_plan P, const sllbm_params *prm, const void *
     double h[kRedWidth];
     HIP_TRY(hipMemcpyAsync(h, P->scratch + kSlotTotals, sizeof(double) * kRedWidth, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    int D = P->mesh.dim;
-    for (int q = 0; q < 2 + D; q++) totals_host[q] = h[q];
-    if (h[kRedWidth - 1] > 0)
-      return fail(SLLBM_EUNSTABLE, "moments: %.0f nodes with non-finite values, rho <= 0 or T <= 0", h[kRedWidth - 1]);
+    return totals_out(P, h, totals_host, "moments");
   }
   return SLLBM_OK;
 }

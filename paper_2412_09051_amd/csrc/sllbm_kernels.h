@@ -69,6 +69,10 @@ int launch_init(sllbm_plan_s *P, const StepArgs &a, const double *rho, const dou
 int launch_step(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout, hipStream_t s);
 int launch_moments(sllbm_plan_s *P, const StepArgs &a, const void *pop, double *rho, double *u, double *T,
                    bool totals, hipStream_t s);
+// The same with the block partials of the totals in part[kRedWidth * nblocks(N)] and the final
+// totals in totals[kRedWidth] (both device memory; totals == nullptr: no reduction).
+int launch_moments_to(sllbm_plan_s *P, const StepArgs &a, const void *pop, double *rho, double *u, double *T,
+                      double *part, double *totals, hipStream_t s);
 int launch_mass_scale(sllbm_plan_s *P, const void *pop, double mass_ref, hipStream_t s);
 int launch_force_reset(sllbm_plan_s *P, const double *force0, hipStream_t s);
 int launch_force_update(sllbm_plan_s *P, int axis, double target, double kp, double ki, double dt, const void *pop,

@@ -437,25 +437,31 @@ int launch_init(sllbm_plan_s *Pl, const StepArgs &a, const double *rho, const do
   return SLLBM_OK;
 }
 
-int launch_moments(sllbm_plan_s *Pl, const StepArgs &a, const void *pop, double *rho, double *u, double *T,
-                   bool totals, hipStream_t s) {
+int launch_moments_to(sllbm_plan_s *Pl, const StepArgs &a, const void *pop, double *rho, double *u, double *T,
+                      double *part, double *totals, hipStream_t s) {
   int64_t N = Pl->mesh.n_nodes, nb = nblocks(N);
   const double *vel = Pl->kernel == 0 ? Pl->tp.vel : Pl->cp.vel;
   const double *vol = Pl->kernel == 0 ? Pl->tp.vol : Pl->cp.vol;
-  double *part = Pl->scratch + kScratchHead;
+  const int do_part = totals ? 1 : 0;
   if (Pl->prec == SLLBM_F32)
     hipLaunchKernelGGL(k_moments<float>, dim3((unsigned)nb), dim3(kBlock), 0, s, N, Pl->vel.Q, Pl->mesh.dim, vel, vol,
-                       a, (const float *)pop, rho, u, T, part, totals ? 1 : 0);
+                       a, (const float *)pop, rho, u, T, part, do_part);
   else
     hipLaunchKernelGGL(k_moments<double>, dim3((unsigned)nb), dim3(kBlock), 0, s, N, Pl->vel.Q, Pl->mesh.dim, vel,
-                       vol, a, (const double *)pop, rho, u, T, part, totals ? 1 : 0);
+                       vol, a, (const double *)pop, rho, u, T, part, do_part);
   HIP_TRY(hipGetLastError());
   if (totals) {
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, (const double *)part, nb,
-                       Pl->scratch + kSlotTotals, 0, 0.0, (double *)nullptr);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, s, (const double *)part, nb, totals, 0, 0.0,
+                       (double *)nullptr);
     HIP_TRY(hipGetLastError());
   }
   return SLLBM_OK;
+}
+
+int launch_moments(sllbm_plan_s *Pl, const StepArgs &a, const void *pop, double *rho, double *u, double *T,
+                   bool totals, hipStream_t s) {
+  return launch_moments_to(Pl, a, pop, rho, u, T, Pl->scratch + kScratchHead,
+                           totals ? Pl->scratch + kSlotTotals : nullptr, s);
 }
 
 namespace {
