@@ -3,15 +3,17 @@
 
 Workload (one "step" = one stream + collide pass over the whole mesh): the 3D periodic
 compressible Taylor-Green vortex at Ma 0.8, Re 400 on 32^3 cells of order p = 3 with GLL
-support points (96^3 = 884,736 nodes) and the D3V125 Gauss-Hermite velocity set; FP64
-populations (headline) and FP32 storage side by side.  A second workload, the
-supersonic NACA 0012 O-grid at Ma 1.5 (256 x 128 cells, p = 4, 525,312 nodes, D2V25,
-curvilinear CSR plan), is reported in the "ogrid" object.
+support points (96^3 = 884,736 nodes) and the reduced degree-9 velocity set D3Q45 the paper
+uses (Sec. 3.2); FP64 populations (headline) and FP32 storage side by side, and the same on
+the D3V125 Gauss-Hermite product set.  Further workloads (the supersonic NACA 0012 O-grid,
+the 2D shear wave at roofline scale, the supersonic channel, the learned correction of the
+mixing layer) are reported in objects of their own.
 
 Prints ONE JSON line.  value = GQUPS = nodes * Q * steps / s (one update = one
-(node, velocity) pair with both f and g).  Inputs are resident in HBM before timing.
-Per-kernel times come from HIP events the library records around each of its launches
-on the timing stream (sllbm_plan_profile).
+(node, velocity) pair with both f and g).  Inputs are resident in HBM before timing.  Every
+leg times REPS = 5 samples of --steps steps (after --warmup untimed ones) with HIP events and
+reports their median.  Per-kernel times come from HIP events the library records around each
+of its launches on the timing stream (sllbm_plan_profile).
 """
 import argparse
 import json
@@ -41,7 +43,8 @@ def curv_bytes_per_update(prec):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=200, help="steps per timed sample (median of --reps samples)")
+    ap.add_argument("--reps", type=int, default=5, help="timed samples per leg (the median is reported)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--ncell", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -57,10 +60,12 @@ def parse():
                     help="convective Mach numbers of the learned-correction legs, comma separated (first one is 'learned')")
     ap.add_argument("--no-extra", action="store_true", help="skip the C1-R (2D roofline-scale) and C4 (channel) lines")
     ap.add_argument("--kernel", choices=["auto", "gather", "tiled"], default="auto")
-    ap.add_argument("--velocity-set", choices=["d3v125", "d3q45"], default="d3v125",
-                    help="velocity set of the headline TGV legs (D3V125 product rule or the reduced D3Q45)")
+    ap.add_argument("--velocity-set", choices=["d3q45", "d3v125"], default="d3q45",
+                    help="velocity set of the headline TGV legs: the reduced degree-9 set D3Q45 the paper "
+                         "uses (Sec. 3.2), or the D3V125 product rule (then reported beside it)")
     ap.add_argument("--no-cubature", action="store_true",
-                    help="skip the TGV legs on the reduced D3Q45 set beside the D3V125 headline")
+                    help="skip the legs on the other TGV velocity set and on the reduced sets D2Q19 / D3Q45 "
+                         "of the other workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for byte counters)")
     return ap.parse_args()
@@ -98,27 +103,47 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def timed_steps(S, plan, prm, a, b, steps, warmup, torch):
-    stream = torch.cuda.current_stream()
-    for _ in range(warmup):
-        S.sllbm_step(plan, prm, a, b, stream)
-        a, b = b, a
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    S.sllbm_plan_profile(plan, True)
-    torch.cuda.synchronize()
+REPS = 5   # timed samples per leg; the reported time is their median
+
+
+def timed_loop(torch, stream, one, steps, reps=None):
+    """reps (default REPS) samples of `steps` calls of one(n), each bracketed by a
+    synchronisation and timed with events on `stream`: (median ms, [ms of each sample], wall
+    seconds of all samples)."""
+    reps = REPS if reps is None else reps
+    samples = []
     w0 = time.perf_counter()
-    t0.record(stream)
-    for _ in range(steps):
-        S.sllbm_step(plan, prm, a, b, stream)
-        a, b = b, a
-    t1.record(stream)
+    for _ in range(reps):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for n in range(steps):
+            one(n)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        samples.append(t0.elapsed_time(t1))
+    return float(np.median(samples)), samples, time.perf_counter() - w0
+
+
+def timed_steps(S, plan, prm, a, b, steps, warmup, torch):
+    """warmup untimed steps, then REPS timed samples of `steps` steps; per-kernel times
+    from the plan's event profile over all samples."""
+    stream = torch.cuda.current_stream()
+    buf = [a, b]
+
+    def one(n):
+        S.sllbm_step(plan, prm, buf[0], buf[1], stream)
+        buf[0], buf[1] = buf[1], buf[0]
+
+    for n in range(warmup):
+        one(n)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
+    S.sllbm_plan_profile(plan, True)
+    med, samples, wall = timed_loop(torch, stream, one, steps)
     prof = S.sllbm_plan_profile_read(plan)
     S.sllbm_plan_profile(plan, False)
-    return a, t0.elapsed_time(t1), wall, prof
+    return buf[0], med, wall, prof, samples
 
 
 def gpu_leg(prec, steps, warmup, ncell, kernel="auto", vel="d3v125"):
@@ -142,11 +167,11 @@ def gpu_leg(prec, steps, warmup, ncell, kernel="auto", vel="d3v125"):
     b = torch.empty_like(a)
     S.sllbm_init_equilibrium(plan, prm, torch.tensor(rho, device=dev), torch.tensor(np.ascontiguousarray(u.T), device=dev),
                              torch.tensor(T, device=dev), a)
-    a, total_ms, wall, prof = timed_steps(S, plan, prm, a, b, steps, warmup, torch)
+    a, total_ms, wall, prof, samples = timed_steps(S, plan, prm, a, b, steps, warmup, torch)
     tot = S.sllbm_moments(plan, prm, a, totals=True)
     torch.cuda.synchronize()
     updates = N * Q
-    return summarize(prof, total_ms, wall, steps, updates, BYTES_PER_UPDATE[prec],
+    return summarize(prof, total_ms, wall, steps, updates, BYTES_PER_UPDATE[prec], samples=samples,
                      finite=all(math.isfinite(x) for x in tot), N=N, Q=Q, mass=float(tot[0]))
 
 
@@ -258,27 +283,24 @@ def tensor_case_leg(case, prec, steps, warmup, Pr=1.0, vel="gh"):
         prm = dataclasses.replace(prm, force_device=1)
     fixp = dataclasses.replace(prm, mass_fix=1, mass_ref=mref)
 
-    def one(n, a, b):
+    buf = [a, b]
+
+    def one(n):
+        a, b = buf
         if fix_every and n % fix_every == 0:
             if ctl:
                 S.sllbm_force_update(plan, a, dt=fix_every * phys.dt, stream=stream, **ctl)
             S.sllbm_step(plan, fixp, a, b, stream)
         else:
             S.sllbm_step(plan, prm, a, b, stream)
+        buf[0], buf[1] = b, a
 
     for n in range(warmup):
-        one(n, a, b)
-        a, b = b, a
+        one(n)
     torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
     S.sllbm_plan_profile(plan, True)
-    t0.record(stream)
-    for n in range(steps):
-        one(n, a, b)
-        a, b = b, a
-    t1.record(stream)
-    torch.cuda.synchronize()
+    med, samples, _ = timed_loop(torch, stream, one, steps)
+    a, b = buf
     prof = S.sllbm_plan_profile_read(plan)
     S.sllbm_plan_profile(plan, False)
     tot = S.sllbm_moments(plan, prm, a, totals=True)
@@ -288,20 +310,23 @@ def tensor_case_leg(case, prec, steps, warmup, Pr=1.0, vel="gh"):
         extra["force_control"] = {"force_x": float(st["force"][0]), "force_x0": float(phys.force[0]),
                                   "mean_momentum": float(st["mean_momentum"]), "target": ctl["target"],
                                   "updates": st["updates"]}
-    r = summarize(prof, t0.elapsed_time(t1), 0.0, steps, N * Q, BYTES_PER_UPDATE[prec],
+    r = summarize(prof, med, 0.0, steps, N * Q, BYTES_PER_UPDATE[prec], samples=samples,
                   finite=all(math.isfinite(x) for x in tot), N=N, Q=Q, **extra)
     del a, b
     torch.cuda.empty_cache()
     return r
 
 
-def summarize(prof, total_ms, wall, steps, updates, bytes_per_update, **extra):
+def summarize(prof, total_ms, wall, steps, updates, bytes_per_update, samples=None, **extra):
+    """total_ms: the (median) time of `steps` steps; samples: the ms of every timed sample."""
     dom = max(prof.items(), key=lambda kv: kv[1][0])
     name, (kms, launches) = dom
     avg_ms = kms / max(launches, 1)
     alg = updates * bytes_per_update
     out = {
         "ms_per_step": total_ms / steps, "wall_s": wall,
+        "median_of": len(samples) if samples else 1,
+        "samples_ms_per_step": [round(x / steps, 5) for x in samples] if samples else None,
         "gqups": updates * steps / (total_ms * 1e-3) / 1e9,
         "kernels": {k: {"avg_ms": round(v[0] / max(v[1], 1), 4), "launches": v[1]} for k, v in prof.items()},
         "dominant": name, "avg_launch_ms": avg_ms, "alg_bytes_per_launch": alg,
@@ -331,10 +356,10 @@ def ogrid_leg(prec, steps, warmup, vel="d2v25"):
     b = torch.empty_like(a)
     S.sllbm_init_equilibrium(plan, prm, torch.tensor(rho, device=dev), torch.tensor(u.T.copy(), device=dev),
                              torch.tensor(T, device=dev), a)
-    a, total_ms, wall, prof = timed_steps(S, plan, prm, a, b, steps, warmup, torch)
+    a, total_ms, wall, prof, samples = timed_steps(S, plan, prm, a, b, steps, warmup, torch)
     tot = S.sllbm_moments(plan, prm, a, totals=True)
     torch.cuda.synchronize()
-    return summarize(prof, total_ms, wall, steps, N * Q, curv_bytes_per_update(prec),
+    return summarize(prof, total_ms, wall, steps, N * Q, curv_bytes_per_update(prec), samples=samples,
                      finite=all(math.isfinite(x) for x in tot), N=N, Q=Q, plan_build_s=plan_s,
                      bpu=curv_bytes_per_update(prec))
 
@@ -618,6 +643,17 @@ def cpu_leg(ncell, steps):
                 break
     except OSError:
         pass
+    lscpu = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=30).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Vendor ID", "CPU family", "Model", "Stepping", "CPU(s)", "Socket(s)",
+                             "Core(s) per socket", "Thread(s) per core", "CPU max MHz", "L3 cache",
+                             "Hypervisor vendor"):
+                lscpu[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     # one thread: the oracle's step at a seeded sample of nodes, in a child process started
     # with OMP_NUM_THREADS=1 (it imports the oracle and numpy only)
     code = ("import time, numpy as np, oracle, workloads as W\n"
@@ -640,6 +676,7 @@ def cpu_leg(ncell, steps):
         one = None
     return {"value": o.N * o.Q * steps / el / 1e9, "unit": "GQUPS", "cores": cores, "kind": "oracle",
             "sample": f"{steps} full step(s) of the {o.N}-node mesh, FP64, {el:.1f} s", "cpu_model": model,
+            "lscpu": lscpu,
             "one_thread": one}
 
 
@@ -652,7 +689,9 @@ def roofline(r, traffic=None):
 
 
 def main():
+    global REPS
     args = parse()
+    REPS = max(1, args.reps)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
@@ -662,11 +701,12 @@ def main():
     r64 = gpu_leg("f64", args.steps, args.warmup, args.ncell, args.kernel, vset)
     print(f"# tgv {vset} f64 done: {r64['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
     r32 = None if args.no_fp32 else gpu_leg("f32", args.steps, args.warmup, args.ncell, args.kernel, vset)
+    other = "d3v125" if vset == "d3q45" else "d3q45"
     cub = {}
-    if vset == "d3v125" and not args.no_cubature:
+    if not args.no_cubature:
         for prec in ("f64", "f32"):
-            cub[prec] = gpu_leg(prec, args.steps, args.warmup, args.ncell, args.kernel, "d3q45")
-            print(f"# tgv d3q45 {prec} done: {cub[prec]['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
+            cub[prec] = gpu_leg(prec, args.steps, args.warmup, args.ncell, args.kernel, other)
+            print(f"# tgv {other} {prec} done: {cub[prec]['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
     og = {}
     if not args.no_ogrid:
         for prec in ("f32", "f64"):
@@ -682,8 +722,6 @@ def main():
         # (case, precisions, Prandtl number, velocity set); the paper's channel set-up (D3Q45,
         # Pr 0.7) belongs to the reduced-set legs
         cases = [("c1r", ("f64", "f32"), 1.0, "gh"), ("c4", ("f32",), 1.0, "gh"), ("c4pr", ("f32",), 0.7, "gh")]
-        if vset == "d3q45":
-            cases = []
         if not args.no_cubature:
             cases += [("c1rq19", ("f64", "f32"), 1.0, "cub"), ("c4paper", ("f32",), 0.7, "cub")]
         for case, precs, Pr, vel in cases:
@@ -691,15 +729,15 @@ def main():
                 extra[f"{case}_{prec}"] = tensor_case_leg("c1r" if case.startswith("c1r") else "c4", prec,
                                                           max(10, args.steps // 5), 3, Pr=Pr, vel=vel)
                 print(f"# {case} {prec} done: {extra[f'{case}_{prec}']['gqups']:.2f} GQUPS", file=sys.stderr, flush=True)
-    prec_cmp = prec_cmp45 = None
+    prec_cmp = prec_cmp_other = None
     if not args.no_fp32 and args.precision_steps > 0:
-        prec_cmp = precision_leg(args.ncell, args.precision_steps)
-        print(f"# FP32 vs FP64 after {args.precision_steps} steps: {prec_cmp['max_rel_diff_at_end']}", file=sys.stderr,
-              flush=True)
+        prec_cmp = precision_leg(args.ncell, args.precision_steps, vel="cub" if vset == "d3q45" else "gh")
+        print(f"# FP32 vs FP64 on {vset} after {args.precision_steps} steps: {prec_cmp['max_rel_diff_at_end']}",
+              file=sys.stderr, flush=True)
         if not args.no_cubature:
-            prec_cmp45 = precision_leg(args.ncell, args.precision_steps, vel="cub")
-            print(f"# FP32 vs FP64 on D3Q45 after {args.precision_steps} steps: {prec_cmp45['max_rel_diff_at_end']}",
-                  file=sys.stderr, flush=True)
+            prec_cmp_other = precision_leg(args.ncell, args.precision_steps, vel="cub" if other == "d3q45" else "gh")
+            print(f"# FP32 vs FP64 on {other} after {args.precision_steps} steps: "
+                  f"{prec_cmp_other['max_rel_diff_at_end']}", file=sys.stderr, flush=True)
     lrn = None
     lrn_more = {}
     if not args.no_learned:
@@ -741,26 +779,33 @@ def main():
         "roofline": roofline(r64, traffic_from_profiles(tkey + "_f64")),
         "cpu_baseline": cpu,
         "kernels": r64["kernels"],
+        "median_of": r64["median_of"],
+        "samples_ms_per_step": r64["samples_ms_per_step"],
     }
     if r32:
         out["fp32"] = {"value": round(r32["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(r32["ms_per_step"], 4),
+                       "median_of": r32["median_of"], "samples_ms_per_step": r32["samples_ms_per_step"],
                        "roofline": roofline(r32, traffic_from_profiles(tkey + "_f32")), "kernels": r32["kernels"]}
     if cub:
-        # same workload and time step on the reduced set: Q = 45 instead of 125, so a step
-        # costs fewer updates; the per-update rate is comparable, the per-step time is not
-        out["d3q45"] = {
-            "workload": f"the same Taylor-Green vortex ({cub['f64']['N']} nodes, same time step) on the reduced "
-                        f"degree-9 velocity set D3Q45",
+        # the same workload and time step on the other velocity set (Q = 125 or 45): the
+        # per-update rate is comparable, the per-step time is not
+        okey = "tgv45" if other == "d3q45" else "tgv"
+        out[other] = {
+            "workload": f"the same Taylor-Green vortex ({cub['f64']['N']} nodes, same time step) on the "
+                        + ("reduced degree-9 velocity set D3Q45" if other == "d3q45" else
+                           "D3V125 Gauss-Hermite product set"),
             **{prec: {"value": round(v["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(v["ms_per_step"], 4),
+                      "median_of": v["median_of"], "samples_ms_per_step": v["samples_ms_per_step"],
                       "node_updates_per_s": round(v["N"] / (v["ms_per_step"] * 1e-3), 1),
-                      "step_time_vs_d3v125": round(v["ms_per_step"] / (r64 if prec == "f64" else r32)["ms_per_step"], 4)
+                      f"step_time_vs_{vset}": round(v["ms_per_step"] / (r64 if prec == "f64" else r32)["ms_per_step"], 4)
                       if (prec == "f64" or r32) else None,
-                      "roofline": roofline(v, traffic_from_profiles("tgv45_" + prec)), "kernels": v["kernels"],
+                      "roofline": roofline(v, traffic_from_profiles(okey + "_" + prec)), "kernels": v["kernels"],
                       "finite": v["finite"]}
                for prec, v in cub.items()}}
     if og:
         def og_line(key, v):
             return {"value": round(v["gqups"], 4), "unit": "GQUPS", "ms_per_step": round(v["ms_per_step"], 4),
+                    "median_of": v["median_of"], "samples_ms_per_step": v["samples_ms_per_step"],
                     "bytes_per_update": v["bpu"], "plan_build_s": round(v["plan_build_s"], 2),
                     "roofline": roofline(v, traffic_from_profiles(key)), "finite": v["finite"]}
         out["ogrid"] = {
@@ -785,13 +830,14 @@ def main():
     for key, v in extra.items():
         case, prec = key.split("_")
         out[key] = {"workload": names[case], "dtype": prec, "value": round(v["gqups"], 4), "unit": "GQUPS",
-                    "ms_per_step": round(v["ms_per_step"], 4), "roofline": roofline(v, traffic_from_profiles(key)),
+                    "ms_per_step": round(v["ms_per_step"], 4), "median_of": v["median_of"],
+                    "samples_ms_per_step": v["samples_ms_per_step"], "roofline": roofline(v, traffic_from_profiles(key)),
                     "kernels": v["kernels"],
                     "finite": v["finite"], **({"force_control": v["force_control"]} if "force_control" in v else {})}
     if prec_cmp:
         out["fp32_vs_fp64"] = prec_cmp
-    if prec_cmp45:
-        out["fp32_vs_fp64_d3q45"] = prec_cmp45
+    if prec_cmp_other:
+        out["fp32_vs_fp64_" + other] = prec_cmp_other
     if lrn:
         out["learned"] = lrn
         if lrn_more:
