@@ -58,6 +58,14 @@ def parse():
                     help="coarse steps of each mixing-layer run (default: to the end of the self-similar window)")
     ap.add_argument("--learned-mach", default="0.7",
                     help="convective Mach numbers of the learned-correction legs, comma separated (first one is 'learned')")
+    ap.add_argument("--learned-ncell", type=int, default=16,
+                    help="coarse cells per axis of the mixing layer (64: the workload's coarse mesh in the paper's "
+                         "160 x 176 x 98 box; smaller: the same cell size in a box scaled with it)")
+    ap.add_argument("--learned-ratio", type=int, default=4, help="refinement per axis of the fine mixing layer")
+    ap.add_argument("--learned-targets", choices=["injected", "trajectory"], default="injected",
+                    help="training targets: one step from the restricted fine state, or along the plain coarse run")
+    ap.add_argument("--learned-set", choices=["gh", "cub"], default="gh",
+                    help="velocity set of the 'learned' legs (D3V125, or D3Q45 at Pr 0.71 as in the paper)")
     ap.add_argument("--no-extra", action="store_true", help="skip the C1-R (2D roofline-scale) and C4 (channel) lines")
     ap.add_argument("--kernel", choices=["auto", "gather", "tiled"], default="auto")
     ap.add_argument("--velocity-set", choices=["d3q45", "d3v125"], default="d3q45",
@@ -381,6 +389,10 @@ def mixing_dtheta(S, torch, plan, prm, pop, shape, du, V, box):
 
 def learned_leg(ncell=16, ratio=4, steps=None, n_train=8, train_iters=1500, Ma_c=0.7, alphas=(0.0, 0.25, 0.5, 1.0),
                 targets="injected", vel="gh", Pr=1.0):
+    return _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, targets, vel, Pr)
+
+
+def _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, targets, vel, Pr):
     """C5: temporal mixing layer on a coarse mesh, plain and with the learned correction,
     against the 4x finer mesh; FP32 populations.  The network is trained by the library's
     kernels on restricted one-step samples of a fine run (seed 5); a gain alpha on its
@@ -398,7 +410,9 @@ def learned_leg(ncell=16, ratio=4, steps=None, n_train=8, train_iters=1500, Ma_c
     import paper_2412_09051_amd as S
     import workloads as W
     d0 = W.MIX_DTHETA0
-    box = tuple(ncell * c * d0 for c in MIX_BOX_CELLS)
+    # 64 coarse cells per axis: the paper's box (Sec. 4.4, 160 x 176 x 98 initial momentum
+    # thicknesses); fewer: the same coarse cell in a box scaled with the cell count
+    box = tuple(x * d0 for x in (160, 176, 98)) if ncell == 64 else tuple(ncell * c * d0 for c in MIX_BOX_CELLS)
     mesh, phys = W.mixing_layer_case(ncell=(ncell,) * 3, box=box, Ma_c=Ma_c)
     fmesh, fphys = W.mixing_layer_case(ncell=(ncell,) * 3, refine=ratio, box=box, Ma_c=Ma_c)
     phys, fphys = dataclasses.replace(phys, Pr=Pr), dataclasses.replace(fphys, Pr=Pr)
@@ -449,9 +463,10 @@ def learned_leg(ncell=16, ratio=4, steps=None, n_train=8, train_iters=1500, Ma_c
             if n == steps:
                 break
             e0.record()
-            S.sllbm_step(cplan, cprm, a, b)
             if net is not None:
-                S.sllbm_mlp_correct(cplan, cprm, net, b)
+                S.sllbm_step_learned(cplan, cprm, net, a, b)
+            else:
+                S.sllbm_step(cplan, cprm, a, b)
             e1.record()
             a, b = b, a
             if timed:
@@ -560,6 +575,9 @@ def learned_leg(ncell=16, ratio=4, steps=None, n_train=8, train_iters=1500, Ma_c
     return {
         "workload": f"3D temporal mixing layer Ma_c {Ma_c}, coarse {ncell}^3 cells p=2 ({Nc} nodes) vs "
                     f"{ratio}x finer ({Nf} nodes), {vname}, Pr {Pr}, FP32; trained on seed 5, evaluated on seed 6",
+        "box_dtheta0": [round(b / d0, 3) for b in box],
+        "coarse_kernel": {0: "gather", 2: "tiled (relaxation and correction in one pass)"}.get(
+            S.sllbm_plan_info(cplan)["kernel"], "other"),
         "steps": steps, "targets": targets, "train_samples": n_train, "train_iters": train_iters, "train_loss": losses,
         "train_s": round(train_s, 2),
         "alpha_selection_window_rate_err": {str(k): round(v, 4) for k, v in sel.items()},
@@ -742,8 +760,10 @@ def main():
     lrn_more = {}
     if not args.no_learned:
         machs = [float(x) for x in args.learned_mach.split(",")]
+        lset = dict(vel="cub", Pr=0.71) if args.learned_set == "cub" else {}
         for i, mc in enumerate(machs):
-            r = learned_leg(Ma_c=mc, steps=args.learned_steps)
+            r = learned_leg(ncell=args.learned_ncell, ratio=args.learned_ratio, Ma_c=mc, steps=args.learned_steps,
+                            targets=args.learned_targets, **lset)
             print(f"# learned Ma_c {mc} done: time-to-solution ratio {r['time_to_solution_ratio']}", file=sys.stderr,
                   flush=True)
             if i == 0:
@@ -751,8 +771,9 @@ def main():
             else:
                 lrn_more[str(mc)] = r
     lrn_paper = None
-    if not args.no_learned and not args.no_cubature:
-        lrn_paper = learned_leg(Ma_c=0.7, vel="cub", Pr=0.71, steps=args.learned_steps)
+    if not args.no_learned and not args.no_cubature and args.learned_set == "gh":
+        lrn_paper = learned_leg(ncell=args.learned_ncell, ratio=args.learned_ratio, Ma_c=0.7, vel="cub", Pr=0.71,
+                                steps=args.learned_steps, targets=args.learned_targets)
         print(f"# learned, the paper's mixing-layer set-up (D3Q45, Pr 0.71) done: time-to-solution ratio "
               f"{lrn_paper['time_to_solution_ratio']}", file=sys.stderr, flush=True)
     cal = copy_calibration() if args.copy_calibration else None

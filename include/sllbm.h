@@ -306,6 +306,16 @@ int sllbm_mlp_forward(sllbm_mlp m, const uint16_t *x_bf16, int64_t rows, float *
 /* In place on a post-collision population field of plan p: features, network, scaled and
  * projected correction added.  The network's n_in / n_out must match the plan. */
 int sllbm_mlp_correct(sllbm_plan p, const sllbm_params *prm, sllbm_mlp m, void *pop, void *stream);
+/* One step of the learned method: sllbm_step followed by sllbm_mlp_correct on its result,
+ * with the same arguments, layouts and errors as those two calls (the network's n_in / n_out
+ * must match the plan).  On 3D plans stepped by the LDS-tiled kernel the relaxation and the
+ * correction share one pass over the populations: the streaming launch stores the streamed
+ * values and each node's state, the node fields (rho, u, T of the post-collision state: the
+ * collision keeps rho and T, Kupershtokh forcing adds F dt / rho to u) and their gradients
+ * come from that state, and one launch relaxes the stored values and adds the projected
+ * correction.  Elsewhere it runs the two calls. */
+int sllbm_step_learned(sllbm_plan p, const sllbm_params *prm, sllbm_mlp m, const void *pop_in, void *pop_out,
+                       void *stream);
 /* Training targets of every node of plan p into t (device FP32 [N][2Q]). */
 int sllbm_learned_targets(sllbm_plan p, const void *pop_plain, const void *pop_true, float *t, void *stream);
 /* Injection of a fine population field onto a nested coarse mesh: coarse node (jx,jy,jz)

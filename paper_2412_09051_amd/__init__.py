@@ -426,7 +426,7 @@ def sllbm_force_read(plan: Plan, stream=None) -> dict:
 # ------------------------------------------------------------------ learned correction
 
 for _name in ("sllbm_mlp_create", "sllbm_mlp_num_params", "sllbm_mlp_get_params", "sllbm_mlp_set_params",
-              "sllbm_features", "sllbm_mlp_forward", "sllbm_mlp_correct", "sllbm_learned_targets", "sllbm_restrict",
+              "sllbm_features", "sllbm_mlp_forward", "sllbm_mlp_correct", "sllbm_step_learned", "sllbm_learned_targets", "sllbm_restrict",
               "sllbm_mlp_gradient", "sllbm_mlp_train_step"):
     getattr(_lib, _name).restype = ctypes.c_int
 _lib.sllbm_mlp_destroy.restype = None
@@ -497,6 +497,16 @@ def sllbm_mlp_correct(plan: Plan, params: Params, m: Mlp, pop, stream=None):
            "sllbm_mlp_correct")
 
 
+def sllbm_step_learned(plan: Plan, params: Params, m: Mlp, pop_in, pop_out, stream=None):
+    """One step with the learned correction (sllbm_step then sllbm_mlp_correct; on 3D tiled
+    plans the relaxation and the correction in one pass)."""
+    n = 2 * plan.Q * plan.N
+    _check(_lib.sllbm_step_learned(plan.handle, ctypes.byref(params.c()), m.handle,
+                                   _dev_ptr(pop_in, _pop_dtype(plan), n, "pop_in"),
+                                   _dev_ptr(pop_out, _pop_dtype(plan), n, "pop_out"), _stream(stream)),
+           "sllbm_step_learned")
+
+
 def sllbm_learned_targets(plan: Plan, pop_plain, pop_true, t, stream=None):
     """t: torch.float32 [N, 2Q]."""
     import torch
@@ -544,5 +554,5 @@ __all__ = ["sllbm_velset_gauss_hermite", "sllbm_velset_cubature", "sllbm_mesh_bu
            "sllbm_moments_noalloc", "sllbm_force_reset", "sllbm_force_update", "sllbm_force_read", "sllbm_set_allocator", "use_torch_allocator",
            "Params", "Plan", "Mesh", "SllbmError", "SLLBM_F64", "SLLBM_F32", "LIB_PATH",
            "Mlp", "sllbm_mlp_create", "sllbm_mlp_get_params", "sllbm_mlp_set_params", "sllbm_features",
-           "sllbm_mlp_forward", "sllbm_mlp_correct", "sllbm_learned_targets", "sllbm_restrict", "sllbm_mlp_gradient",
+           "sllbm_mlp_forward", "sllbm_mlp_correct", "sllbm_step_learned", "sllbm_learned_targets", "sllbm_restrict", "sllbm_mlp_gradient",
            "sllbm_mlp_train_step", "n_features"]

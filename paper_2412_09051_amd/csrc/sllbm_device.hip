@@ -450,6 +450,33 @@ extern "C" int sllbm_step(sllbm_plan P, const sllbm_params *prm, const void *pin
   return launch_step(P, a, pin, pout, s);
 }
 
+extern "C" int sllbm_step_learned(sllbm_plan P, const sllbm_params *prm, sllbm_mlp m, const void *pin, void *pout,
+                                  void *stream) {
+  if (!P) return fail(SLLBM_EINVAL, "step_learned: plan is NULL");
+  int rc = check_params(P, prm);
+  if (rc) return rc;
+  if ((rc = check_pop(P, pin, "pop_in")) || (rc = check_pop(P, pout, "pop_out"))) return rc;
+  size_t bytes = 2 * (size_t)P->vel.Q * (size_t)P->mesh.n_nodes * elem_size(P);
+  const char *a0 = (const char *)pin, *b0 = (const char *)pout;
+  if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(SLLBM_EINVAL, "step_learned: pop_in and pop_out overlap");
+  if ((rc = require_device(P))) return rc;
+  if ((rc = learned_check(P, m))) return rc;
+  StepArgs a = make_args(P, prm);
+  hipStream_t s = (hipStream_t)stream;
+  if (prm->mass_fix) {
+    rc = launch_mass_scale(P, pin, prm->mass_ref, s);
+    if (rc) return rc;
+    a.scale = P->scratch + kSlotScale;
+  }
+  if (!step_has_relax_launch(P)) {
+    // kernels that relax as they stream: the step, then the correction on its result
+    if ((rc = launch_step(P, a, pin, pout, s))) return rc;
+    return launch_mlp_correct(P, prm, m, pout, s);
+  }
+  if ((rc = launch_step(P, a, pin, pout, s, false))) return rc;
+  return launch_relax_correct(P, a, m, pout, s);
+}
+
 extern "C" int sllbm_force_reset(sllbm_plan P, const double *force0, void *stream) {
   if (!P || !force0) return fail(SLLBM_EINVAL, "force_reset: NULL argument");
   double F[3] = {0.0, 0.0, 0.0};

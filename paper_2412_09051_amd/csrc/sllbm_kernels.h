@@ -63,10 +63,17 @@ template <> struct TileShape<3, 3> {
 template <> struct TileShape<3, 4> { static constexpr int CX = 2, CY = 2, CZ = 2; };
 
 int launch_step_csr(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout, hipStream_t s);
-int launch_step_tile(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout, hipStream_t s);
+// relax = false: 3D plans on the two-launch tile path stop after the streaming launch (the
+// owned nodes' streamed values and node state stored, the relaxation left to the caller); the
+// boundary layers' gather launch still relaxes its nodes.
+int launch_step_tile(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout, hipStream_t s,
+                     bool relax = true);
 int launch_init(sllbm_plan_s *P, const StepArgs &a, const double *rho, const double *u, const double *T, void *pop,
                 hipStream_t s);
-int launch_step(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout, hipStream_t s);
+int launch_step(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout, hipStream_t s, bool relax = true);
+// True if a step of this plan runs the 3D two-launch tile path (streaming launch, node state,
+// relaxation launch), whose relaxation launch_step(..., relax = false) leaves out.
+bool step_has_relax_launch(const sllbm_plan_s *P);
 int launch_moments(sllbm_plan_s *P, const StepArgs &a, const void *pop, double *rho, double *u, double *T,
                    bool totals, hipStream_t s);
 // The same with the block partials of the totals in part[kRedWidth * nblocks(N)] and the final
@@ -74,6 +81,15 @@ int launch_moments(sllbm_plan_s *P, const StepArgs &a, const void *pop, double *
 int launch_moments_to(sllbm_plan_s *P, const StepArgs &a, const void *pop, double *rho, double *u, double *T,
                       double *part, double *totals, hipStream_t s);
 int launch_mass_scale(sllbm_plan_s *P, const void *pop, double mass_ref, hipStream_t s);
+// Learned correction (sllbm_mlp.hip).  learned_check: the network fits the plan (inputs,
+// outputs, device) and the plan's learned-mode buffers exist (allocated on first use).
+// launch_mlp_correct: features of pop, network, projected correction added in place.
+// launch_relax_correct: after launch_step(..., relax = false) on a plan with a relaxation
+// launch, the node fields from the node state, the features, then the relaxation and the
+// correction in one pass over pop.
+int learned_check(sllbm_plan_s *P, sllbm_mlp m);
+int launch_mlp_correct(sllbm_plan_s *P, const sllbm_params *prm, sllbm_mlp m, void *pop, hipStream_t s);
+int launch_relax_correct(sllbm_plan_s *P, const StepArgs &a, sllbm_mlp m, void *pop, hipStream_t s);
 int launch_force_reset(sllbm_plan_s *P, const double *force0, hipStream_t s);
 int launch_force_update(sllbm_plan_s *P, int axis, double target, double kp, double ki, double dt, const void *pop,
                         hipStream_t s);

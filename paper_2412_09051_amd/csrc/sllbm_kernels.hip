@@ -379,7 +379,9 @@ int dispatch_gather(sllbm_plan_s *Pl, const StepArgs &a, const Slab &sl, const v
 }
 }  // namespace
 
-int launch_step(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
+bool step_has_relax_launch(const sllbm_plan_s *P) { return P->kernel == 0 && P->use_tile() && P->mesh.dim == 3; }
+
+int launch_step(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s, bool relax) {
   if (Pl->kernel == 1) {
     int rc = launch_step_csr(Pl, a, pin, pout, s);
     if (rc) return rc;
@@ -394,7 +396,7 @@ int launch_step(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout
   int rc;
   if (Pl->use_tile()) {
     // interior nodes: LDS-tiled kernel; boundary-layer slabs: per-node gather
-    rc = launch_step_tile(Pl, a, pin, pout, s);
+    rc = launch_step_tile(Pl, a, pin, pout, s, relax);
     if (rc) return rc;
     // the faces with boundary layers all lie on the one bounded axis: one launch covers both
     Slab sl{-1, 0, 0, 0, 1};

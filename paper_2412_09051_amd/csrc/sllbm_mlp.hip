@@ -38,9 +38,9 @@ constexpr int NT = 256;      // threads per workgroup (4 waves)
 constexpr int WBF_W1 = 0, WBF_W2 = KIN * HW, WBF_W3 = KIN * HW + HW * HW, WBF_W4 = KIN * HW + 2 * HW * HW;
 constexpr int WBF_N = KIN * HW + 2 * HW * HW + HW * NOUTP;
 constexpr int kMaxPartialBlocks = 512;
-// The correction kernel's LDS (126 KB) admits one workgroup per compute unit: a grid of one
-// workgroup per CU stages the weights once per CU and walks the tiles from there.
-constexpr int64_t kCorrectGrid = 256;
+// The correction kernels' LDS (about 76 KB) admits two workgroups per compute unit: a grid of
+// two per CU stages the weights twice per CU and walks the tiles from there.
+constexpr int64_t kCorrectGrid = 512;
 
 __host__ __device__ inline uint16_t f2bf(float f) {
   uint32_t u;
@@ -106,7 +106,8 @@ __device__ inline float tile_colsum(float4_t acc) {
 struct MlpArgs {
   int n_in, n_out;
   const float *theta;     // master weights (biases read from here)
-  const uint16_t *wbf;    // padded BF16 weights
+  const uint16_t *wbf;    // padded BF16 weights, each layer [in][out]
+  const uint16_t *wbt;    // the same transposed, each layer [out][in] (the correction kernels)
   int off[8];
 };
 
@@ -185,95 +186,338 @@ struct ProjArgs {
   double G[25];            // (M W M^T)^-1, (D+2) x (D+2)
 };
 
+// A node lies in a boundary layer of a bounded face (the gather kernel's nodes, relaxed
+// there) if its index along the face axis is within the face's depth.
+__device__ inline bool in_layer(const DevTensorPlan &pl, int64_t k) {
+  const int Nx = pl.ax[0].N, Ny = pl.ax[1].N;
+  for (int fc = 0; fc < pl.nfaces; fc++) {
+    const DevFace &F = pl.face[fc];
+    const int64_t n3 = F.axis == 0 ? k % Nx : (F.axis == 1 ? (k / Nx) % Ny : k / ((int64_t)Nx * Ny));
+    const int64_t l = F.side == 0 ? n3 : pl.ax[F.axis].N - 1 - n3;
+    if (l < F.depth) return true;
+  }
+  return false;
+}
+
+// Post-collision node fields (rho, u, T) [D+2][N] of a 3D tile step whose relaxation is still
+// to come: for the tile's nodes from the node state the streaming launch stored (the
+// collision keeps rho and T and Kupershtokh's difference adds F dt / rho to u), for the
+// boundary layers (already relaxed by the gather launch) from their populations.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_mlp_correct(MlpArgs m, ProjArgs pa, const uint16_t *feat,
-                                                    const double *rho, int64_t N, T *pop) {
-  __shared__ FwdShared S;
-  __shared__ float Y[R * NOUTP];
-  __shared__ double C[R * 5];
-  stage_weights(m, S.W);   // once per workgroup; the workgroup then walks its tiles
-  const int64_t ntiles = (N + R - 1) / R;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-  const int64_t row0 = tile * R;
-  __syncthreads();
-  stage_x(m, feat, row0, N, S.X);
-  __syncthreads();
-  hidden_layers(m, S);
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, g = l >> 4;
-  const float *b4 = m.theta + m.off[7];
-  for (int t = wave; t < 2 * (NOUTP / 16); t += 4) {
-    const int rt = t & 1, ct = t >> 1;
-    float4_t acc = {0.f, 0.f, 0.f, 0.f};
-    acc = mma_ab(S.H[2] + rt * 16 * HW, HW, S.W + WBF_W4 + ct * 16, NOUTP, HW, acc);
+__global__ void k_step_fields(const DevTensorPlan pl, const StepArgs sa, const double *nstate, const T *pop,
+                              double *fld) {
+  const int64_t N = pl.N;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  double rho, u[3], Tk;
+  if (in_layer(pl, k)) {
+    const int Q = pl.Q;
+    double j[3] = {0, 0, 0}, E = 0;
+    rho = 0;
+    for (int i = 0; i < Q; i++) {
+      const double *vi = pl.vel + 8 * i;
+      const double f = (double)pop[(size_t)i * N + k], g = (double)pop[((size_t)Q + i) * N + k];
+      rho += f;
+      double z2 = 0;
+      for (int a = 0; a < 3; a++) {
+        j[a] += vi[a] * f;
+        z2 += vi[a] * vi[a];
+      }
+      E += z2 * f + g;
+    }
+    double uu = 0;
+    for (int a = 0; a < 3; a++) {
+      u[a] = j[a] / rho;
+      uu += u[a] * u[a];
+    }
+    Tk = (E - rho * uu) / (2.0 * rho * sa.cv);
+  } else {
+    rho = nstate[k];
+    Tk = nstate[4 * N + k];
+    double F[3] = {0, 0, 0};
+    if (sa.has_force) {
+      for (int a = 0; a < 3; a++) F[a] = sa.force_dev ? sa.force_dev[a] : sa.force[a];
+    }
+    for (int a = 0; a < 3; a++) u[a] = nstate[(size_t)(1 + a) * N + k] + F[a] * sa.dt / rho;
+  }
+  fld[k] = rho;
+  for (int a = 0; a < 3; a++) fld[(size_t)(1 + a) * N + k] = u[a];
+  fld[4 * (size_t)N + k] = Tk;
+}
+
+// The correction kernels: a persistent grid of 256-thread workgroups (4 waves), two per
+// compute unit as their LDS allows (so that one workgroup's network runs while the other's
+// population pass waits on memory), each walking 32-node tiles.  Per workgroup the hidden
+// layers' transposed BF16 weights, the biases and the velocity constants are staged once;
+// the output layer's weights (up to 32 KB) are read from the L1/L2-resident global copy.  Per
+// tile: the network on the 32 nodes' features (16x16x16 BF16 MFMA tiles, operands read 4
+// values at a time: the activations row-major, the weights transposed), the invariant sums
+// of the scaled outputs, then one pass over the tile's populations, one node per lane and
+// several populations in flight per lane.
+constexpr int RC = 32;       // nodes per tile
+constexpr int NTC = 256;     // threads per workgroup
+constexpr int UB = 8;        // populations per lane in flight in the population pass
+constexpr int WH_N = KIN * HW + 2 * HW * HW;   // hidden layers' weights
+
+// D += A B over K, A (16 x K) row-major with leading dimension lda, B given transposed
+// (Bt: 16 x K, row n holds column n of B); lane l reads A[l%16][k0+4(l/16) .. +3] and
+// Bt[l%16][k0+4(l/16) .. +3] as single 8-byte loads (v_mfma_f32_16x16x16_bf16 layout), all
+// k-steps' operands before the products.
+template <int K>
+__device__ inline float4_t mma_abt4(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, float4_t acc) {
+  const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+  short4_t a[K / 16], b[K / 16];
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-      int row = rt * 16 + 4 * g + j, col = ct * 16 + r;
-      Y[row * NOUTP + col] = col < m.n_out ? acc[j] + b4[col] : 0.f;
-    }
+  for (int q = 0; q < K / 16; q++) {
+    a[q] = *(const short4_t *)(A + r * lda + 16 * q + 4 * g);
+    b[q] = *(const short4_t *)(Bt + r * ldb + 16 * q + 4 * g);
   }
-  __syncthreads();
-  const int Q = pa.Q, D = pa.D, NQ = D + 2, Q2 = 2 * Q;
-  {  // invariant sums s = M (w rho y) per node, then c = G s
-    const int row = threadIdx.x >> 3, part = threadIdx.x & 7;
-    const int64_t k = row0 + row;
-    const double rk = k < N ? rho[k] : 0.0;
-    double s[5] = {0, 0, 0, 0, 0};
-    for (int c = part; c < Q2; c += 8) {
-      const int i = c < Q ? c : c - Q;
-      const double *vi = pa.vel + 8 * i;
-      const double dy = vi[7] * rk * (double)Y[row * NOUTP + c];
-      if (c < Q) {
-        s[0] += dy;
-        double z2 = 0.0;
-        for (int a = 0; a < D; a++) {
-          s[1 + a] += vi[a] * dy;
-          z2 += vi[a] * vi[a];
+#pragma unroll
+  for (int q = 0; q < K / 16; q++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[q], b[q], acc, 0, 0, 0);
+  return acc;
+}
+
+// tanh from one exponential: tanh x = sign(x) (1 - e) / (1 + e), e = exp(-2 |x|) (FP32; the
+// result is rounded to BF16 next)
+__device__ inline float tanh_fast(float x) {
+  const float e = __expf(-2.f * fabsf(x));
+  return copysignf((1.f - e) / (1.f + e), x);
+}
+
+struct CorrShared {
+  uint16_t W[WH_N];                       // hidden layers' transposed weights
+  float B[3 * HW + NOUTP];                // biases
+  union {
+    struct {
+      uint16_t X[RC * KIN];
+      uint16_t H[2][RC * HW];
+    } a;
+    double hq[2 * NTC / 64][RC][6];       // heat-flux partials of the half-waves (Pr != 1)
+  } u;
+  float Y[RC * (NOUTP + 1)];              // rows padded to an odd stride (bank-conflict free
+                                          // column reads)
+  double C[RC * 5];
+  double V[kMaxQ][8];                     // velocity constants: zeta, xi, |xi|^2, w
+};
+
+// RELAX = 0: the correction alone, in place on post-collision populations (fld: the node
+// fields of those populations).  RELAX = 1: the relaxation of a 3D tile step fused with the
+// correction: the tile's nodes hold their stored streamed values and node state (nstate) and
+// are relaxed (BGK against the equilibrium of their node state, the Prandtl-number term when
+// PR = 1, Kupershtokh forcing) exactly as the relaxation launch does, then corrected;
+// boundary-layer nodes arrive relaxed by the gather launch and are only corrected.
+template <typename T, int RELAX, int PR, int D>
+__global__ void __launch_bounds__(NTC, 2) k_correct(MlpArgs m, ProjArgs pa, const DevTensorPlan pl,
+                                                    const StepArgs sa, int64_t N, const uint16_t *feat,
+                                                    const double *fld, const double *nstate, T *pop) {
+  __shared__ CorrShared S;
+  constexpr int NQ = D + 2;
+  const int Q = pa.Q, Q2 = 2 * Q;
+  {  // hidden weights, biases and velocity constants, once per workgroup
+    const uint32_t *src = (const uint32_t *)m.wbt;
+    uint32_t *dst = (uint32_t *)S.W;
+    for (int e = threadIdx.x; e < WH_N / 2; e += NTC) dst[e] = src[e];
+    for (int e = threadIdx.x; e < 3 * HW + NOUTP; e += NTC) {
+      const int layer = e < 3 * HW ? e / HW : 3, c = e - layer * HW;
+      S.B[e] = (layer < 3 || c < m.n_out) ? m.theta[m.off[2 * layer + 1] + c] : 0.f;
+    }
+    for (int e = threadIdx.x; e < Q * 8; e += NTC) S.V[e >> 3][e & 7] = pa.vel[e];
+  }
+  const uint16_t *W4t = m.wbt + WBF_W4;   // output layer, transposed [NOUTP][HW], global
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  const int nct = (m.n_out + 15) / 16;    // output column tiles
+  // population passes: node `node` of the tile, half-wave `hw` of 8 (one population each)
+  const int node = lane & (RC - 1), hw = 2 * wave + (lane >> 5);
+  const int64_t ntiles = (N + RC - 1) / RC;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row0 = tile * RC;
+    const int64_t k = row0 + node;
+    const bool valid = k < N;
+    // ---- relaxation coefficients of this lane's node
+    bool act = false;
+    EqNode eq{}, ef{};
+    double itau = 0.0, gT = 0.0;
+    if constexpr (RELAX) {
+      if (valid && sa.relax_mode != 2 && !in_layer(pl, k)) {
+        act = true;
+        const double rho = nstate[k], u0 = nstate[N + k], u1 = nstate[2 * N + k], u2 = nstate[3 * N + k];
+        const double Tn = nstate[4 * N + k];
+        itau = nstate[5 * N + k];
+        eq = eq_prepare(rho, u0, u1, u2, Tn, sa, D);
+        ef = sa.has_force ? eq_forced(rho, u0, u1, u2, Tn, sa, D) : eq;
+        gT = Tn * sa.gbase;
+      }
+    }
+    __syncthreads();   // the previous tile's passes are done with every buffer
+    PrTerm pt{};
+    if constexpr (RELAX && PR) {  // Pr != 1: heat flux of the streamed values over the half-waves
+      HeatFlux h = {0, 0, 0, 0, 0, 0};
+      if (act) {
+        const double u0 = nstate[N + k], u1 = nstate[2 * N + k], u2 = nstate[3 * N + k];
+        for (int i = hw; i < Q; i += 2 * NTC / 64)
+          heat_flux_add(h, S.V[i], u0, u1, u2, (double)pop[(size_t)i * N + k], (double)pop[((size_t)Q + i) * N + k]);
+      }
+      double *hp = S.u.hq[hw][node];
+      hp[0] = h.f0;
+      hp[1] = h.f1;
+      hp[2] = h.f2;
+      hp[3] = h.g0;
+      hp[4] = h.g1;
+      hp[5] = h.g2;
+      __syncthreads();
+      double t[6] = {0, 0, 0, 0, 0, 0};
+      for (int w = 0; w < 2 * NTC / 64; w++)
+#pragma unroll
+        for (int q = 0; q < 6; q++) t[q] += S.u.hq[w][node][q];
+      if (act) pt = pr_term(HeatFlux{t[0], t[1], t[2], t[3], t[4], t[5]}, itau, sa, D);
+      __syncthreads();   // the partials share their space with X and H
+    }
+    // ---- network: features -> three tanh layers -> outputs
+    for (int e = threadIdx.x; e < RC * KIN; e += NTC) {
+      const int rr = e / KIN, c = e % KIN;
+      const int64_t gr = row0 + rr;
+      S.u.a.X[e] = (gr < N && c < m.n_in) ? feat[gr * m.n_in + c] : (uint16_t)0;
+    }
+    __syncthreads();
+    for (int layer = 0; layer < 3; layer++) {
+      const uint16_t *in = layer == 0 ? S.u.a.X : S.u.a.H[(layer - 1) & 1];
+      uint16_t *out = S.u.a.H[layer & 1];
+      const uint16_t *Wt = S.W + (layer == 0 ? WBF_W1 : (layer == 1 ? WBF_W2 : WBF_W3));
+      const float *b = S.B + layer * HW;
+      // 8 output tiles of 16 x 16 over 4 waves: two each, their products issued together
+      float4_t acc[2];
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        const int t = wave + 4 * h, rt = t & 1, ct = t >> 1;
+        acc[h] = float4_t{0.f, 0.f, 0.f, 0.f};
+        if (layer == 0) acc[h] = mma_abt4<KIN>(in + rt * 16 * KIN, KIN, Wt + ct * 16 * KIN, KIN, acc[h]);
+        else acc[h] = mma_abt4<HW>(in + rt * 16 * HW, HW, Wt + ct * 16 * HW, HW, acc[h]);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        const int t = wave + 4 * h, rt = t & 1, ct = t >> 1;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int row = rt * 16 + 4 * g + j, col = ct * 16 + r;
+          out[row * HW + col] = f2bf(tanh_fast(acc[h][j] + b[col]));
         }
-        s[NQ - 1] += z2 * dy;
-      } else {
-        s[NQ - 1] += dy;
+      }
+      __syncthreads();
+    }
+    {
+      const float *b4 = S.B + 3 * HW;
+      const uint16_t *h3 = S.u.a.H[0];     // the third layer's output (layer 2 writes H[0])
+      for (int t = wave; t < 2 * nct; t += NTC / 64) {
+        const int rt = t & 1, ct = t >> 1;
+        float4_t acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mma_abt4<HW>(h3 + rt * 16 * HW, HW, W4t + ct * 16 * HW, HW, acc);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int row = rt * 16 + 4 * g + j, col = ct * 16 + r;
+          S.Y[row * (NOUTP + 1) + col] = acc[j] + b4[col];
+        }
       }
     }
-    for (int q = 0; q < NQ; q++) {
-      s[q] += __shfl_xor(s[q], 1);
-      s[q] += __shfl_xor(s[q], 2);
-      s[q] += __shfl_xor(s[q], 4);
-    }
-    if (part == 0)
-      for (int q = 0; q < NQ; q++) {
-        double v = 0.0;
-        for (int q2 = 0; q2 < NQ; q2++) v += pa.G[q * NQ + q2] * s[q2];
-        C[row * 5 + q] = v;
-      }
-  }
-  __syncthreads();
-  {  // pop += w rho y - w (M^T c): 32 consecutive nodes per population, coalesced
-    const int row = threadIdx.x & 31, part = threadIdx.x >> 5;
-    const int64_t k = row0 + row;
-    if (k < N) {
-      const double rk = rho[k];
-      const double *cc = C + row * 5;
+    __syncthreads();
+    {  // invariant sums s = M (w rho y) per node, then c = G s: 8 threads per node
+      const int row = threadIdx.x >> 3, part = threadIdx.x & 7;
+      const int64_t kr = row0 + row;
+      const double rk = kr < N ? fld[kr] : 0.0;
+      double sm[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; q++) sm[q] = 0.0;
       for (int c = part; c < Q2; c += 8) {
-        const int i = c < Q ? c : c - Q;
-        const double *vi = pa.vel + 8 * i;
-        double mt;
-        if (c < Q) {
+        const bool isf = c < Q;
+        const double *vi = S.V[isf ? c : c - Q];
+        const double dy = vi[7] * rk * (double)S.Y[row * (NOUTP + 1) + c];
+        if (isf) {
+          sm[0] += dy;
           double z2 = 0.0;
-          mt = cc[0];
+#pragma unroll
           for (int a = 0; a < D; a++) {
-            mt += cc[1 + a] * vi[a];
+            sm[1 + a] += vi[a] * dy;
             z2 += vi[a] * vi[a];
           }
-          mt += cc[NQ - 1] * z2;
+          sm[NQ - 1] += z2 * dy;
         } else {
-          mt = cc[NQ - 1];
+          sm[NQ - 1] += dy;
         }
-        const double delta = vi[7] * (rk * (double)Y[row * NOUTP + c] - mt);
-        T *pp = pop + (size_t)c * N + k;
-        *pp = (T)((double)*pp + delta);
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; q++) {
+        sm[q] += __shfl_xor(sm[q], 1);
+        sm[q] += __shfl_xor(sm[q], 2);
+        sm[q] += __shfl_xor(sm[q], 4);
+      }
+      if (part == 0)
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+          double v = 0.0;
+#pragma unroll
+          for (int q2 = 0; q2 < NQ; q2++) v += pa.G[q * NQ + q2] * sm[q2];
+          S.C[row * 5 + q] = v;
+        }
+    }
+    __syncthreads();
+    // ---- populations: pop = relax(pop) + w rho y - w (M^T c), node `node`, c = hw + 8 n
+    if (valid) {
+      const double rk = fld[k];
+      double cc[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; q++) cc[q] = S.C[node * 5 + q];
+      for (int c0 = hw; c0 < Q2; c0 += UB * (2 * NTC / 64)) {
+        T hv[UB];
+#pragma unroll
+        for (int b = 0; b < UB; b++) {
+          const int c = c0 + b * (2 * NTC / 64);
+          if (c < Q2) hv[b] = pop[(size_t)c * N + k];
+        }
+#pragma unroll
+        for (int b = 0; b < UB; b++) {
+          const int c = c0 + b * (2 * NTC / 64);
+          if (c >= Q2) break;
+          const bool isf = c < Q;
+          const double *vi = S.V[isf ? c : c - Q];
+          double mt;
+          if (isf) {
+            double z2 = 0.0;
+            mt = cc[0];
+#pragma unroll
+            for (int a = 0; a < D; a++) {
+              mt += cc[1 + a] * vi[a];
+              z2 += vi[a] * vi[a];
+            }
+            mt += cc[NQ - 1] * z2;
+          } else {
+            mt = cc[NQ - 1];
+          }
+          double h = (double)hv[b];
+          if constexpr (RELAX) {
+            if (act) {
+              const double fe = eq_f(eq, vi);
+              if (isf) {
+                double fo = h - (h - fe) * itau;
+                if constexpr (PR) {
+                  double unused = 0.0;
+                  pr_add(pt, vi, fo, unused);
+                }
+                if (sa.has_force) fo += eq_f(ef, vi) - fe;
+                h = fo;
+              } else {
+                double go = h - (h - gT * fe) * itau;
+                if constexpr (PR) {
+                  double unused = 0.0;
+                  pr_add(pt, vi, unused, go);
+                }
+                if (sa.has_force) go += gT * (eq_f(ef, vi) - fe);
+                h = go;
+              }
+            }
+          }
+          pop[(size_t)c * N + k] = (T)(h + vi[7] * (rk * (double)S.Y[node * (NOUTP + 1) + c] - mt));
+        }
       }
     }
-  }
   }
 }
 
@@ -453,6 +697,28 @@ __global__ void k_refresh_bf16(MlpArgs m, uint16_t *wbf) {
   wbf[e] = f2bf(v);
 }
 
+// the same BF16 weights transposed: layer blocks at the same offsets, [out][in] (inputs
+// padded to KIN, outputs of the last layer to NOUTP)
+__global__ void k_refresh_bf16t(MlpArgs m, uint16_t *wbt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= WBF_N) return;
+  float v = 0.f;
+  if (e < WBF_W2) {
+    int o = e / KIN, i = e % KIN;
+    if (i < m.n_in) v = m.theta[m.off[0] + i * HW + o];
+  } else if (e < WBF_W3) {
+    int q = e - WBF_W2, o = q / HW, i = q % HW;
+    v = m.theta[m.off[2] + i * HW + o];
+  } else if (e < WBF_W4) {
+    int q = e - WBF_W3, o = q / HW, i = q % HW;
+    v = m.theta[m.off[4] + i * HW + o];
+  } else {
+    int q = e - WBF_W4, o = q / HW, i = q % HW;
+    if (o < m.n_out) v = m.theta[m.off[6] + i * m.n_out + o];
+  }
+  wbt[e] = f2bf(v);
+}
+
 // ---------------------------------------------------------------- features
 struct FeatArgs {
   int D, p, nf;             // nf = D + 2 fields
@@ -592,7 +858,7 @@ struct sllbm_mlp_s {
   int64_t nparam = 0;
   int off[8] = {};
   float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
-  uint16_t *wbf = nullptr;
+  uint16_t *wbf = nullptr, *wbt = nullptr;
   float *part = nullptr;
   double *lpart = nullptr, *loss = nullptr;
   int64_t step = 0;
@@ -602,6 +868,7 @@ struct sllbm_mlp_s {
     a.n_out = n_out;
     a.theta = theta;
     a.wbf = wbf;
+    a.wbt = wbt;
     for (int k = 0; k < 8; k++) a.off[k] = off[k];
     return a;
   }
@@ -618,6 +885,8 @@ uint64_t splitmix64(uint64_t x) {
 
 int refresh(sllbm_mlp m, hipStream_t s) {
   hipLaunchKernelGGL(k_refresh_bf16, dim3((WBF_N + 255) / 256), dim3(256), 0, s, m->args(), m->wbf);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_refresh_bf16t, dim3((WBF_N + 255) / 256), dim3(256), 0, s, m->args(), m->wbt);
   HIP_TRY(hipGetLastError());
   return SLLBM_OK;
 }
@@ -751,6 +1020,21 @@ int check_pop_ptr(const void *p, const char *what) {
   return SLLBM_OK;
 }
 
+void feature_args(const sllbm_plan_s *P, FeatArgs &fa) {
+  const Mesh &m = P->mesh;
+  fa.D = m.dim;
+  fa.p = m.p;
+  fa.nf = m.dim + 2;
+  fa.N = m.n_nodes;
+  for (int a = 0; a < 3; a++) {
+    fa.Na[a] = a < m.dim ? m.N[a] : 1;
+    fa.didx[a] = a < m.dim ? P->ldidx[a] : nullptr;
+    fa.dw[a] = a < m.dim ? P->ldw[a] : nullptr;
+  }
+  fa.T0 = P->vel.T0;
+  fa.inv_sqrtT0 = 1.0 / std::sqrt(P->vel.T0);
+}
+
 int run_features(sllbm_plan_s *P, const sllbm_params *prm, const void *pop, uint16_t *feat, hipStream_t s) {
   const Mesh &m = P->mesh;
   const int64_t N = m.n_nodes;
@@ -768,17 +1052,7 @@ int run_features(sllbm_plan_s *P, const sllbm_params *prm, const void *pop, uint
   }
   HIP_TRY(hipGetLastError());
   FeatArgs fa{};
-  fa.D = m.dim;
-  fa.p = m.p;
-  fa.nf = m.dim + 2;
-  fa.N = N;
-  for (int a = 0; a < 3; a++) {
-    fa.Na[a] = a < m.dim ? m.N[a] : 1;
-    fa.didx[a] = a < m.dim ? P->ldidx[a] : nullptr;
-    fa.dw[a] = a < m.dim ? P->ldw[a] : nullptr;
-  }
-  fa.T0 = P->vel.T0;
-  fa.inv_sqrtT0 = 1.0 / std::sqrt(P->vel.T0);
+  feature_args(P, fa);
   {
     ProfScope ps(P, "k_features", s);
     hipLaunchKernelGGL(k_features, grid, dim3(256), 0, s, fa, (const double *)P->lfield, feat);
@@ -866,7 +1140,7 @@ extern "C" int sllbm_mlp_create(int n_in, int width, int depth, int n_out, uint6
   }
   auto alloc = [&](void **p, size_t b) { return m->dalloc.get(p, b) == hipSuccess; };
   if (!alloc((void **)&m->theta, o * 4) || !alloc((void **)&m->m, o * 4) || !alloc((void **)&m->v, o * 4) ||
-      !alloc((void **)&m->grad, o * 4) || !alloc((void **)&m->wbf, WBF_N * 2)) {
+      !alloc((void **)&m->grad, o * 4) || !alloc((void **)&m->wbf, WBF_N * 2) || !alloc((void **)&m->wbt, WBF_N * 2)) {
     sllbm_mlp_destroy(m);
     return fail(SLLBM_ENOMEM, "mlp_create: device allocation");
   }
@@ -882,7 +1156,7 @@ extern "C" int sllbm_mlp_create(int n_in, int width, int depth, int n_out, uint6
 extern "C" void sllbm_mlp_destroy(sllbm_mlp m) {
   if (!m) return;
   (void)hipSetDevice(m->device);
-  void *ptrs[] = {m->theta, m->m, m->v, m->grad, m->wbf, m->part, m->lpart, m->loss};
+  void *ptrs[] = {m->theta, m->m, m->v, m->grad, m->wbf, m->wbt, m->part, m->lpart, m->loss};
   for (void *p : ptrs) m->dalloc.put(p);
   delete m;
 }
@@ -932,32 +1206,91 @@ extern "C" int sllbm_mlp_forward(sllbm_mlp m, const uint16_t *x, int64_t rows, f
   return SLLBM_OK;
 }
 
-extern "C" int sllbm_mlp_correct(sllbm_plan P, const sllbm_params *prm, sllbm_mlp m, void *pop, void *stream) {
+int sllbm::learned_check(sllbm_plan_s *P, sllbm_mlp m) {
   int rc = learned_ready(P);
   if (rc) return rc;
-  if ((rc = check_params_basic(prm)) || (rc = check_pop_ptr(pop, "mlp_correct: pop"))) return rc;
-  if (!m) return fail(SLLBM_EINVAL, "mlp_correct: mlp is NULL");
+  if (!m) return fail(SLLBM_EINVAL, "learned: mlp is NULL");
   const int D = P->mesh.dim;
   if (m->n_in != (D + 2) * (D + 1) || m->n_out != 2 * P->vel.Q)
-    return fail(SLLBM_EINVAL, "mlp_correct: network is %d -> %d, the plan needs %d -> %d", m->n_in, m->n_out,
+    return fail(SLLBM_EINVAL, "learned: network is %d -> %d, the plan needs %d -> %d", m->n_in, m->n_out,
                 (D + 2) * (D + 1), 2 * P->vel.Q);
-  if (m->device != P->device) return fail(SLLBM_EINVAL, "mlp_correct: network and plan on different devices");
-  hipStream_t s = (hipStream_t)stream;
+  if (m->device != P->device) return fail(SLLBM_EINVAL, "learned: network and plan on different devices");
+  return SLLBM_OK;
+}
+
+int sllbm::launch_relax_correct(sllbm_plan_s *P, const StepArgs &a, sllbm_mlp m, void *pop, hipStream_t s) {
+  const int64_t N = P->mesh.n_nodes;
+  const dim3 grid1((unsigned)((N + 255) / 256));
+  {
+    ProfScope ps(P, "k_step_fields", s);
+    if (P->prec == SLLBM_F32)
+      hipLaunchKernelGGL(k_step_fields<float>, grid1, dim3(256), 0, s, P->tp, a, (const double *)P->nstate,
+                         (const float *)pop, P->lfield);
+    else
+      hipLaunchKernelGGL(k_step_fields<double>, grid1, dim3(256), 0, s, P->tp, a, (const double *)P->nstate,
+                         (const double *)pop, P->lfield);
+  }
+  HIP_TRY(hipGetLastError());
+  FeatArgs fa{};
+  feature_args(P, fa);
+  {
+    ProfScope ps(P, "k_features", s);
+    hipLaunchKernelGGL(k_features, grid1, dim3(256), 0, s, fa, (const double *)P->lfield, P->lfeat);
+  }
+  HIP_TRY(hipGetLastError());
+  ProjArgs pa{};
+  int rc = proj_args(P, pa);
+  if (rc) return rc;
+  pa.vel = P->tp.vel;
+  const dim3 grid((unsigned)std::min<int64_t>((N + RC - 1) / RC, kCorrectGrid));
+  {
+    ProfScope ps(P, "k_relax_correct", s);
+#define RC_LAUNCH(TT, PRV)                                                                                     \
+  hipLaunchKernelGGL((k_correct<TT, 1, PRV, 3>), grid, dim3(NTC), 0, s, m->args(), pa, P->tp, a, N,             \
+                     (const uint16_t *)P->lfeat, (const double *)P->lfield, (const double *)P->nstate, (TT *)pop)
+    if (P->prec == SLLBM_F32) {
+      if (a.pr_on) RC_LAUNCH(float, 1);
+      else RC_LAUNCH(float, 0);
+    } else {
+      if (a.pr_on) RC_LAUNCH(double, 1);
+      else RC_LAUNCH(double, 0);
+    }
+#undef RC_LAUNCH
+  }
+  HIP_TRY(hipGetLastError());
+  return SLLBM_OK;
+}
+
+extern "C" int sllbm_mlp_correct(sllbm_plan P, const sllbm_params *prm, sllbm_mlp m, void *pop, void *stream) {
+  int rc = learned_check(P, m);
+  if (rc) return rc;
+  if ((rc = check_params_basic(prm)) || (rc = check_pop_ptr(pop, "mlp_correct: pop"))) return rc;
+  return launch_mlp_correct(P, prm, m, pop, (hipStream_t)stream);
+}
+
+int sllbm::launch_mlp_correct(sllbm_plan_s *P, const sllbm_params *prm, sllbm_mlp m, void *pop, hipStream_t s) {
+  int rc;
   if ((rc = run_features(P, prm, pop, P->lfeat, s))) return rc;
   ProjArgs pa{};
   if ((rc = proj_args(P, pa))) return rc;
   pa.vel = P->tp.vel;
   const int64_t N = P->mesh.n_nodes;
   // a persistent grid: each workgroup stages the weights once and walks several tiles
-  dim3 grid((unsigned)std::min<int64_t>((N + R - 1) / R, kCorrectGrid));
+  dim3 grid((unsigned)std::min<int64_t>((N + RC - 1) / RC, kCorrectGrid));
+  const StepArgs none{};
   {
     ProfScope ps(P, "k_mlp_correct", s);
-    if (P->prec == SLLBM_F32)
-      hipLaunchKernelGGL(k_mlp_correct<float>, grid, dim3(NT), 0, s, m->args(), pa, (const uint16_t *)P->lfeat,
-                         (const double *)P->lfield, N, (float *)pop);
-    else
-      hipLaunchKernelGGL(k_mlp_correct<double>, grid, dim3(NT), 0, s, m->args(), pa, (const uint16_t *)P->lfeat,
-                         (const double *)P->lfield, N, (double *)pop);
+#define MC_LAUNCH(TT, DD)                                                                                      \
+  hipLaunchKernelGGL((k_correct<TT, 0, 0, DD>), grid, dim3(NTC), 0, s, m->args(), pa, P->tp, none, N,           \
+                     (const uint16_t *)P->lfeat, (const double *)P->lfield, (const double *)nullptr, (TT *)pop)
+    if (P->prec == SLLBM_F32) {
+      if (P->mesh.dim == 2) MC_LAUNCH(float, 2);
+      else MC_LAUNCH(float, 3);
+    } else {
+      if (P->mesh.dim == 2) MC_LAUNCH(double, 2);
+      else MC_LAUNCH(double, 3);
+    }
+#undef MC_LAUNCH
   }
   HIP_TRY(hipGetLastError());
   return SLLBM_OK;

@@ -881,7 +881,7 @@ void launch_tile2d_single(const DevTensorPlan &tp, const StepArgs &a, const Tile
 }
 
 template <typename T, int D, int P, int CX, int CY, int CZ>
-int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
+int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s, bool relax) {
   constexpr int BS = D == 3 ? 512 : 256;   // threads per workgroup
   // 3D schedule: the skewed two-barrier one except at p = 3 in FP64, where its separate
   // y buffer takes the 12 x 12 x 6 tile to 95 KB of LDS and one workgroup per CU.  Tile
@@ -932,6 +932,7 @@ int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *po
       hipLaunchKernelGGL((k_step_tile2d<T, D, P, CX, CY, CZ, BS, WPE, 0, 0, kTileTabs>), dim3(ntiles), dim3(BS), 0, s,
                          tp, a, tg, (const T *)pin, (T *)pout, Pl->nstate);
   }
+  if (!relax) return SLLBM_OK;   // the caller relaxes the stored streamed values itself
   {
     ProfScope ps(Pl, "k_relax_nodes", s);
     // FP64 with even N (rows keep 2-node groups aligned): 16-byte vector accesses, 4 % faster;
@@ -960,14 +961,14 @@ int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *po
 }
 }  // namespace
 
-int launch_step_tile(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
+int launch_step_tile(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s, bool relax) {
   int D = Pl->mesh.dim, p = Pl->mesh.p;
   bool f32 = Pl->prec == SLLBM_F32;
 #define TCASE(DD, PP)                                                                                  \
   if (D == DD && p == PP) {                                                                            \
     constexpr int CX = TileShape<DD, PP>::CX, CY = TileShape<DD, PP>::CY, CZ = TileShape<DD, PP>::CZ; \
-    return f32 ? launch_tile_t<float, DD, PP, CX, CY, CZ>(Pl, a, pin, pout, s)                          \
-               : launch_tile_t<double, DD, PP, CX, CY, CZ>(Pl, a, pin, pout, s);                        \
+    return f32 ? launch_tile_t<float, DD, PP, CX, CY, CZ>(Pl, a, pin, pout, s, relax)                   \
+               : launch_tile_t<double, DD, PP, CX, CY, CZ>(Pl, a, pin, pout, s, relax);                 \
   }
   TCASE(2, 2) TCASE(2, 3) TCASE(2, 4) TCASE(3, 2) TCASE(3, 3) TCASE(3, 4)
 #undef TCASE
