@@ -298,7 +298,8 @@ int sllbm_mlp_num_params(sllbm_mlp m, int64_t *n);
 int sllbm_mlp_get_params(sllbm_mlp m, float *host);
 int sllbm_mlp_set_params(sllbm_mlp m, const float *host);
 
-/* Node features of a population field (see above) into feat_bf16 (device, [N][n_feat]). */
+/* Node features of a population field (see above) into feat_bf16 (device, [N][n_feat],
+ * 8-byte aligned: SLLBM_EINVAL otherwise). */
 int sllbm_features(sllbm_plan p, const sllbm_params *prm, const void *pop, uint16_t *feat_bf16, void *stream);
 /* y = network(x) for `rows` rows of BF16 inputs [rows][n_in] (device); y device FP32
  * [rows][n_out]. */

@@ -1,10 +1,11 @@
 // Learned post-collision correction on tensor-product meshes (gfx950).
 //
 // Node features (moments and their interpolant gradients), the network's forward pass on
-// BF16 MFMA (v_mfma_f32_16x16x16_bf16, FP32 accumulation), the projected correction added
-// in place, one-step training targets, restriction by injection, and training: a fused
-// forward / loss / backward kernel per 32-row tile whose weight gradients are again MFMA
-// products, written as per-workgroup partials and summed in a fixed order, then Adam on
+// BF16 MFMA with FP32 accumulation, the projected correction added in place (one network per
+// wave on v_mfma_f32_16x16x32_bf16, optionally fused with the relaxation of a tiled step),
+// one-step training targets, restriction by injection, and training: a fused forward / loss /
+// backward kernel per 32-row tile (v_mfma_f32_16x16x16_bf16) whose weight gradients are again
+// MFMA products, written as per-workgroup partials and summed in a fixed order, then Adam on
 // the FP32 master weights.
 #include <hip/hip_runtime.h>
 
@@ -39,7 +40,7 @@ constexpr int WBF_W1 = 0, WBF_W2 = KIN * HW, WBF_W3 = KIN * HW + HW * HW, WBF_W4
 constexpr int WBF_N = KIN * HW + 2 * HW * HW + HW * NOUTP;
 constexpr int kMaxPartialBlocks = 512;
 // The correction kernels' LDS (about 76 KB) admits two workgroups per compute unit: a grid of
-// two per CU stages the weights twice per CU and walks the tiles from there.
+// two per CU stages the weights twice per CU and walks the node groups from there.
 constexpr int64_t kCorrectGrid = 512;
 
 __host__ __device__ inline uint16_t f2bf(float f) {
@@ -107,7 +108,7 @@ struct MlpArgs {
   int n_in, n_out;
   const float *theta;     // master weights (biases read from here)
   const uint16_t *wbf;    // padded BF16 weights, each layer [in][out]
-  const uint16_t *wbt;    // the same transposed, each layer [out][in] (the correction kernels)
+  const uint16_t *wbt;    // the correction kernels' stored layout (k_refresh_corr)
   int off[8];
 };
 
@@ -245,278 +246,347 @@ __global__ void k_step_fields(const DevTensorPlan pl, const StepArgs sa, const d
   fld[4 * (size_t)N + k] = Tk;
 }
 
-// The correction kernels: a persistent grid of 256-thread workgroups (4 waves), two per
-// compute unit as their LDS allows (so that one workgroup's network runs while the other's
-// population pass waits on memory), each walking 32-node tiles.  Per workgroup the hidden
-// layers' transposed BF16 weights, the biases and the velocity constants are staged once;
-// the output layer's weights (up to 32 KB) are read from the L1/L2-resident global copy.  Per
-// tile: the network on the 32 nodes' features (16x16x16 BF16 MFMA tiles, operands read 4
-// values at a time: the activations row-major, the weights transposed), the invariant sums
-// of the scaled outputs, then one pass over the tile's populations, one node per lane and
-// several populations in flight per lane.
-constexpr int RC = 32;       // nodes per tile
-constexpr int NTC = 256;     // threads per workgroup
-constexpr int UB = 8;        // populations per lane in flight in the population pass
-constexpr int WH_N = KIN * HW + 2 * HW * HW;   // hidden layers' weights
+// The correction kernels run one independent network per wave, 16 nodes at a time, on
+// v_mfma_f32_16x16x32_bf16 with the layers evaluated transposed (D = W^T H^T, nodes as
+// columns).  Lane l (r = l % 16, g = l / 16) supplies A[r][k(g, j)] and B[k(g, j)][r] for
+// j < 8 and receives D[4 g + j][r] for j < 4, so after a layer it holds units 16 t + 4 g + j
+// of node r for each 16-unit tile t.  Those eight values of tiles 2 b and 2 b + 1 are its B
+// operand of the next layer's 32-deep K block b once the next layer's weight columns are
+// stored in the matching order (hid_unit_of_col): activations never leave registers.  The
+// output layer's rows are ordered so that a lane's four outputs of tile t are f and g of the
+// velocities 8 t + 2 g and 8 t + 2 g + 1 (out_of_row), so that the population pass updates
+// both populations of a velocity from one equilibrium evaluation.  The output layer runs
+// twice, for the projection's invariant sums and again in the population pass (two MFMAs a
+// tile, cheaper than holding 2Q outputs per node).  The weights (rows padded by 16 B against
+// LDS bank conflicts), biases and velocity constants are staged once per workgroup; the waves
+// then run without barriers.
+// 8 waves per workgroup, two workgroups per CU (4 waves per SIMD, at most 128 VGPRs; the
+// variants with both the Prandtl-number term and forcing spill a few registers, still faster
+// than 6 waves without spills).  Population loads run PD tiles ahead of the tile computed.
+// 64^3 cells p = 2 (2.1M nodes), FP32, per launch: correction alone 1.31 ms (D3V125) and
+// 0.55 ms (D3Q45); fused with the relaxation 1.38 ms (D3V125), 0.65 / 0.99 ms (D3Q45 at
+// Pr 1 / 0.71); 6 waves: 1.44, 0.73, 1.77 ms; one tile ahead: within 5 %.
+constexpr int NTC = 512;
+constexpr int PD = 2;
+constexpr int KP1 = KIN + 8, KPH = HW + 8;    // LDS row strides (bf16) of layer 1 and of layers 2-4
+constexpr int WC_W2 = HW * KP1, WC_W3 = WC_W2 + HW * KPH, WC_W4 = WC_W3 + HW * KPH;
+constexpr int WC_N = WC_W4 + NOUTP * KPH;
 
-// D += A B over K, A (16 x K) row-major with leading dimension lda, B given transposed
-// (Bt: 16 x K, row n holds column n of B); lane l reads A[l%16][k0+4(l/16) .. +3] and
-// Bt[l%16][k0+4(l/16) .. +3] as single 8-byte loads (v_mfma_f32_16x16x16_bf16 layout), all
-// k-steps' operands before the products.
-template <int K>
-__device__ inline float4_t mma_abt4(const uint16_t *A, int lda, const uint16_t *Bt, int ldb, float4_t acc) {
-  const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
-  short4_t a[K / 16], b[K / 16];
-#pragma unroll
-  for (int q = 0; q < K / 16; q++) {
-    a[q] = *(const short4_t *)(A + r * lda + 16 * q + 4 * g);
-    b[q] = *(const short4_t *)(Bt + r * ldb + 16 * q + 4 * g);
-  }
-#pragma unroll
-  for (int q = 0; q < K / 16; q++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[q], b[q], acc, 0, 0, 0);
-  return acc;
+// hidden unit held in stored column c (c = 32 b + 8 g + j) of a layer fed by a hidden layer
+__host__ __device__ inline int hid_unit_of_col(int c) {
+  const int b = c >> 5, g = (c >> 3) & 3, j = c & 7;
+  return 32 * b + 16 * (j >> 2) + 4 * g + (j & 3);
+}
+// network output of the output layer's row R = 16 t + 4 g + j for Q velocities (f_v: v,
+// g_v: Q + v), -1 for a padding row
+__host__ __device__ inline int out_of_row(int R, int Q) {
+  const int t = R >> 4, g = (R >> 2) & 3, j = R & 3;
+  const int v = 8 * t + 2 * g + (j & 1);
+  if (v >= Q) return -1;
+  return (j >> 1) ? Q + v : v;
 }
 
-// tanh from one exponential: tanh x = sign(x) (1 - e) / (1 + e), e = exp(-2 |x|) (FP32; the
-// result is rounded to BF16 next)
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline float4_t mfma32(u32x4_t a, u32x4_t b, float4_t acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                 acc, 0, 0, 0);
+}
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
+// two values rounded to BF16 (nearest even, as f2bf) and packed, low half first
+__device__ inline uint32_t pack_bf(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(float2_t{a, b}, bf16x2_t));
+}
+// An offset of zero the compiler cannot see through: LDS reads indexed with it are not hoisted
+// out of the node-group loop or merged across its passes (the staged weights would otherwise
+// be held in registers, well beyond the register budget, and spilled).
+__device__ inline int opaque_zero() {
+  int z = 0;
+  asm volatile("" : "+v"(z));
+  return z;
+}
+
+// Population access of the correction kernels through buffer resources: the base (eight
+// population planes from a wave-uniform plane) stays in scalar registers, each lane supplies
+// a 32-bit byte offset, and an offset past the range (kOutOfRange) reads 0 and drops a store.
+// Lanes without a population thus need no branch: loads under divergent branches would make
+// the compiler wait for every load in flight before the next use, voiding the prefetch.
+constexpr int kOutOfRange = 0x7ffffff0;
+template <typename T>
+__device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(T *pop, int64_t plane0, int64_t N) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(pop + plane0 * N), (short)0, (int)(8 * N * (int64_t)sizeof(T)),
+                                           0x00020000);
+}
+template <typename T> struct PopBuf;
+template <> struct PopBuf<float> {
+  __device__ static float load(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  }
+  __device__ static void store(__amdgpu_buffer_rsrc_t r, int off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+  }
+};
+template <> struct PopBuf<double> {
+  typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+  __device__ static double load(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+  __device__ static void store(__amdgpu_buffer_rsrc_t r, int off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, 0);
+  }
+};
+
+// tanh in FP32 for the correction kernels (the result is rounded to BF16 next): for |x| >=
+// 1/8, sign(x) (1 - e) / (1 + e) with e = exp(-2 |x|) from the hardware exp2 and reciprocal
+// (a few ulp); below, where 1 - e loses digits, the Taylor series to x^7 (truncation under
+// 2e-10 relative at 1/8).
 __device__ inline float tanh_fast(float x) {
-  const float e = __expf(-2.f * fabsf(x));
-  return copysignf((1.f - e) / (1.f + e), x);
+  const float ax = fabsf(x);
+  const float e = __builtin_amdgcn_exp2f(-2.8853900817779268f * ax);   // 2 log2(e)
+  const float big = (1.f - e) * __builtin_amdgcn_rcpf(1.f + e);
+  const float x2 = x * x;
+  const float small = ax * (1.f + x2 * (-1.f / 3.f + x2 * (2.f / 15.f + x2 * (-17.f / 315.f))));
+  return copysignf(ax < 0.125f ? small : big, x);
+}
+
+// One tanh layer of 64 units: in[b] the B operands of the KB 32-deep K blocks, Wl the stored
+// weights (row = unit, stride ld), out the B operands of the next layer.
+template <int KB>
+__device__ inline void corr_hidden(const uint16_t *Wl, int ld, const float *bias, const u32x4_t (&in)[KB],
+                                   u32x4_t (&out)[2], int r, int g) {
+#pragma unroll
+  for (int t = 0; t < 4; t++) {
+    float4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < KB; b++) acc = mfma32(*(const u32x4_t *)(Wl + (16 * t + r) * ld + 32 * b + 8 * g), in[b], acc);
+    const float4_t bb = *(const float4_t *)(bias + 16 * t + 4 * g);
+    out[t >> 1][2 * (t & 1)] = pack_bf(tanh_fast(acc[0] + bb[0]), tanh_fast(acc[1] + bb[1]));
+    out[t >> 1][2 * (t & 1) + 1] = pack_bf(tanh_fast(acc[2] + bb[2]), tanh_fast(acc[3] + bb[3]));
+  }
+}
+
+// output tile t: this lane's rows 16 t + 4 g + j (f, f, g, g of velocities 8 t + 2 g + 0, 1)
+__device__ inline float4_t corr_out(const uint16_t *W4, const float *b4, const u32x4_t (&h)[2], int t, int r, int g) {
+  float4_t acc = {0.f, 0.f, 0.f, 0.f};
+  acc = mfma32(*(const u32x4_t *)(W4 + (16 * t + r) * KPH + 8 * g), h[0], acc);
+  acc = mfma32(*(const u32x4_t *)(W4 + (16 * t + r) * KPH + 32 + 8 * g), h[1], acc);
+  const float4_t bb = *(const float4_t *)(b4 + 16 * t + 4 * g);
+  return float4_t{acc[0] + bb[0], acc[1] + bb[1], acc[2] + bb[2], acc[3] + bb[3]};
 }
 
 struct CorrShared {
-  uint16_t W[WH_N];                       // hidden layers' transposed weights
-  float B[3 * HW + NOUTP];                // biases
-  union {
-    struct {
-      uint16_t X[RC * KIN];
-      uint16_t H[2][RC * HW];
-    } a;
-    double hq[2 * NTC / 64][RC][6];       // heat-flux partials of the half-waves (Pr != 1)
-  } u;
-  float Y[RC * (NOUTP + 1)];              // rows padded to an odd stride (bank-conflict free
-                                          // column reads)
-  double C[RC * 5];
-  double V[kMaxQ][8];                     // velocity constants: zeta, xi, |xi|^2, w
+  uint16_t W[WC_N] __attribute__((aligned(16)));   // stored weights, layers 1-4
+  float B[3 * HW + NOUTP] __attribute__((aligned(16)));   // biases (output layer in row order)
+  double V[kMaxQ][8];                              // zeta, xi, |xi|^2, w
+  double PW[kMaxQ][6];                             // w zeta, w |zeta|^2, |zeta|^2 (zeta: D components)
 };
 
 // RELAX = 0: the correction alone, in place on post-collision populations (fld: the node
 // fields of those populations).  RELAX = 1: the relaxation of a 3D tile step fused with the
 // correction: the tile's nodes hold their stored streamed values and node state (nstate) and
 // are relaxed (BGK against the equilibrium of their node state, the Prandtl-number term when
-// PR = 1, Kupershtokh forcing) exactly as the relaxation launch does, then corrected;
-// boundary-layer nodes arrive relaxed by the gather launch and are only corrected.
-template <typename T, int RELAX, int PR, int D>
-__global__ void __launch_bounds__(NTC, 2) k_correct(MlpArgs m, ProjArgs pa, const DevTensorPlan pl,
+// PR = 1, Kupershtokh forcing when FORCE = 1) exactly as the relaxation launch does, then
+// corrected; boundary-layer nodes arrive relaxed by the gather launch and are only corrected.
+template <typename T, int RELAX, int PR, int FORCE, int D>
+__global__ void __launch_bounds__(NTC, 4) k_correct(MlpArgs m, ProjArgs pa, const DevTensorPlan pl,
                                                     const StepArgs sa, int64_t N, const uint16_t *feat,
                                                     const double *fld, const double *nstate, T *pop) {
   __shared__ CorrShared S;
   constexpr int NQ = D + 2;
-  const int Q = pa.Q, Q2 = 2 * Q;
-  {  // hidden weights, biases and velocity constants, once per workgroup
-    const uint32_t *src = (const uint32_t *)m.wbt;
-    uint32_t *dst = (uint32_t *)S.W;
-    for (int e = threadIdx.x; e < WH_N / 2; e += NTC) dst[e] = src[e];
+  const int Q = pa.Q;
+  const int ntile = (Q + 7) / 8;   // output tiles, 8 velocities (16 outputs) each
+  {  // weights (the output layer's used rows only), biases and velocity constants
+    const int nw = (WC_W4 + 16 * ntile * KPH) / 8;
+    const u32x4_t *src = (const u32x4_t *)m.wbt;
+    u32x4_t *dst = (u32x4_t *)S.W;
+    for (int e = threadIdx.x; e < nw; e += NTC) dst[e] = src[e];
     for (int e = threadIdx.x; e < 3 * HW + NOUTP; e += NTC) {
       const int layer = e < 3 * HW ? e / HW : 3, c = e - layer * HW;
-      S.B[e] = (layer < 3 || c < m.n_out) ? m.theta[m.off[2 * layer + 1] + c] : 0.f;
+      const int o = layer < 3 ? c : out_of_row(c, Q);
+      S.B[e] = o >= 0 ? m.theta[m.off[2 * layer + 1] + o] : 0.f;
     }
     for (int e = threadIdx.x; e < Q * 8; e += NTC) S.V[e >> 3][e & 7] = pa.vel[e];
+    for (int v = threadIdx.x; v < Q; v += NTC) {
+      const double *z = pa.vel + 8 * v, w = z[7];
+      double z2 = 0.0;
+      for (int a = 0; a < D; a++) z2 += z[a] * z[a];
+      for (int a = 0; a < 3; a++) S.PW[v][a] = a < D ? w * z[a] : 0.0;
+      S.PW[v][3] = w * z2;
+      S.PW[v][4] = z2;
+      S.PW[v][5] = 0.0;
+    }
   }
-  const uint16_t *W4t = m.wbt + WBF_W4;   // output layer, transposed [NOUTP][HW], global
+  __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-  const int nct = (m.n_out + 15) / 16;    // output column tiles
-  // population passes: node `node` of the tile, half-wave `hw` of 8 (one population each)
-  const int node = lane & (RC - 1), hw = 2 * wave + (lane >> 5);
-  const int64_t ntiles = (N + RC - 1) / RC;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t row0 = tile * RC;
-    const int64_t k = row0 + node;
+  const uint16_t *W4 = S.W + WC_W4;
+  const float *b4 = S.B + 3 * HW;
+  const bool vec_feat = (m.n_in & 3) == 0;
+  const int64_t ngroups = (N + 15) / 16, nwaves = (int64_t)gridDim.x * (NTC / 64);
+  // features 8 g .. 8 g + 7 of node kk (zero past N)
+  auto load_x = [&](int64_t kk) {
+    u32x4_t x = {0u, 0u, 0u, 0u};
+    if (vec_feat) {   // branch-free: out-of-range lanes read row 0 and drop it
+      const uint16_t *fr = feat + (kk < N ? kk : 0) * m.n_in;
+#pragma unroll
+      for (int q = 0; q < 2; q++) {
+        const int c0 = 8 * g + 4 * q;
+        const bool ok = kk < N && c0 + 4 <= m.n_in;
+        const uint2 v = *(const uint2 *)(fr + (ok ? c0 : 0));
+        x[2 * q] = ok ? v.x : 0u;
+        x[2 * q + 1] = ok ? v.y : 0u;
+      }
+    } else if (kk < N) {
+      const uint16_t *fr = feat + kk * m.n_in;
+      for (int c = 8 * g; c < 8 * g + 8 && c < m.n_in; c++)
+        x[(c - 8 * g) >> 1] |= (uint32_t)fr[c] << (16 * ((c - 8 * g) & 1));
+    }
+    return x;
+  };
+  for (int64_t grp = (int64_t)blockIdx.x * (NTC / 64) + wave; grp < ngroups; grp += nwaves) {
+    const int64_t k = grp * 16 + r;
     const bool valid = k < N;
-    // ---- relaxation coefficients of this lane's node
+    const int z1 = opaque_zero();
+    // ---- network: three tanh layers on the node's features
+    u32x4_t h[2];
+    {
+      u32x4_t x1[1] = {load_x(k)}, h1[2];
+      corr_hidden<1>(S.W + z1, KP1, S.B + z1, x1, h1, r, g);
+      corr_hidden<2>(S.W + z1 + WC_W2, KPH, S.B + z1 + HW, h1, h, r, g);
+      corr_hidden<2>(S.W + z1 + WC_W3, KPH, S.B + z1 + 2 * HW, h, h1, r, g);
+      h[0] = h1[0];
+      h[1] = h1[1];
+    }
+    const double rk = valid ? fld[k] : 0.0;
+    // ---- relaxation coefficients of node k
     bool act = false;
     EqNode eq{}, ef{};
-    double itau = 0.0, gT = 0.0;
+    double itau = 0.0, gT = 0.0, uk[3] = {0.0, 0.0, 0.0};
     if constexpr (RELAX) {
       if (valid && sa.relax_mode != 2 && !in_layer(pl, k)) {
         act = true;
-        const double rho = nstate[k], u0 = nstate[N + k], u1 = nstate[2 * N + k], u2 = nstate[3 * N + k];
-        const double Tn = nstate[4 * N + k];
+        const double rho = nstate[k], Tn = nstate[4 * N + k];
+        uk[0] = nstate[N + k];
+        uk[1] = nstate[2 * N + k];
+        uk[2] = nstate[3 * N + k];
         itau = nstate[5 * N + k];
-        eq = eq_prepare(rho, u0, u1, u2, Tn, sa, D);
-        ef = sa.has_force ? eq_forced(rho, u0, u1, u2, Tn, sa, D) : eq;
+        eq = eq_prepare(rho, uk[0], uk[1], uk[2], Tn, sa, D);
+        if constexpr (FORCE) ef = eq_forced(rho, uk[0], uk[1], uk[2], Tn, sa, D);
         gT = Tn * sa.gbase;
       }
     }
-    __syncthreads();   // the previous tile's passes are done with every buffer
+    // byte offset of velocity 8 t + 2 g + e (e < 2) of node k in the planes of tile t, or
+    // out of range for a lane without that population
+    auto pop_off = [&](int t, int e) {
+      const int v = 8 * t + 2 * g + e;
+      int off = (valid && v < Q) ? (int)(((int64_t)(2 * g + e) * N + k) * (int64_t)sizeof(T)) : kOutOfRange;
+      asm volatile("" : "+v"(off));   // one offset in a register: keeps the access out of branches
+      return off;
+    };
+    auto load_tile = [&](int t, T (&d)[4]) {
+      const __amdgpu_buffer_rsrc_t rf = plane_rsrc(pop, 8 * t, N), rg = plane_rsrc(pop, Q + 8 * t, N);
+#pragma unroll
+      for (int e = 0; e < 2; e++) {
+        const int off = pop_off(t, e);
+        d[e] = PopBuf<T>::load(rf, off);
+        d[2 + e] = PopBuf<T>::load(rg, off);
+      }
+    };
+    T B[PD + 1][4];
+    // ---- pass 1: invariant sums of w y over this lane's outputs (and the heat flux of the
+    // streamed values when PR = 1), then over the node's four lanes
+    double sm[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; q++) sm[q] = 0.0;
+    HeatFlux hq = {0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+    for (int t = 0; t < ntile; t++) {
+      const float4_t y = corr_out(W4 + z1, b4 + z1, h, t, r, g);
+#pragma unroll
+      for (int e = 0; e < 2; e++) {
+        const bool has = 8 * t + 2 * g + e < Q;        // lanes past Q add zeros
+        const int v = min(8 * t + 2 * g + e, Q - 1);
+        const double *pw = S.PW[v] + z1;
+        const double w = S.V[v][7 + z1], yf = has ? (double)y[e] : 0.0, yg = has ? (double)y[2 + e] : 0.0;
+        sm[0] += w * yf;
+#pragma unroll
+        for (int a = 0; a < D; a++) sm[1 + a] += pw[a] * yf;
+        sm[NQ - 1] += pw[3] * yf + w * yg;
+        if constexpr (RELAX && PR) {
+          const int off = act ? pop_off(t, e) : kOutOfRange;
+          const double f = (double)PopBuf<T>::load(plane_rsrc(pop, 8 * t, N), off);
+          const double gv = (double)PopBuf<T>::load(plane_rsrc(pop, Q + 8 * t, N), off);
+          heat_flux_add(hq, S.V[v] + z1, uk[0], uk[1], uk[2], f, gv);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+      sm[q] += __shfl_xor(sm[q], 16);
+      sm[q] += __shfl_xor(sm[q], 32);
+    }
+    double cc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+      double v = 0.0;
+#pragma unroll
+      for (int q2 = 0; q2 < NQ; q2++) v += pa.G[q * NQ + q2] * (rk * sm[q2]);
+      cc[q] = v;
+    }
     PrTerm pt{};
-    if constexpr (RELAX && PR) {  // Pr != 1: heat flux of the streamed values over the half-waves
-      HeatFlux h = {0, 0, 0, 0, 0, 0};
-      if (act) {
-        const double u0 = nstate[N + k], u1 = nstate[2 * N + k], u2 = nstate[3 * N + k];
-        for (int i = hw; i < Q; i += 2 * NTC / 64)
-          heat_flux_add(h, S.V[i], u0, u1, u2, (double)pop[(size_t)i * N + k], (double)pop[((size_t)Q + i) * N + k]);
-      }
-      double *hp = S.u.hq[hw][node];
-      hp[0] = h.f0;
-      hp[1] = h.f1;
-      hp[2] = h.f2;
-      hp[3] = h.g0;
-      hp[4] = h.g1;
-      hp[5] = h.g2;
-      __syncthreads();
-      double t[6] = {0, 0, 0, 0, 0, 0};
-      for (int w = 0; w < 2 * NTC / 64; w++)
+    if constexpr (RELAX && PR) {
+      double hv[6] = {hq.f0, hq.f1, hq.f2, hq.g0, hq.g1, hq.g2};
 #pragma unroll
-        for (int q = 0; q < 6; q++) t[q] += S.u.hq[w][node][q];
-      if (act) pt = pr_term(HeatFlux{t[0], t[1], t[2], t[3], t[4], t[5]}, itau, sa, D);
-      __syncthreads();   // the partials share their space with X and H
+      for (int q = 0; q < 6; q++) {
+        hv[q] += __shfl_xor(hv[q], 16);
+        hv[q] += __shfl_xor(hv[q], 32);
+      }
+      pt = pr_term(HeatFlux{hv[0], hv[1], hv[2], hv[3], hv[4], hv[5]}, itau, sa, D);
     }
-    // ---- network: features -> three tanh layers -> outputs
-    for (int e = threadIdx.x; e < RC * KIN; e += NTC) {
-      const int rr = e / KIN, c = e % KIN;
-      const int64_t gr = row0 + rr;
-      S.u.a.X[e] = (gr < N && c < m.n_in) ? feat[gr * m.n_in + c] : (uint16_t)0;
-    }
-    __syncthreads();
-    for (int layer = 0; layer < 3; layer++) {
-      const uint16_t *in = layer == 0 ? S.u.a.X : S.u.a.H[(layer - 1) & 1];
-      uint16_t *out = S.u.a.H[layer & 1];
-      const uint16_t *Wt = S.W + (layer == 0 ? WBF_W1 : (layer == 1 ? WBF_W2 : WBF_W3));
-      const float *b = S.B + layer * HW;
-      // 8 output tiles of 16 x 16 over 4 waves: two each, their products issued together
-      float4_t acc[2];
+    const int z2 = opaque_zero();
+    // ---- pass 2: pop = relax(pop) + w (rho y - M^T c) for this lane's velocities, the next
+    // tile's four populations in flight while the current one is computed.  Every lane stays
+    // in the loop (the MFMAs take their operands from the whole wave); loads and stores are
+    // guarded per lane.
 #pragma unroll
-      for (int h = 0; h < 2; h++) {
-        const int t = wave + 4 * h, rt = t & 1, ct = t >> 1;
-        acc[h] = float4_t{0.f, 0.f, 0.f, 0.f};
-        if (layer == 0) acc[h] = mma_abt4<KIN>(in + rt * 16 * KIN, KIN, Wt + ct * 16 * KIN, KIN, acc[h]);
-        else acc[h] = mma_abt4<HW>(in + rt * 16 * HW, HW, Wt + ct * 16 * HW, HW, acc[h]);
-      }
+    for (int p = 0; p < PD; p++) load_tile(p, B[p]);
+#pragma unroll 1
+    for (int t = 0; t < ntile; t++) {
+      load_tile(t + PD, B[PD]);
+      const float4_t y = corr_out(W4 + z2, b4 + z2, h, t, r, g);
+      const __amdgpu_buffer_rsrc_t rf = plane_rsrc(pop, 8 * t, N), rg = plane_rsrc(pop, Q + 8 * t, N);
 #pragma unroll
-      for (int h = 0; h < 2; h++) {
-        const int t = wave + 4 * h, rt = t & 1, ct = t >> 1;
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-          const int row = rt * 16 + 4 * g + j, col = ct * 16 + r;
-          out[row * HW + col] = f2bf(tanh_fast(acc[h][j] + b[col]));
-        }
-      }
-      __syncthreads();
-    }
-    {
-      const float *b4 = S.B + 3 * HW;
-      const uint16_t *h3 = S.u.a.H[0];     // the third layer's output (layer 2 writes H[0])
-      for (int t = wave; t < 2 * nct; t += NTC / 64) {
-        const int rt = t & 1, ct = t >> 1;
-        float4_t acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mma_abt4<HW>(h3 + rt * 16 * HW, HW, W4t + ct * 16 * HW, HW, acc);
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-          const int row = rt * 16 + 4 * g + j, col = ct * 16 + r;
-          S.Y[row * (NOUTP + 1) + col] = acc[j] + b4[col];
-        }
-      }
-    }
-    __syncthreads();
-    {  // invariant sums s = M (w rho y) per node, then c = G s: 8 threads per node
-      const int row = threadIdx.x >> 3, part = threadIdx.x & 7;
-      const int64_t kr = row0 + row;
-      const double rk = kr < N ? fld[kr] : 0.0;
-      double sm[NQ];
-#pragma unroll
-      for (int q = 0; q < NQ; q++) sm[q] = 0.0;
-      for (int c = part; c < Q2; c += 8) {
-        const bool isf = c < Q;
-        const double *vi = S.V[isf ? c : c - Q];
-        const double dy = vi[7] * rk * (double)S.Y[row * (NOUTP + 1) + c];
-        if (isf) {
-          sm[0] += dy;
-          double z2 = 0.0;
-#pragma unroll
-          for (int a = 0; a < D; a++) {
-            sm[1 + a] += vi[a] * dy;
-            z2 += vi[a] * vi[a];
-          }
-          sm[NQ - 1] += z2 * dy;
-        } else {
-          sm[NQ - 1] += dy;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < NQ; q++) {
-        sm[q] += __shfl_xor(sm[q], 1);
-        sm[q] += __shfl_xor(sm[q], 2);
-        sm[q] += __shfl_xor(sm[q], 4);
-      }
-      if (part == 0)
-#pragma unroll
-        for (int q = 0; q < NQ; q++) {
-          double v = 0.0;
-#pragma unroll
-          for (int q2 = 0; q2 < NQ; q2++) v += pa.G[q * NQ + q2] * sm[q2];
-          S.C[row * 5 + q] = v;
-        }
-    }
-    __syncthreads();
-    // ---- populations: pop = relax(pop) + w rho y - w (M^T c), node `node`, c = hw + 8 n
-    if (valid) {
-      const double rk = fld[k];
-      double cc[NQ];
-#pragma unroll
-      for (int q = 0; q < NQ; q++) cc[q] = S.C[node * 5 + q];
-      for (int c0 = hw; c0 < Q2; c0 += UB * (2 * NTC / 64)) {
-        T hv[UB];
-#pragma unroll
-        for (int b = 0; b < UB; b++) {
-          const int c = c0 + b * (2 * NTC / 64);
-          if (c < Q2) hv[b] = pop[(size_t)c * N + k];
-        }
-#pragma unroll
-        for (int b = 0; b < UB; b++) {
-          const int c = c0 + b * (2 * NTC / 64);
-          if (c >= Q2) break;
-          const bool isf = c < Q;
-          const double *vi = S.V[isf ? c : c - Q];
-          double mt;
-          if (isf) {
-            double z2 = 0.0;
-            mt = cc[0];
-#pragma unroll
-            for (int a = 0; a < D; a++) {
-              mt += cc[1 + a] * vi[a];
-              z2 += vi[a] * vi[a];
-            }
-            mt += cc[NQ - 1] * z2;
-          } else {
-            mt = cc[NQ - 1];
-          }
-          double h = (double)hv[b];
-          if constexpr (RELAX) {
-            if (act) {
-              const double fe = eq_f(eq, vi);
-              if (isf) {
-                double fo = h - (h - fe) * itau;
-                if constexpr (PR) {
-                  double unused = 0.0;
-                  pr_add(pt, vi, fo, unused);
-                }
-                if (sa.has_force) fo += eq_f(ef, vi) - fe;
-                h = fo;
-              } else {
-                double go = h - (h - gT * fe) * itau;
-                if constexpr (PR) {
-                  double unused = 0.0;
-                  pr_add(pt, vi, unused, go);
-                }
-                if (sa.has_force) go += gT * (eq_f(ef, vi) - fe);
-                h = go;
-              }
+      for (int e = 0; e < 2; e++) {
+        const int v = min(8 * t + 2 * g + e, Q - 1);   // lanes past Q compute on a valid row, store nothing
+        const double *vi = S.V[v] + z2;
+        double fo = (double)B[0][e], go = (double)B[0][2 + e];
+        if constexpr (RELAX) {
+          if (act) {
+            const double fe = eq_f(eq, vi);
+            fo = fo - (fo - fe) * itau;
+            go = go - (go - gT * fe) * itau;
+            if constexpr (PR) pr_add(pt, vi, fo, go);
+            if constexpr (FORCE) {
+              const double df = eq_f(ef, vi) - fe;
+              fo += df;
+              go += gT * df;
             }
           }
-          pop[(size_t)c * N + k] = (T)(h + vi[7] * (rk * (double)S.Y[node * (NOUTP + 1) + c] - mt));
         }
+        double mt = cc[0];
+#pragma unroll
+        for (int a = 0; a < D; a++) mt += cc[1 + a] * vi[a];
+        mt += cc[NQ - 1] * S.PW[v][4 + z2];
+        const double w = vi[7];
+        const int off = pop_off(t, e);
+        PopBuf<T>::store(rf, off, (T)(fo + w * (rk * (double)y[e] - mt)));
+        PopBuf<T>::store(rg, off, (T)(go + w * (rk * (double)y[2 + e] - cc[NQ - 1])));
       }
+#pragma unroll
+      for (int p = 0; p < PD; p++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) B[p][j] = B[p + 1][j];
     }
   }
 }
@@ -697,26 +767,25 @@ __global__ void k_refresh_bf16(MlpArgs m, uint16_t *wbf) {
   wbf[e] = f2bf(v);
 }
 
-// the same BF16 weights transposed: layer blocks at the same offsets, [out][in] (inputs
-// padded to KIN, outputs of the last layer to NOUTP)
-__global__ void k_refresh_bf16t(MlpArgs m, uint16_t *wbt) {
+// the BF16 weights as the correction kernels stage them: each layer [unit][input] with rows
+// padded to KP1 / KPH, the inputs of layers 2-4 in the order hid_unit_of_col gives and the
+// output layer's rows in the order out_of_row gives
+__global__ void k_refresh_corr(MlpArgs m, uint16_t *wc) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= WBF_N) return;
+  if (e >= WC_N) return;
   float v = 0.f;
-  if (e < WBF_W2) {
-    int o = e / KIN, i = e % KIN;
+  if (e < WC_W2) {
+    const int o = e / KP1, i = e % KP1;
     if (i < m.n_in) v = m.theta[m.off[0] + i * HW + o];
-  } else if (e < WBF_W3) {
-    int q = e - WBF_W2, o = q / HW, i = q % HW;
-    v = m.theta[m.off[2] + i * HW + o];
-  } else if (e < WBF_W4) {
-    int q = e - WBF_W3, o = q / HW, i = q % HW;
-    v = m.theta[m.off[4] + i * HW + o];
+  } else if (e < WC_W4) {
+    const int L = e < WC_W3 ? 1 : 2, q = e - (L == 1 ? WC_W2 : WC_W3), o = q / KPH, c = q % KPH;
+    if (c < HW) v = m.theta[m.off[2 * L] + hid_unit_of_col(c) * HW + o];
   } else {
-    int q = e - WBF_W4, o = q / HW, i = q % HW;
-    if (o < m.n_out) v = m.theta[m.off[6] + i * m.n_out + o];
+    const int q = e - WC_W4, R = q / KPH, c = q % KPH;
+    const int o = out_of_row(R, m.n_out / 2);
+    if (c < HW && o >= 0) v = m.theta[m.off[6] + hid_unit_of_col(c) * m.n_out + o];
   }
-  wbt[e] = f2bf(v);
+  wc[e] = f2bf(v);
 }
 
 // ---------------------------------------------------------------- features
@@ -762,30 +831,48 @@ __device__ inline double scaled_field(const FeatArgs &fa, const double *fld, int
   return v * fa.inv_sqrtT0;
 }
 
+// One node per thread: the D + 2 scaled fields, then their derivatives along each axis (the
+// per-axis table rows loaded once for all fields), stored 8 bytes at a time.
+template <int D>
 __global__ void k_features(FeatArgs fa, const double *fld, uint16_t *feat) {
+  constexpr int NF = D + 2, NFEAT = NF * (1 + D);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= fa.N) return;
-  const int D = fa.D, nf = fa.nf, P1 = fa.p + 1;
-  const int nfeat = nf * (1 + D);
+  const int P1 = fa.p + 1;
   int n[3] = {0, 0, 0};
-  int64_t stride[3] = {1, fa.Na[0], (int64_t)fa.Na[0] * fa.Na[1]};
+  const int64_t stride[3] = {1, fa.Na[0], (int64_t)fa.Na[0] * fa.Na[1]};
   n[0] = (int)(k % fa.Na[0]);
   if (D > 1) n[1] = (int)((k / fa.Na[0]) % fa.Na[1]);
   if (D > 2) n[2] = (int)(k / ((int64_t)fa.Na[0] * fa.Na[1]));
-  uint16_t *out = feat + k * nfeat;
-  for (int q = 0; q < nf; q++) out[q] = f2bf((float)scaled_field(fa, fld, q, k));
-  for (int q = 0; q < nf; q++)
-    for (int a = 0; a < D; a++) {
-      double s = 0.0;
-      const int64_t base = k - (int64_t)n[a] * stride[a];
-      for (int slot = 0; slot < 2; slot++) {
-        const int32_t *id = fa.didx[a] + ((size_t)n[a] * 2 + slot) * P1;
-        const double *w = fa.dw[a] + ((size_t)n[a] * 2 + slot) * P1;
-        if (id[0] < 0) continue;
-        for (int m = 0; m < P1; m++) s += w[m] * scaled_field(fa, fld, q, base + (int64_t)id[m] * stride[a]);
+  uint16_t o[NFEAT];
+#pragma unroll
+  for (int q = 0; q < NF; q++) o[q] = f2bf((float)scaled_field(fa, fld, q, k));
+#pragma unroll
+  for (int a = 0; a < D; a++) {
+    double s[NF];
+#pragma unroll
+    for (int q = 0; q < NF; q++) s[q] = 0.0;
+    const int64_t base = k - (int64_t)n[a] * stride[a];
+    for (int slot = 0; slot < 2; slot++) {
+      const int32_t *id = fa.didx[a] + ((size_t)n[a] * 2 + slot) * P1;
+      const double *w = fa.dw[a] + ((size_t)n[a] * 2 + slot) * P1;
+      if (id[0] < 0) continue;
+      for (int mm = 0; mm < P1; mm++) {
+        const int64_t kk = base + (int64_t)id[mm] * stride[a];
+        const double wm = w[mm];
+#pragma unroll
+        for (int q = 0; q < NF; q++) s[q] += wm * scaled_field(fa, fld, q, kk);
       }
-      out[nf + q * D + a] = f2bf((float)s);
     }
+#pragma unroll
+    for (int q = 0; q < NF; q++) o[NF + q * D + a] = f2bf((float)s[q]);
+  }
+  static_assert(NFEAT % 4 == 0, "feature rows are stored 8 bytes at a time");
+  uint2 *out = (uint2 *)(feat + k * NFEAT);
+#pragma unroll
+  for (int c = 0; c < NFEAT / 4; c++)
+    out[c] = make_uint2((uint32_t)o[4 * c] | ((uint32_t)o[4 * c + 1] << 16),
+                        (uint32_t)o[4 * c + 2] | ((uint32_t)o[4 * c + 3] << 16));
 }
 
 // ---------------------------------------------------------------- targets, restriction
@@ -886,7 +973,7 @@ uint64_t splitmix64(uint64_t x) {
 int refresh(sllbm_mlp m, hipStream_t s) {
   hipLaunchKernelGGL(k_refresh_bf16, dim3((WBF_N + 255) / 256), dim3(256), 0, s, m->args(), m->wbf);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_refresh_bf16t, dim3((WBF_N + 255) / 256), dim3(256), 0, s, m->args(), m->wbt);
+  hipLaunchKernelGGL(k_refresh_corr, dim3((WC_N + 255) / 256), dim3(256), 0, s, m->args(), m->wbt);
   HIP_TRY(hipGetLastError());
   return SLLBM_OK;
 }
@@ -1055,7 +1142,8 @@ int run_features(sllbm_plan_s *P, const sllbm_params *prm, const void *pop, uint
   feature_args(P, fa);
   {
     ProfScope ps(P, "k_features", s);
-    hipLaunchKernelGGL(k_features, grid, dim3(256), 0, s, fa, (const double *)P->lfield, feat);
+    if (m.dim == 2) hipLaunchKernelGGL(k_features<2>, grid, dim3(256), 0, s, fa, (const double *)P->lfield, feat);
+    else hipLaunchKernelGGL(k_features<3>, grid, dim3(256), 0, s, fa, (const double *)P->lfield, feat);
   }
   HIP_TRY(hipGetLastError());
   return SLLBM_OK;
@@ -1140,7 +1228,7 @@ extern "C" int sllbm_mlp_create(int n_in, int width, int depth, int n_out, uint6
   }
   auto alloc = [&](void **p, size_t b) { return m->dalloc.get(p, b) == hipSuccess; };
   if (!alloc((void **)&m->theta, o * 4) || !alloc((void **)&m->m, o * 4) || !alloc((void **)&m->v, o * 4) ||
-      !alloc((void **)&m->grad, o * 4) || !alloc((void **)&m->wbf, WBF_N * 2) || !alloc((void **)&m->wbt, WBF_N * 2)) {
+      !alloc((void **)&m->grad, o * 4) || !alloc((void **)&m->wbf, WBF_N * 2) || !alloc((void **)&m->wbt, WC_N * 2)) {
     sllbm_mlp_destroy(m);
     return fail(SLLBM_ENOMEM, "mlp_create: device allocation");
   }
@@ -1194,6 +1282,7 @@ extern "C" int sllbm_features(sllbm_plan P, const sllbm_params *prm, const void 
   if (rc) return rc;
   if ((rc = check_params_basic(prm)) || (rc = check_pop_ptr(pop, "features: pop"))) return rc;
   if (!feat) return fail(SLLBM_EINVAL, "features: output is NULL");
+  if ((uintptr_t)feat % 8) return fail(SLLBM_EINVAL, "features: output must be 8-byte aligned");
   return run_features(P, prm, pop, feat, (hipStream_t)stream);
 }
 
@@ -1215,6 +1304,10 @@ int sllbm::learned_check(sllbm_plan_s *P, sllbm_mlp m) {
     return fail(SLLBM_EINVAL, "learned: network is %d -> %d, the plan needs %d -> %d", m->n_in, m->n_out,
                 (D + 2) * (D + 1), 2 * P->vel.Q);
   if (m->device != P->device) return fail(SLLBM_EINVAL, "learned: network and plan on different devices");
+  const int64_t esz = P->prec == SLLBM_F32 ? 4 : 8;
+  if (8 * P->mesh.n_nodes * esz > kOutOfRange)
+    return fail(SLLBM_EUNSUPPORTED, "learned correction: at most %lld nodes in this precision",
+                (long long)(kOutOfRange / (8 * esz)));
   return SLLBM_OK;
 }
 
@@ -1235,26 +1328,35 @@ int sllbm::launch_relax_correct(sllbm_plan_s *P, const StepArgs &a, sllbm_mlp m,
   feature_args(P, fa);
   {
     ProfScope ps(P, "k_features", s);
-    hipLaunchKernelGGL(k_features, grid1, dim3(256), 0, s, fa, (const double *)P->lfield, P->lfeat);
+    hipLaunchKernelGGL(k_features<3>, grid1, dim3(256), 0, s, fa, (const double *)P->lfield, P->lfeat);
   }
   HIP_TRY(hipGetLastError());
   ProjArgs pa{};
   int rc = proj_args(P, pa);
   if (rc) return rc;
   pa.vel = P->tp.vel;
-  const dim3 grid((unsigned)std::min<int64_t>((N + RC - 1) / RC, kCorrectGrid));
   {
     ProfScope ps(P, "k_relax_correct", s);
-#define RC_LAUNCH(TT, PRV)                                                                                     \
-  hipLaunchKernelGGL((k_correct<TT, 1, PRV, 3>), grid, dim3(NTC), 0, s, m->args(), pa, P->tp, a, N,             \
-                     (const uint16_t *)P->lfeat, (const double *)P->lfield, (const double *)P->nstate, (TT *)pop)
+#define RC_LAUNCH(TT, PRV, FV)                                                                                 \
+  do {                                                                                                         \
+    const dim3 grid((unsigned)std::min<int64_t>((N + NTC / 4 - 1) / (NTC / 4), kCorrectGrid));                \
+    hipLaunchKernelGGL((k_correct<TT, 1, PRV, FV, 3>), grid, dim3(NTC), 0, s, m->args(), pa, P->tp, a, N,     \
+                       (const uint16_t *)P->lfeat, (const double *)P->lfield, (const double *)P->nstate,       \
+                       (TT *)pop);                                                                             \
+  } while (0)
+#define RC_LAUNCH_F(TT, PRV)           \
+  do {                                 \
+    if (a.has_force) RC_LAUNCH(TT, PRV, 1); \
+    else RC_LAUNCH(TT, PRV, 0);        \
+  } while (0)
     if (P->prec == SLLBM_F32) {
-      if (a.pr_on) RC_LAUNCH(float, 1);
-      else RC_LAUNCH(float, 0);
+      if (a.pr_on) RC_LAUNCH_F(float, 1);
+      else RC_LAUNCH_F(float, 0);
     } else {
-      if (a.pr_on) RC_LAUNCH(double, 1);
-      else RC_LAUNCH(double, 0);
+      if (a.pr_on) RC_LAUNCH_F(double, 1);
+      else RC_LAUNCH_F(double, 0);
     }
+#undef RC_LAUNCH_F
 #undef RC_LAUNCH
   }
   HIP_TRY(hipGetLastError());
@@ -1276,12 +1378,12 @@ int sllbm::launch_mlp_correct(sllbm_plan_s *P, const sllbm_params *prm, sllbm_ml
   pa.vel = P->tp.vel;
   const int64_t N = P->mesh.n_nodes;
   // a persistent grid: each workgroup stages the weights once and walks several tiles
-  dim3 grid((unsigned)std::min<int64_t>((N + RC - 1) / RC, kCorrectGrid));
+  dim3 grid((unsigned)std::min<int64_t>((N + NTC / 4 - 1) / (NTC / 4), kCorrectGrid));
   const StepArgs none{};
   {
     ProfScope ps(P, "k_mlp_correct", s);
 #define MC_LAUNCH(TT, DD)                                                                                      \
-  hipLaunchKernelGGL((k_correct<TT, 0, 0, DD>), grid, dim3(NTC), 0, s, m->args(), pa, P->tp, none, N,           \
+  hipLaunchKernelGGL((k_correct<TT, 0, 0, 0, DD>), grid, dim3(NTC), 0, s, m->args(), pa, P->tp, none, N,        \
                      (const uint16_t *)P->lfeat, (const double *)P->lfield, (const double *)nullptr, (TT *)pop)
     if (P->prec == SLLBM_F32) {
       if (P->mesh.dim == 2) MC_LAUNCH(float, 2);
