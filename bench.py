@@ -66,6 +66,9 @@ def parse():
                     help="training targets: one step from the restricted fine state, or along the plain coarse run")
     ap.add_argument("--learned-set", choices=["gh", "cub"], default="gh",
                     help="velocity set of the 'learned' legs (D3V125, or D3Q45 at Pr 0.71 as in the paper)")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="run only the learned-correction legs (--learned-* options) and print their results as "
+                         "one JSON line")
     ap.add_argument("--no-extra", action="store_true", help="skip the C1-R (2D roofline-scale) and C4 (channel) lines")
     ap.add_argument("--kernel", choices=["auto", "gather", "tiled"], default="auto")
     ap.add_argument("--velocity-set", choices=["d3q45", "d3v125"], default="d3q45",
@@ -311,7 +314,10 @@ def tensor_case_leg(case, prec, steps, warmup, Pr=1.0, vel="gh"):
     a, b = buf
     prof = S.sllbm_plan_profile_read(plan)
     S.sllbm_plan_profile(plan, False)
-    tot = S.sllbm_moments(plan, prm, a, totals=True)
+    try:
+        tot = S.sllbm_moments(plan, prm, a, totals=True)
+    except S.SllbmError:              # non-finite or non-physical nodes (EUNSTABLE)
+        tot = [float("nan")]
     extra = {}
     if ctl:
         st = S.sllbm_force_read(plan, stream)
@@ -388,17 +394,19 @@ def mixing_dtheta(S, torch, plan, prm, pop, shape, du, V, box):
 
 
 def learned_leg(ncell=16, ratio=4, steps=None, n_train=8, train_iters=1500, Ma_c=0.7, alphas=(0.0, 0.25, 0.5, 1.0),
-                targets="injected", vel="gh", Pr=1.0):
-    return _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, targets, vel, Pr)
+                targets="injected", vel="gh", Pr=1.0, train_seeds=(6, 7), eval_seed=5):
+    return _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, targets, vel, Pr, train_seeds,
+                        eval_seed)
 
 
-def _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, targets, vel, Pr):
+def _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, targets, vel, Pr, train_seeds, eval_seed):
     """C5: temporal mixing layer on a coarse mesh, plain and with the learned correction,
-    against the 4x finer mesh; FP32 populations.  The network is trained by the library's
-    kernels on restricted one-step samples of a fine run (seed 5); a gain alpha on its
-    output (0 = the plain method) is chosen on that same run's momentum-thickness history;
-    everything is then evaluated on a run it never saw (seed 6): momentum-thickness history
-    and time per coarse step.  targets="injected": a sample starts the plain coarse step
+    against the `ratio`x finer mesh; FP32 populations.  The network is trained by the
+    library's kernels on restricted one-step samples (n_train per run) of fine runs with the
+    perturbation seeds train_seeds; a gain alpha on its output (0 = the plain method) is
+    chosen on the first training run's momentum-thickness history; everything is then
+    evaluated on a run it never saw (eval_seed): momentum-thickness history and time per
+    coarse step.  targets="injected": a sample starts the plain coarse step
     from the restricted fine state; "trajectory": from the plain coarse run started at the
     restricted initial state, so that the features come from coarse-evolved states as in
     use and the target includes the drift accumulated so far.  vel "cub" runs the reduced set
@@ -481,9 +489,14 @@ def _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, target
         hist, X, T, ms = [], [], [], 0.0
         every = max(1, steps // n_train)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
         for n in range(steps + 1):
             if n % every_h == 0:
                 hist.append(dth("f", fa))
+            if n % 250 == 0 and n and time.perf_counter() - w0 > 30:
+                print(f"# learned Ma_c {Ma_c}: fine run seed {seed} at coarse step {n} of {steps}", file=sys.stderr,
+                      flush=True)
+                w0 = time.perf_counter()
             if n == steps:
                 break
             take = samples and n % every == 0 and len(X) < n_train
@@ -530,9 +543,15 @@ def _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, target
     def rate_err(h, ref):
         return abs(late_rate(h) - late_rate(ref)) / abs(late_rate(ref))
 
-    # ---- training on seed 5
+    # ---- training on the runs of train_seeds
     t0 = time.perf_counter()
-    c5, f5, X, T, _ = fine_history(5, samples=True)
+    X, T = [], []
+    for i, sd in enumerate(train_seeds):
+        c_s, f_s, Xs, Ts, _ = fine_history(sd, samples=True)
+        X += Xs
+        T += Ts
+        if i == 0:
+            c_sel, f_sel = c_s, f_s          # the gain is selected on the first training run
     X, T = torch.cat(X), torch.cat(T)
     net = S.sllbm_mlp_create(nf, 2 * Q, seed=1)
     gen = torch.Generator(device="cuda")
@@ -556,9 +575,9 @@ def _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, target
         th = theta.copy()
         th[o4:] *= a
         S.sllbm_mlp_set_params(net, th)
-        h, _ = coarse_rollout(c5, None if a == 0.0 else net)
-        sel[a] = rate_err(h, f5)
-        sel_growth[a] = growth_err(h, f5)
+        h, _ = coarse_rollout(c_sel, None if a == 0.0 else net)
+        sel[a] = rate_err(h, f_sel)
+        sel_growth[a] = growth_err(h, f_sel)
     alpha = min(sel, key=sel.get)
     print(f"# learned Ma_c {Ma_c} {vname}: gain {alpha} selected ({sel})", file=sys.stderr, flush=True)
     th = theta.copy()
@@ -567,14 +586,15 @@ def _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, target
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
 
-    # ---- evaluation on seed 6
-    c6, f6, _, _, t_f = fine_history(6, timed=True)
-    hp, t_p = coarse_rollout(c6, None, timed=True)
-    hl, t_l = coarse_rollout(c6, net, timed=True)
-    hist = {"fine": f6, "plain": hp, "learned": hl}
+    # ---- evaluation on eval_seed
+    c_ev, f_ev, _, _, t_f = fine_history(eval_seed, timed=True)
+    hp, t_p = coarse_rollout(c_ev, None, timed=True)
+    hl, t_l = coarse_rollout(c_ev, net, timed=True)
+    hist = {"fine": f_ev, "plain": hp, "learned": hl}
     return {
         "workload": f"3D temporal mixing layer Ma_c {Ma_c}, coarse {ncell}^3 cells p=2 ({Nc} nodes) vs "
-                    f"{ratio}x finer ({Nf} nodes), {vname}, Pr {Pr}, FP32; trained on seed 5, evaluated on seed 6",
+                    f"{ratio}x finer ({Nf} nodes), {vname}, Pr {Pr}, FP32; trained on seeds "
+                    f"{', '.join(map(str, train_seeds))}, evaluated on seed {eval_seed}",
         "box_dtheta0": [round(b / d0, 3) for b in box],
         "coarse_kernel": {0: "gather", 2: "tiled (relaxation and correction in one pass)"}.get(
             S.sllbm_plan_info(cplan)["kernel"], "other"),
@@ -587,19 +607,19 @@ def _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, target
                                "learned": round(t_l / steps, 4)},
         "time_to_solution_ratio": {"fine_vs_learned": round(t_f / t_l, 2), "fine_vs_plain": round(t_f / t_p, 2)},
         "dtheta": {k: [round(v, 6) for v in h] for k, h in hist.items()},
-        "dtheta_growth_max_rel_err": {"plain": round(growth_err(hp, f6), 4), "learned": round(growth_err(hl, f6), 4)},
+        "dtheta_growth_max_rel_err": {"plain": round(growth_err(hp, f_ev), 4), "learned": round(growth_err(hl, f_ev), 4)},
         "tau_per_step": round(tau_step, 5),
         "self_similar_window_tau": list(window) if window else None,
         "window_samples": int(in_window.sum()),
-        "dtheta_rate_in_window": {"fine": late_rate(f6), "plain": late_rate(hp), "learned": late_rate(hl),
-                                  "plain_rel_err": round(rate_err(hp, f6), 4),
-                                  "learned_rel_err": round(rate_err(hl, f6), 4)},
-        "dtheta_final_rel_err": {"plain": round(abs(hp[-1] - f6[-1]) / f6[-1], 4),
-                                 "learned": round(abs(hl[-1] - f6[-1]) / f6[-1], 4)},
+        "dtheta_rate_in_window": {"fine": late_rate(f_ev), "plain": late_rate(hp), "learned": late_rate(hl),
+                                  "plain_rel_err": round(rate_err(hp, f_ev), 4),
+                                  "learned_rel_err": round(rate_err(hl, f_ev), 4)},
+        "dtheta_final_rel_err": {"plain": round(abs(hp[-1] - f_ev[-1]) / f_ev[-1], 4),
+                                 "learned": round(abs(hl[-1] - f_ev[-1]) / f_ev[-1], 4)},
         # the workload's bar: growth rate in the self-similar window within 5 % of the fine run
         # at >= 8x lower time to solution
-        "meets_5pct_at_8x": {"plain": bool(rate_err(hp, f6) <= 0.05 and t_f / t_p >= 8.0),
-                             "learned": bool(rate_err(hl, f6) <= 0.05 and t_f / t_l >= 8.0)},
+        "meets_5pct_at_8x": {"plain": bool(rate_err(hp, f_ev) <= 0.05 and t_f / t_p >= 8.0),
+                             "learned": bool(rate_err(hl, f_ev) <= 0.05 and t_f / t_l >= 8.0)},
         "finite": {k: all(math.isfinite(v) for v in h) for k, h in hist.items()},
     }
 
@@ -714,6 +734,16 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.learned_only:
+        lset = dict(vel="cub", Pr=0.71) if args.learned_set == "cub" else {}
+        res = []
+        for mc in (float(x) for x in args.learned_mach.split(",")):
+            res.append(learned_leg(ncell=args.learned_ncell, ratio=args.learned_ratio, Ma_c=mc,
+                                   steps=args.learned_steps, targets=args.learned_targets, **lset))
+            print(f"# learned Ma_c {mc} done: time-to-solution ratio {res[-1]['time_to_solution_ratio']}",
+                  file=sys.stderr, flush=True)
+        print(json.dumps({"learned": res}))
+        return
     vset = args.velocity_set
     tkey = "tgv45" if vset == "d3q45" else "tgv"
     r64 = gpu_leg("f64", args.steps, args.warmup, args.ncell, args.kernel, vset)

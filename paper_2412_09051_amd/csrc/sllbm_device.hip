@@ -168,7 +168,9 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
   P->vol = node_volumes(m);
   if (P->kernel == 0) {
     int c[3];
-    P->tile_ok = tile_cells(m.dim, m.p, c) && tile_eligible(m, t, c) ? 1 : 0;
+    // (the tiled kernels address a population plane through 32-bit byte offsets)
+    const int64_t plane_bytes = m.n_nodes * (prec == SLLBM_F32 ? 4 : 8);
+    P->tile_ok = tile_cells(m.dim, m.p, c) && tile_eligible(m, t, c) && plane_bytes <= kBufMaxBytes ? 1 : 0;
     if (P->tile_ok) {
       int64_t ntiles = 1;
       for (int a = 0; a < m.dim; a++) ntiles *= (m.N[a] + c[a] * m.p - 1) / (c[a] * m.p);

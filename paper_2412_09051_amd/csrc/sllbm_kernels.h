@@ -39,6 +39,10 @@ struct StepArgs {
 constexpr int kTileTabs = 5;
 constexpr int kTileTabsMax = 16;
 
+// The 3D tiled kernel reads and writes each population plane through a buffer resource with
+// 32-bit byte offsets: its plans hold at most this many bytes per plane.
+constexpr int64_t kBufMaxBytes = 0x7ffffff0;
+
 // Cell-aligned tile (cells per axis) of the LDS-tiled step kernel for (dim, order).
 template <int D, int P> struct TileShape;
 // 2D tiles hold at most 256 nodes: one node per lane of a 256-thread workgroup, so that the

@@ -109,6 +109,44 @@ template <> struct BufLoad<float> {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
   }
 };
+template <typename T> struct BufStore;
+template <> struct BufStore<double> {
+  __device__ static void put(__amdgpu_buffer_rsrc_t r, int off, double v) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, 0);
+  }
+};
+template <> struct BufStore<float> {
+  __device__ static void put(__amdgpu_buffer_rsrc_t r, int off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+  }
+};
+// A byte offset past every buffer this file builds (they hold at most kBufMaxBytes): loads
+// at it return 0 and stores are dropped, so a lane without an element needs no branch.
+// Memory accesses under divergent branches make the compiler wait for every access in
+// flight (vmcnt(0)) before the next use of any of them, which serialises the prefetch
+// with the passes it is meant to overlap.
+constexpr int kBufOutOfRange = (int)kBufMaxBytes;
+// the offset through an empty asm: the compiler keeps one offset register per access instead
+// of turning the choice between a real and the out-of-range offset back into branches
+__device__ __forceinline__ int opaque_off(int off) {
+  asm volatile("" : "+v"(off));
+  return off;
+}
+// The 8 constants of velocity i (zeta, xi, |xi|^2, w) through the scalar cache: the step
+// never writes the velocity table, and scalar loads stay out of the vector-memory counter
+// that the population loads and stores are waited on with.
+__device__ __forceinline__ void vel_consts(const double *vel, int i, double (&v)[8]) {
+  const double __attribute__((address_space(4))) *c = (const double __attribute__((address_space(4))) *)(vel + 8 * i);
+#pragma unroll
+  for (int j = 0; j < 8; j++) v[j] = c[j];
+}
+// one of three values by a runtime index, taken by value: a conditional expression over
+// lvalues selects their addresses, which pins the arrays or the plan they live in to scratch
+template <typename V>
+__device__ __forceinline__ V sel3(int k, V a, V b, V c) {
+  return k == 0 ? a : (k == 1 ? b : c);
+}
 template <typename T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const T *base, int64_t elems) {
   const int64_t bytes = elems * (int64_t)sizeof(T);
@@ -148,6 +186,8 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
   __shared__ T X[2 * XS];
   __shared__ T WT[NTAB * NW * (P + 1)];   // row tb * NW + (axis base) + t
   __shared__ int OT[NTAB * NW];           // stencil start relative to the table's region
+  __shared__ int GEO[2 * kMaxQ];          // per axis and velocity: region start rs | extent R << 16
+  __shared__ int GTB[2 * kMaxQ];          // table id | identity flag << 30
 
   const int Q = pl.Q;
   const int tid = threadIdx.x;
@@ -209,17 +249,24 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
     for (int j = 0; j <= P; j++) WT[r * (P + 1) + j] = w[j];
     OT[r] = off;
   }
+  // the departure-region geometry of every velocity along x and y, once per tile
+  for (int e = tid; e < 2 * Q; e += BS) {
+    const int a = e / Q, i = e - a * Q;
+    const int tb = pl.tab_reg[a * Q + i];
+    const AxGeo g = a == 0 ? axis_geo<P>(pl.ax[0], tb, n0x, vx, TX) : axis_geo<P>(pl.ax[1], tb, n0y, vy, TY);
+    GEO[a * kMaxQ + i] = (g.rs & 0xffff) | (g.R << 16);
+    GTB[a * kMaxQ + i] = g.tb | (g.ident << 30);
+  }
+  __syncthreads();
 
-  // staging elements of this thread: region coordinates and their offset in a population
-  // when the region does not cross a periodic seam (both independent of the velocity)
-  // (coordinates packed 10 bits each: x | y << 10 | z << 20; x = RX marks no element)
-  int epk[NST], eoff[NST];
+  // staging elements of this thread: region coordinates, independent of the velocity
+  // (packed 10 bits each: x | y << 10 | z << 20; x = RX marks no element)
+  int epk[NST];
 #pragma unroll
   for (int s = 0; s < NST; s++) {
     const int e = tid + BS * s;
     const int rx = e < SS ? e % RX : RX, ry = e < SS ? (e / RX) % RY : 0, rz = e < SS ? e / (RX * RY) : 0;
     epk[s] = rx | (ry << 10) | (rz << 20);
-    eoff[s] = (rx + Nx * (ry + Ny * rz)) * (int)sizeof(T);   // bytes
   }
   static_assert(RX < 1024 && RY < 1024 && RZ < 1024, "staging coordinates are packed in 10 bits");
   auto staged = [&](int s, const AxGeo (&g)[3]) __attribute__((always_inline)) -> bool {
@@ -227,44 +274,39 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
   };
 
   // ---- software pipeline: registers hold the departure region of the velocity after
-  // the one in LDS
+  // the one in LDS.  The loads are issued by every lane (out-of-range offsets for lanes
+  // without an element), so that the compiler counts the loads in flight exactly instead of
+  // waiting for all of them at the next use of any.
   T pf[NST], pg[NST];
   AxGeo ng[3], cg[3];
+  auto geo = [&](int a, int i) __attribute__((always_inline)) {
+    AxGeo g;   // the same for the whole workgroup: held in scalar registers
+    const int v = __builtin_amdgcn_readfirstlane(GEO[a * kMaxQ + i]);
+    const int t = __builtin_amdgcn_readfirstlane(GTB[a * kMaxQ + i]);
+    g.rs = (int)(short)(v & 0xffff);
+    g.R = v >> 16;
+    g.tb = t & 0x3fffffff;
+    g.ident = t >> 30;
+    return g;
+  };
+  // velocity i (i >= Q: nothing, every offset out of range)
   auto prefetch = [&](int i) __attribute__((always_inline)) {
-    ng[0] = axis_geo<P>(pl.ax[0], pl.tab_reg[i], n0x, vx, TX);
-    ng[1] = axis_geo<P>(pl.ax[1], pl.tab_reg[Q + i], n0y, vy, TY);
-    if (D == 3) {
-      ng[2] = axis_geo<P>(pl.ax[2], pl.tab_reg[2 * Q + i], n0z, vz, TZ);
-    } else {
-      ng[2].tb = 0; ng[2].ident = 1; ng[2].rs = 0; ng[2].R = 1;
-    }
-    const T *F = pin + (size_t)i * N;
-    const T *G = pin + ((size_t)Q + i) * N;
-    const int sx = n0x + ng[0].rs, sy = n0y + ng[1].rs, sz = (D == 3) ? n0z + ng[2].rs : 0;
-    const bool inside = sx >= 0 && sx + ng[0].R <= Nx && sy >= 0 && sy + ng[1].R <= Ny &&
-                        (D == 2 || (sz >= 0 && sz + ng[2].R <= Nz));
-    if (inside) {
-      const int64_t kb = (int64_t)sx + (int64_t)Nx * ((int64_t)sy + (int64_t)Ny * sz);
-      const __amdgpu_buffer_rsrc_t rf = buf_rsrc(F + kb, N - kb), rg = buf_rsrc(G + kb, N - kb);
+    const bool real = i < Q;
+    const int iv = real ? i : Q - 1;
+    ng[0] = geo(0, iv);
+    ng[1] = geo(1, iv);
+    ng[2].tb = 0; ng[2].ident = 1; ng[2].rs = 0; ng[2].R = 1;
+    const __amdgpu_buffer_rsrc_t rf = buf_rsrc(pin + (size_t)iv * N, N);
+    const __amdgpu_buffer_rsrc_t rg = buf_rsrc(pin + ((size_t)Q + iv) * N, N);
+    const int sx = n0x + ng[0].rs, sy = n0y + ng[1].rs;
 #pragma unroll
-      for (int s = 0; s < NST; s++) {
-        if (staged(s, ng)) {
-          pf[s] = BufLoad<T>::get(rf, eoff[s]);
-          pg[s] = BufLoad<T>::get(rg, eoff[s]);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int s = 0; s < NST; s++) {
-        if (staged(s, ng)) {
-          int gxx = wrap_idx(sx + (epk[s] & 1023), Nx);
-          int gyy = wrap_idx(sy + ((epk[s] >> 10) & 1023), Ny);
-          int gzz = (D == 3) ? wrap_idx(sz + (epk[s] >> 20), Nz) : 0;
-          size_t k = (size_t)gxx + (size_t)Nx * ((size_t)gyy + (size_t)Ny * gzz);
-          pf[s] = F[k];
-          pg[s] = G[k];
-        }
-      }
+    for (int s = 0; s < NST; s++) {
+      const bool in = real && staged(s, ng);
+      const int gxx = wrap_idx(sx + (epk[s] & 1023), Nx);
+      const int gyy = wrap_idx(sy + ((epk[s] >> 10) & 1023), Ny);
+      const int off = opaque_off(in ? (gxx + Nx * gyy) * (int)sizeof(T) : kBufOutOfRange);
+      pf[s] = BufLoad<T>::get(rf, off);
+      pg[s] = BufLoad<T>::get(rg, off);
     }
   };
   auto commit = [&]() __attribute__((always_inline)) {
@@ -344,12 +386,12 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
     xpass();
     __syncthreads();   // X holds velocity i; S is free
     const int tby = cg[1].tb, leny = cg[1].ident ? 1 : P + 1;
-    if (i + 1 < Q) {
-      commit();
-      if (i + 2 < Q) prefetch(i + 2);
-    }
+    if (i + 1 < Q) commit();
+    prefetch(i + 2);
     ypass_nodes(tby, leny, fv, gv);
-    const double *vi = pl.vel + 8 * i;
+    // the velocity table is never written by the step: read through the scalar cache
+    const double __attribute__((address_space(4))) *vi =
+        (const double __attribute__((address_space(4))) *)(pl.vel + 8 * i);
     const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
 #pragma unroll
     for (int m = 0; m < NPT; m++) {
@@ -367,7 +409,7 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
   T fs[NPT][QL], gs[NPT][QL];
   prefetch(0);
   commit();
-  if (Q > 1) prefetch(1);
+  prefetch(1);
   if constexpr (QR > 0) {
 #pragma unroll
     for (int i = 0; i < QR; i++) {
@@ -383,12 +425,13 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
     for (int i = 0; i < Q; i++) {
       double fv[NPT], gv[NPT];
       velocity(i, fv, gv);
+      const __amdgpu_buffer_rsrc_t of = buf_rsrc(pout + (size_t)i * N, N);
+      const __amdgpu_buffer_rsrc_t og = buf_rsrc(pout + ((size_t)Q + i) * N, N);
 #pragma unroll
       for (int m = 0; m < NPT; m++) {
-        if (!own[m]) continue;
-        const int64_t k = node_index(m);
-        pout[(size_t)i * N + k] = (T)fv[m];
-        pout[((size_t)Q + i) * N + k] = (T)gv[m];
+        const int off = opaque_off(own[m] ? (int)node_index(m) * (int)sizeof(T) : kBufOutOfRange);
+        BufStore<T>::put(of, off, (T)fv[m]);
+        BufStore<T>::put(og, off, (T)gv[m]);
       }
     }
   }
@@ -426,12 +469,17 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
       if constexpr (PR) {  // Pr != 1
         HeatFlux hq = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-        for (int i = 0; i < QR; i++) heat_flux_add(hq, pl.vel + 8 * i, u0, u1, u2, (double)fs[m][i], (double)gs[m][i]);
+        for (int i = 0; i < QR; i++) {
+          double vi[8];
+          vel_consts(pl.vel, i, vi);
+          heat_flux_add(hq, vi, u0, u1, u2, (double)fs[m][i], (double)gs[m][i]);
+        }
         pt = pr_term(hq, it, sa, D);
       }
 #pragma unroll
       for (int i = 0; i < QR; i++) {
-        const double *vi = pl.vel + 8 * i;
+        double vi[8];
+        vel_consts(pl.vel, i, vi);
         const double f = (double)fs[m][i], g = (double)gs[m][i];
         const double fe = eq_f(e, vi);
         double fo = f - (f - fe) * it;
@@ -483,7 +531,7 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
   constexpr int NST = (SS + BS - 1) / BS;    // staged elements per thread and population
   constexpr int NW = TX + TY + TZ;           // weight rows: one per tile position and axis
   constexpr int WS = NW * (P + 1);
-  static_assert(NW <= BS, "weight rows exceed the workgroup");
+  static_assert(NW <= 64, "the weight rows are loaded by the first wave");
   static_assert(BS >= TX * TY, "tile cross-section exceeds the workgroup");
   constexpr int NB = SK ? 2 : 1;             // weight-row buffers
   __shared__ T S[2 * SS];
@@ -491,6 +539,8 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
   __shared__ T Ys[SK ? 2 * YS : 1];
   __shared__ T WT[NB * WS];
   __shared__ int OT[NB * NW];
+  __shared__ int GEO[3 * kMaxQ];             // per axis and velocity: region start rs | extent R << 16
+  __shared__ int GTB[3 * kMaxQ];             // table id | identity flag << 30
   static_assert(SK || YS <= SS, "the y-pass output must fit the staging buffer it reuses");
   T *const Y = SK ? Ys : S;
 
@@ -530,49 +580,96 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
     }
   }
   const double scale = sa.scale ? *sa.scale : 1.0;
+  // the departure-region geometry of every velocity along every axis, once per tile (a
+  // chain of dependent table loads each; per velocity it is then an LDS read)
+  for (int e = tid; e < 3 * Q; e += BS) {
+    const int a = e / Q, i = e - a * Q;
+    const int vt = sel3(a, vx, vy, vz), n0 = sel3(a, n0x, n0y, n0z), Ta = sel3(a, TX, TY, TZ);
+    const int tb = pl.tab_reg[a * Q + i];
+    AxGeo g;   // (one call per axis: a runtime index into the plan would copy it to scratch)
+    if (a == 0) g = axis_geo<P>(pl.ax[0], tb, n0, vt, Ta);
+    else if (a == 1) g = axis_geo<P>(pl.ax[1], tb, n0, vt, Ta);
+    else g = axis_geo<P>(pl.ax[2], tb, n0, vt, Ta);
+    GEO[a * kMaxQ + i] = (g.rs & 0xffff) | (g.R << 16);
+    GTB[a * kMaxQ + i] = g.tb | (g.ident << 30);
+  }
+  __syncthreads();
 
   auto node_index = [&](int m) __attribute__((always_inline)) -> int64_t {
     return (int64_t)(n0x + otx[m]) + (int64_t)Nx * ((int64_t)(n0y + oty[m]) + (int64_t)Ny * (n0z + otz[m]));
   };
   // ---- software pipeline: the departure region of velocity i+2 is loaded into
-  // registers while velocities i and i+1 are interpolated out of LDS
+  // registers while velocities i and i+1 are interpolated out of LDS.  The per-velocity
+  // geometry comes from LDS (built once per tile), the weight rows are loaded by the first
+  // wave without a divergent branch, every lane issues the stores of the streamed values
+  // (out-of-range offsets for lanes without a node) and the velocity constants come through
+  // the scalar cache: none of these makes the compiler wait for all memory accesses in
+  // flight, which the per-velocity table loads and branchy stores used to do.
   T pf[NST], pg[NST];
   T pw[P + 1];
-  int poff = 0;
+  int pst = 0;       // raw stencil start of this thread's weight row
+#pragma unroll
+  for (int s = 0; s < NST; s++) pf[s] = pg[s] = T(0);
+#pragma unroll
+  for (int j = 0; j <= P; j++) pw[j] = T(0);
   AxGeo ng[3], cg[3];
+  auto geo = [&](int a, int i) __attribute__((always_inline)) {
+    AxGeo g;   // the same for the whole workgroup: held in scalar registers
+    const int v = __builtin_amdgcn_readfirstlane(GEO[a * kMaxQ + i]);
+    const int t = __builtin_amdgcn_readfirstlane(GTB[a * kMaxQ + i]);
+    g.rs = (int)(short)(v & 0xffff);
+    g.R = v >> 16;
+    g.tb = t & 0x3fffffff;
+    g.ident = t >> 30;
+    return g;
+  };
+  // velocity i's departure region and this thread's weight row (thread t < NW: row t, for
+  // axis ax and tile position q); i >= Q loads nothing (every offset out of range)
   auto prefetch = [&](int i) __attribute__((always_inline)) {
-    ng[0] = axis_geo<P>(pl.ax[0], pl.tab_reg[i], n0x, vx, TX);
-    ng[1] = axis_geo<P>(pl.ax[1], pl.tab_reg[Q + i], n0y, vy, TY);
-    ng[2] = axis_geo<P>(pl.ax[2], pl.tab_reg[2 * Q + i], n0z, vz, TZ);
-    const T *F = pin + (size_t)i * N;
-    const T *G = pin + ((size_t)Q + i) * N;
+    const bool real = i < Q;
+    const int iv = real ? i : Q - 1;
+    ng[0] = geo(0, iv);
+    ng[1] = geo(1, iv);
+    ng[2] = geo(2, iv);
+    const T *F = pin + (size_t)iv * N, *G = pin + ((size_t)Q + iv) * N;
 #pragma unroll
     for (int s = 0; s < NST; s++) {
       int e = tid + BS * s;
       int rx = e % RX, ry = (e / RX) % RY, rz = e / (RX * RY);
-      if (e < SS && rx < ng[0].R && ry < ng[1].R && rz < ng[2].R) {
-        int gxx = wrap_idx(n0x + ng[0].rs + rx, Nx);
-        int gyy = wrap_idx(n0y + ng[1].rs + ry, Ny);
-        int gzz = wrap_idx(n0z + ng[2].rs + rz, Nz);
-        size_t k = (size_t)gxx + (size_t)Nx * ((size_t)gyy + (size_t)Ny * gzz);
-        pf[s] = F[k];
-        pg[s] = G[k];
+      const bool in = real && e < SS && rx < ng[0].R && ry < ng[1].R && rz < ng[2].R;
+      const int gxx = wrap_idx(n0x + ng[0].rs + rx, Nx);
+      const int gyy = wrap_idx(n0y + ng[1].rs + ry, Ny);
+      const int gzz = wrap_idx(n0z + ng[2].rs + rz, Nz);
+      // Conditional loads here (unlike the weight rows, stores and the 2D kernel): the
+      // compiler then waits for them before the passes of the current velocity, which keeps
+      // the workgroups of an XCD close in velocity, so that neighbouring tiles still find each
+      // other's departure regions in L2.  Fully pipelined loads (every lane, out-of-range
+      // offsets) drift the workgroups apart: on the 128 x 96 x 64 channel (D3V125, p = 2, FP32,
+      // 8^3-node tiles) the launch then fetches 29 GB instead of 9 GB and takes 10.6 ms against
+      // 8.3 ms, while the larger p = 3 tiles of the Taylor-Green vortex gain at most 2 %.
+      if (in) {
+        pf[s] = F[gxx + (size_t)Nx * (gyy + (size_t)Ny * gzz)];
+        pg[s] = G[gxx + (size_t)Nx * (gyy + (size_t)Ny * gzz)];
       }
     }
-    if (tid < NW) {
-      int ax = tid < TX ? 0 : (tid < TX + TY ? 1 : 2);
-      int q = tid - (ax == 0 ? 0 : (ax == 1 ? TX : TX + TY));
-      int vt = ax == 0 ? vx : (ax == 1 ? vy : vz);
-      int n0a = ax == 0 ? n0x : (ax == 1 ? n0y : n0z);
-      int Ta = ax == 0 ? TX : (ax == 1 ? TY : TZ);
-      int len;
-      const AxGeo &ga = ax == 0 ? ng[0] : (ax == 1 ? ng[1] : ng[2]);
-      const DevAxis &da = ax == 0 ? pl.ax[0] : (ax == 1 ? pl.ax[1] : pl.ax[2]);
-      if (q < vt) axis_weights<T, P>(da, ga, n0a, q, Ta, poff, len, pw);
+    if (tid < 64) {   // the wave holding the NW row threads (a wave-uniform branch)
+      const int tt = opaque_off(tid), t = tt < NW ? tt : 0;
+      const int ax = t < TX ? 0 : (t < TX + TY ? 1 : 2);
+      const int q = t - sel3(ax, 0, TX, TX + TY);
+      const int n0a = sel3(ax, n0x, n0y, n0z), axN = sel3(ax, Nx, Ny, Nz);
+      const int tb = sel3(ax, ng[0].tb, ng[1].tb, ng[2].tb);
+      const int32_t *st = sel3(ax, pl.ax[0].start, pl.ax[1].start, pl.ax[2].start);
+      const T *wt = sel3(ax, WeightSel<T>::get(pl.ax[0]), WeightSel<T>::get(pl.ax[1]), WeightSel<T>::get(pl.ax[2]));
+      // positions past a partial tile read the axis's last row (their weights are not used)
+      const int row = opaque_off(tb * axN + min(n0a + q, axN - 1));
+      pst = st[row];
+#pragma unroll
+      for (int j = 0; j <= P; j++) pw[j] = wt[(size_t)row * (P + 1) + j];
     }
   };
-  // the prefetched velocity into S and weight buffer wb
-  auto commit = [&](int wb) __attribute__((always_inline)) {
+  // the prefetched velocity into S and weight buffer wb (placeholder: offsets 0, so that the
+  // passes over it stay inside the buffers)
+  auto commit = [&](int wb, bool placeholder = false) __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < NST; s++) {
       int e = tid + BS * s;
@@ -583,9 +680,18 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
       }
     }
     if (tid < NW) {
+      // (derived from an opaque copy of tid: recomputed here each velocity rather than held
+      // across the loop, where the register budget would spill them and the reload would
+      // wait on every access in flight)
+      const int t = opaque_off(tid);
+      const int ax = t < TX ? 0 : (t < TX + TY ? 1 : 2);
+      const int q = t - sel3(ax, 0, TX, TX + TY);
+      const int n0a = sel3(ax, n0x, n0y, n0z), axN = sel3(ax, Nx, Ny, Nz), Ta = sel3(ax, TX, TY, TZ);
+      const int ident = sel3(ax, ng[0].ident, ng[1].ident, ng[2].ident);
+      const int rs = sel3(ax, ng[0].rs, ng[1].rs, ng[2].rs);
 #pragma unroll
-      for (int j = 0; j <= P; j++) WT[wb * WS + tid * (P + 1) + j] = pw[j];
-      OT[wb * NW + tid] = poff;
+      for (int j = 0; j <= P; j++) WT[wb * WS + t * (P + 1) + j] = ident ? T(j == 0 ? 1 : 0) : pw[j];
+      OT[wb * NW + t] = placeholder ? 0 : (ident ? q : rel_start<P>(pst, n0a, axN, Ta) - rs);
     }
     cg[0] = ng[0];
     cg[1] = ng[1];
@@ -677,16 +783,23 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
 #pragma unroll
   for (int m = 0; m < NPT; m++) rho[m] = j0[m] = j1[m] = j2[m] = E[m] = 0.0;
   // store the streamed values of velocity i and add them to the moments
+  // (i < 0: a placeholder velocity, every store out of range and no moments)
   auto accumulate = [&](int i, const double (&fv)[NPT], const double (&gv)[NPT]) __attribute__((always_inline)) {
-    const double *vi = pl.vel + 8 * i;
+    const int iv = i < 0 ? 0 : i;
+    // the velocity table is never written by the step: read through the scalar cache, so
+    // that these loads do not join the vector-memory counter the prefetch waits on
+    const double __attribute__((address_space(4))) *vi =
+        (const double __attribute__((address_space(4))) *)(pl.vel + 8 * iv);
     const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
+    const __amdgpu_buffer_rsrc_t of = buf_rsrc(pout + (size_t)iv * N, N);
+    const __amdgpu_buffer_rsrc_t og = buf_rsrc(pout + ((size_t)Q + iv) * N, N);
 #pragma unroll
     for (int m = 0; m < NPT; m++) {
-      if (!own[m]) continue;
-      const int64_t k = node_index(m);
-      pout[(size_t)i * N + k] = (T)fv[m];
-      pout[((size_t)Q + i) * N + k] = (T)gv[m];
+      const int off = opaque_off(own[m] && i >= 0 ? (int)node_index(m) * (int)sizeof(T) : kBufOutOfRange);
+      BufStore<T>::put(of, off, (T)fv[m]);
+      BufStore<T>::put(og, off, (T)gv[m]);
     }
+    if (i < 0) return;
 #pragma unroll
     for (int m = 0; m < NPT; m++) {
       rho[m] += fv[m];
@@ -698,11 +811,17 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
   };
 
   if constexpr (!SK) {
-    prefetch(0);
-    for (int i = 0; i < Q; i++) {
+    // iteration -1 only issues the loads of velocity 0: its commit, passes and stores run on
+    // placeholder values (a valid geometry, offsets 0, every store out of range), so that every
+    // iteration issues the same memory operations in the same order and the compiler's
+    // counts of those in flight stay exact around the loop
+    ng[0] = geo(0, 0);
+    ng[1] = geo(1, 0);
+    ng[2] = geo(2, 0);
+    for (int i = -1; i < Q; i++) {
       __syncthreads();  // everyone is done reading the previous velocity out of LDS
-      commit(0);
-      if (i + 1 < Q) prefetch(i + 1);
+      commit(0, i < 0);
+      prefetch(i + 1);
       __syncthreads();
       xpass(0);
       __syncthreads();
@@ -715,13 +834,14 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
   } else {
   prefetch(0);
   commit(0);
-  if (Q > 1) prefetch(1);
+  prefetch(1);
   __syncthreads();
   int zlen = 0;
   for (int i = 0; i < Q; i++) {
     const int wb = i & 1;
-    // phase A: z of velocity i-1, x of velocity i
-    if (i > 0) {
+    // phase A: z of velocity i-1, x of velocity i (at i = 0 a placeholder with no rows and
+    // every store out of range, so that each iteration issues the same memory operations)
+    {
       double fv[NPT], gv[NPT];
       zpass(wb ^ 1, zlen, fv, gv);
       accumulate(i - 1, fv, gv);
@@ -731,10 +851,8 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile3d(const DevTensorPlan pl,
     // phase B: y of velocity i, commit of velocity i+1, loads of i+2
     ypass(wb);
     zlen = cg[2].ident ? 1 : P + 1;
-    if (i + 1 < Q) {
-      commit(wb ^ 1);
-      if (i + 2 < Q) prefetch(i + 2);
-    }
+    if (i + 1 < Q) commit(wb ^ 1);
+    prefetch(i + 2);
     __syncthreads();
   }
   {
@@ -826,7 +944,8 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
       uu[v][2] = nstate[3 * N + kk];
     }
     for (int i = 0; i < Q; i++) {
-      const double *vi = pl.vel + 8 * i;
+      double vi[8];
+      vel_consts(pl.vel, i, vi);
       VT fvec = *(const VT *)(pop + (size_t)i * N + k0), gvec = *(const VT *)(pop + ((size_t)Q + i) * N + k0);
 #pragma unroll
       for (int v = 0; v < V; v++)
@@ -836,7 +955,8 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
     for (int v = 0; v < V; v++) pt[v] = pr_term(hq[v], itau[v], sa, D);
   }
   for (int i = 0; i < Q; i++) {
-    const double *vi = pl.vel + 8 * i;
+    double vi[8];
+    vel_consts(pl.vel, i, vi);
     VT *pf = (VT *)(pop + (size_t)i * N + k0);
     VT *pg = (VT *)(pop + ((size_t)Q + i) * N + k0);
     VT fvec = *pf, gvec = *pg;
