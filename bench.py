@@ -69,6 +69,10 @@ def parse():
     ap.add_argument("--learned-only", action="store_true",
                     help="run only the learned-correction legs (--learned-* options) and print their results as "
                          "one JSON line")
+    ap.add_argument("--learned-speed", action="store_true",
+                    help="time the plain and the learned coarse step (relaxation and correction in one pass) "
+                         "on the 64^3-cell mixing layer, D3V125 at Pr 1 and D3Q45 at Pr 0.71 and 1, and print one "
+                         "JSON line")
     ap.add_argument("--no-extra", action="store_true", help="skip the C1-R (2D roofline-scale) and C4 (channel) lines")
     ap.add_argument("--kernel", choices=["auto", "gather", "tiled"], default="auto")
     ap.add_argument("--velocity-set", choices=["d3q45", "d3v125"], default="d3q45",
@@ -578,9 +582,11 @@ def _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, target
         h, _ = coarse_rollout(c_sel, None if a == 0.0 else net)
         sel[a] = rate_err(h, f_sel)
         sel_growth[a] = growth_err(h, f_sel)
-    alpha = min(sel, key=sel.get)
+    alpha = min(sel, key=lambda a: sel[a] if math.isfinite(sel[a]) else math.inf)
     print(f"# learned Ma_c {Ma_c} {vname}: gain {alpha} selected ({sel})", file=sys.stderr, flush=True)
-    th = theta.copy()
+    # at gain 0 every weight is zeroed, so that the correction is exactly 0 even where training
+    # diverged (0 x NaN), while the learned run still does the network's work
+    th = theta.copy() if alpha else np.zeros_like(theta)
     th[o4:] *= alpha
     S.sllbm_mlp_set_params(net, th)
     torch.cuda.synchronize()
@@ -599,6 +605,7 @@ def _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, target
         "coarse_kernel": {0: "gather", 2: "tiled (relaxation and correction in one pass)"}.get(
             S.sllbm_plan_info(cplan)["kernel"], "other"),
         "steps": steps, "targets": targets, "train_samples": n_train, "train_iters": train_iters, "train_loss": losses,
+        "train_finite": bool(np.isfinite(theta).all()),
         "train_s": round(train_s, 2),
         "alpha_selection_window_rate_err": {str(k): round(v, 4) for k, v in sel.items()},
         "alpha_selection_growth_err": {str(k): round(v, 4) for k, v in sel_growth.items()},
@@ -622,6 +629,55 @@ def _learned_leg(ncell, ratio, steps, n_train, train_iters, Ma_c, alphas, target
                              "learned": bool(rate_err(hl, f_ev) <= 0.05 and t_f / t_l >= 8.0)},
         "finite": {k: all(math.isfinite(v) for v in h) for k, h in hist.items()},
     }
+
+
+def learned_speed_leg(vel, Pr, steps=20, ncell=64, Ma_c=0.7):
+    """Cost of the learned correction at the mixing layer's coarse size (ncell^3 cells, p = 2,
+    FP32, the paper's 160 x 176 x 98 initial momentum thicknesses at 64 cells): the plain step
+    against one learned step (relaxation and correction in one pass), median of REPS samples,
+    with the library's per-kernel event times.  The network is freshly initialised: its
+    weights do not change the work."""
+    import dataclasses
+    import torch
+    import paper_2412_09051_amd as S
+    import workloads as W
+    d0 = W.MIX_DTHETA0
+    box = tuple(x * d0 for x in (160, 176, 98)) if ncell == 64 else tuple(ncell * c * d0 for c in MIX_BOX_CELLS)
+    mesh, phys = W.mixing_layer_case(ncell=(ncell,) * 3, box=box, Ma_c=Ma_c)
+    phys = dataclasses.replace(phys, Pr=Pr)
+    m = S.sllbm_mesh_build(mesh)
+    vs = S.sllbm_velset_cubature(3, phys.T0) if vel == "d3q45" else S.sllbm_velset_gauss_hermite(3, 5, phys.T0)
+    plan = S.sllbm_interp_plan(m, vs, phys.dt, S.SLLBM_F32)
+    prm = S.Params.from_physics(phys)
+    rho, u, T = W.mixing_layer_fields(S.sllbm_mesh_nodes(m), Ma_c=Ma_c, box=box)
+    a = torch.empty(2 * plan.Q * plan.N, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    S.sllbm_init_equilibrium(plan, prm, torch.tensor(rho, device="cuda"),
+                             torch.tensor(np.ascontiguousarray(u.T), device="cuda"), torch.tensor(T, device="cuda"), a)
+    net = S.sllbm_mlp_create(S.n_features(3), 2 * plan.Q, seed=1)
+    stream = torch.cuda.current_stream()
+    buf = [a, b]
+    out = {"workload": f"mixing layer coarse {ncell}^3 cells p=2 ({plan.N} nodes), {vel.upper()}, Pr {Pr}, FP32",
+           "kernel": S.sllbm_plan_info(plan)["kernel"]}
+    for mode in ("plain", "learned"):
+        def one(n):
+            if mode == "plain":
+                S.sllbm_step(plan, prm, buf[0], buf[1], stream)
+            else:
+                S.sllbm_step_learned(plan, prm, net, buf[0], buf[1], stream)
+            buf[0], buf[1] = buf[1], buf[0]
+        for n in range(3):
+            one(n)
+        torch.cuda.synchronize()
+        S.sllbm_plan_profile(plan, True)
+        med, samples, _ = timed_loop(torch, stream, one, steps)
+        prof = S.sllbm_plan_profile_read(plan)
+        S.sllbm_plan_profile(plan, False)
+        out[mode] = {"ms_per_step": round(med / steps, 4), "samples_ms": [round(x, 3) for x in samples],
+                     "kernels_ms": {k: round(v[0] / v[1], 4) for k, v in prof.items()}}
+    out["learned_over_plain"] = round(out["learned"]["ms_per_step"] / out["plain"]["ms_per_step"], 3)
+    out["finite"] = all(math.isfinite(x) for x in S.sllbm_moments(plan, prm, buf[0], totals=True))
+    return out
 
 
 def copy_calibration():
@@ -734,6 +790,13 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.learned_speed:
+        res = []
+        for vel, Pr in (("d3v125", 1.0), ("d3q45", 1.0), ("d3q45", 0.71)):
+            res.append(learned_speed_leg(vel, Pr))
+            print(f"# learned speed {vel} Pr {Pr}: {res[-1]['learned_over_plain']}", file=sys.stderr, flush=True)
+        print(json.dumps({"learned_speed": res}))
+        return
     if args.learned_only:
         lset = dict(vel="cub", Pr=0.71) if args.learned_set == "cub" else {}
         res = []
