@@ -81,6 +81,10 @@ def parse():
     ap.add_argument("--no-cubature", action="store_true",
                     help="skip the legs on the other TGV velocity set and on the reduced sets D2Q19 / D3Q45 "
                          "of the other workloads")
+    ap.add_argument("--make-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU work: write profiles/traffic.json from the output directories of the two counter "
+                         "runs (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE) of this script with --no-cpu --no-learned "
+                         "--precision-steps 0 --steps 3 --warmup 1 --reps 1 --copy-calibration")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (reference for byte counters)")
     return ap.parse_args()
@@ -107,6 +111,74 @@ def traffic_from_profiles(key):
 # device headers they include
 KERNEL_SOURCES = ("sllbm_tile.hip", "sllbm_csr_kernel.hip", "sllbm_kernels.hip", "sllbm_device_common.h",
                   "sllbm_kernels.h")
+
+
+# the workload lines whose dominant kernel's HBM traffic profiles/traffic.json records, in the
+# order `bench.py --no-cpu --no-learned --precision-steps 0` runs them
+TRAFFIC_LEGS = ("tgv45_f64", "tgv45_f32", "tgv_f64", "tgv_f32", "ogrid_f32", "ogrid_f64", "ogrid19_f32", "ogrid19_f64",
+                "c1r_f64", "c1r_f32", "c4_f32", "c4pr_f32", "c1rq19_f64", "c1rq19_f32", "c4paper_f32")
+
+
+def make_traffic(fetch_dir, write_dir, out_path=None):
+    """Write profiles/traffic.json from two rocprofv3 --pmc runs, FETCH_SIZE then WRITE_SIZE
+    (KiB per dispatch), of `bench.py --no-cpu --no-learned --precision-steps 0 --steps 3
+    --warmup 1 --reps 1 --copy-calibration`: per workload line (split at each k_init
+    dispatch: every line starts with sllbm_init_equilibrium) the mean bytes per launch of its
+    dominant streaming kernel, each counter scaled by what it reads for the run's 1 GiB
+    device-to-device copy, tagged with the hash of the kernel sources."""
+    import csv
+    import glob
+    import re
+
+    def load(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not f:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        rows = {}
+        for r in csv.DictReader(open(f[0])):
+            if r["Counter_Name"] != counter:
+                continue
+            rows.setdefault(int(r["Dispatch_Id"]), [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+        return [(k, v[0], v[1]) for k, v in sorted(rows.items())]
+
+    fe, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    if len(fe) != len(wr):
+        raise SystemExit(f"the two runs dispatched {len(fe)} and {len(wr)} kernels")
+    copy_f = [v for _, n, v in fe if "copyBuffer" in n]
+    copy_w = [v for _, n, v in wr if "copyBuffer" in n]
+    if not copy_f or not copy_w:
+        raise SystemExit("no 1 GiB copy in the runs (--copy-calibration)")
+    gib = 1 << 30
+    ff, fw = gib / (max(copy_f) * 1024), gib / (max(copy_w) * 1024)
+    segs, cur = [], None
+    for (_, n, f), (_, _, w) in zip(fe, wr):
+        if "k_init" in n:
+            cur = []
+            segs.append(cur)
+        if cur is not None and "copyBuffer" not in n:
+            cur.append((n, f, w))
+    if len(segs) != len(TRAFFIC_LEGS):
+        raise SystemExit(f"{len(segs)} workload lines in the runs, {len(TRAFFIC_LEGS)} expected")
+    h = kernel_source_hash()
+    res = {"_note": "HBM bytes per launch of each workload's dominant kernel: FETCH_SIZE and WRITE_SIZE (KiB per "
+                    "dispatch, rocprofv3 --pmc, one counter per run) scaled by what the same counters read for a 1 GiB "
+                    "device copy (fetch factor %.3f, write factor %.3f); kernel_source_hash covers the step kernels' "
+                    "sources and device headers (bench.py KERNEL_SOURCES) at the time of the counter runs" % (ff, fw)}
+    for key, seg in zip(TRAFFIC_LEGS, segs):
+        names = {}
+        for n, f, w in seg:
+            if re.search(r"k_step_(tile|csr)|k_stream_col", n):
+                names.setdefault(n, []).append((f, w))
+        n, vals = max(names.items(), key=lambda kv: sum(a for a, b in kv[1]))
+        fm = sum(a for a, b in vals) / len(vals) * 1024 * ff
+        wm = sum(b for a, b in vals) / len(vals) * 1024 * fw
+        short = re.sub(r"\(.*", "", n).replace("void ", "")
+        res[key] = {"kernel": short, "bytes_per_launch": int(round(fm)) + int(round(wm)), "read_bytes": int(round(fm)),
+                    "write_bytes": int(round(wm)), "kernel_source_hash": h, "dispatches": len(vals)}
+        print(key, short, len(vals), round(fm / 1e9, 3), round(wm / 1e9, 3))
+    out_path = out_path or os.path.join(ROOT, "profiles", "traffic.json")
+    with open(out_path, "w") as fh:
+        json.dump(res, fh, indent=1)
 
 
 def kernel_source_hash():
@@ -786,6 +858,9 @@ def main():
     global REPS
     args = parse()
     REPS = max(1, args.reps)
+    if args.make_traffic:
+        make_traffic(*args.make_traffic)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))

@@ -159,15 +159,21 @@ typedef struct {
   int64_t table_bytes;       /* device bytes of the interpolation tables */
   int has_device;            /* 1 if the tables are on a GPU */
   int kernel;                /* step kernel in use: 0 tensor-product per-node gather,
-                                1 CSR (curvilinear), 2 tensor-product LDS-tiled */
+                                1 CSR (curvilinear), 2 tensor-product LDS-tiled, 3 the same
+                                with velocity-split 3D steps (see sllbm_plan_select_kernel) */
 } sllbm_plan_info_t;
 int sllbm_plan_info(sllbm_plan p, sllbm_plan_info_t *info);
 /* Choose the step kernel of a tensor-product plan: 0 automatic (tiled when it applies and the
- * mesh has at least 256 tiles, one per compute unit; smaller meshes step faster on the gather
- * kernel),
+ * mesh has at least 256 tiles, one per compute unit, with velocity-split steps where those
+ * apply; smaller meshes step faster on the gather kernel),
  * 1 the per-node gather kernel, 2 the LDS-tiled kernel (SLLBM_EUNSUPPORTED when a
- * departure stencil leaves the one-cell halo the tile stages, e.g. CFL > 1).  Both
- * compute the same step; the choice exists for testing and measurement. */
+ * departure stencil leaves the one-cell halo the tile stages, e.g. CFL > 1), 3 the tiled
+ * kernel with velocity-split 3D steps: the step of Sec. 3.1 as a streaming launch with one
+ * velocity per workgroup, walking each departure plane once along z, and a launch that forms
+ * the moments from a node's streamed values held in registers and relaxes them
+ * (SLLBM_EUNSUPPORTED unless the plan is 3D, periodic on every axis, on a 45-velocity set and
+ * tiled-eligible; learned steps keep the tiled kernel).  All compute the same step; the
+ * choice exists for testing and measurement. */
 int sllbm_plan_select_kernel(sllbm_plan p, int kernel);
 /* Per-kernel timing of a plan's launches (for measurement, not part of the method).
  * enable = 1 clears the counters and starts recording a HIP event pair around every

@@ -102,6 +102,30 @@ int require_device(const sllbm_plan_s *P) {
   return SLLBM_OK;
 }
 
+// z chunk (cells) of the velocity-split 3D step: the work items (x-y tiles x chunks x
+// velocities) should fill whole rounds of two workgroups per compute unit, and each chunk
+// re-reads about half a cell of departure planes beyond its own; the chunk with the best
+// product of the two
+int col_chunk_cells(const Mesh &m, int Q, int cpt) {
+  const int P = m.p, ncz = m.N[2] / P;
+  const int64_t tiles = (int64_t)((m.N[0] + 23) / 24) * ((m.N[1] + 24 * cpt - 1) / (24 * cpt));
+  const double slots = 256.0 * 2.0;
+  int best = 0;
+  double best_eff = -1.0;
+  // (a periodic axis must be longer than a chunk and its halo)
+  for (int zc = 1; zc <= ncz - 2 && zc * P <= kColZMax; zc++) {
+    const int nzc = (ncz + zc - 1) / zc;
+    const double rounds = (double)(tiles * Q * nzc) / slots;
+    const double planes = zc * P;
+    const double eff = rounds / std::ceil(rounds) * planes / (planes + 0.5 * (P + 1));
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = zc;
+    }
+  }
+  return best;
+}
+
 }  // namespace
 
 namespace sllbm {
@@ -177,6 +201,21 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
       P->tile_auto = ntiles >= kTileMinTiles ? 1 : 0;
     }
     for (int id : t.tab_reg) P->tile_tabs = std::max(P->tile_tabs, id + 1);
+    if (P->tile_ok && m.dim == 3 && col_q_supported(V.Q)) {
+      // the widest tile that applies (FP32: two columns per thread, else one)
+      for (int cpt = col_cpt(prec == SLLBM_F32 ? 4 : 8); cpt >= 1 && !P->col_ok; cpt--) {
+        const int zc = col_chunk_cells(m, V.Q, cpt);
+        int cx = 0, cy = 0, L = 0;
+        if (m.p == 2) cx = ColShape<2>::CX, cy = cpt * ColShape<2>::CY, L = kColWin<2>;
+        if (m.p == 3) cx = ColShape<3>::CX, cy = cpt * ColShape<3>::CY, L = kColWin<3>;
+        if (m.p == 4) cx = ColShape<4>::CX, cy = cpt * ColShape<4>::CY, L = kColWin<4>;
+        if (zc > 0 && L > 0 && col_eligible(m, t, cx, cy, zc, L)) {
+          P->col_ok = 1;
+          P->col_zc = zc;
+          P->col_cpt = cpt;
+        }
+      }
+    }
   }
 
   // velocity constants: zeta x,y,z, xi = zeta/sqrt(T0), |xi|^2, w
@@ -304,15 +343,17 @@ extern "C" int sllbm_plan_info(sllbm_plan P, sllbm_plan_info_t *info) {
   info->n_thermal_nodes = P->n_thermal;
   info->table_bytes = P->table_bytes;
   info->has_device = P->has_device;
-  info->kernel = P->kernel == 1 ? 1 : (P->use_tile() ? 2 : 0);
+  info->kernel = P->kernel == 1 ? 1 : (P->use_col() ? 3 : (P->use_tile() ? 2 : 0));
   return SLLBM_OK;
 }
 
 extern "C" int sllbm_plan_select_kernel(sllbm_plan P, int kernel) {
   if (!P) return fail(SLLBM_EINVAL, "plan_select_kernel: plan is NULL");
-  if (kernel < 0 || kernel > 2) return fail(SLLBM_EINVAL, "plan_select_kernel: kernel must be 0, 1 or 2");
+  if (kernel < 0 || kernel > 3) return fail(SLLBM_EINVAL, "plan_select_kernel: kernel must be 0, 1, 2 or 3");
   if (kernel == 2 && !P->tile_ok)
     return fail(SLLBM_EUNSUPPORTED, "plan_select_kernel: the tiled kernel does not apply to this plan");
+  if (kernel == 3 && !P->col_ok)
+    return fail(SLLBM_EUNSUPPORTED, "plan_select_kernel: the velocity-split 3D step does not apply to this plan");
   P->kernel_choice = kernel;
   return SLLBM_OK;
 }

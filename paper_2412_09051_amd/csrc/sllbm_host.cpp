@@ -773,4 +773,38 @@ bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]) {
   return true;
 }
 
+bool col_eligible(const Mesh &m, const HostTables &t, int cx, int cy, int zc, int L) {
+  const int P = m.p;
+  if (m.dim != 3 || t.nfaces != 0) return false;
+  for (int a = 0; a < 3; a++)
+    if (!m.periodic(a)) return false;
+  const int c[3] = {cx, cy, zc};
+  if (!tile_eligible(m, t, c)) return false;
+  // along z: the kernel emits output plane k of a chunk after source plane k + D of the
+  // chunk's departure region, D the largest lag of a stencil's last plane behind its output
+  // plane; stencil plane j of k then sits lag = k + D - (its first plane) planes back
+  const int Q = (int)(t.tab_reg.size() / 3), N = m.N[2], T = zc * P;
+  for (int q = 0; q < Q; q++) {
+    const int tb = t.tab_reg[2 * Q + q];
+    if (t.ident[2][tb]) continue;
+    for (int n0 = 0; n0 < N; n0 += T) {
+      const int v = std::min(T, N - n0);
+      std::vector<int> rel(v);
+      for (int k = 0; k < v; k++) {
+        int r = t.start[2][(size_t)tb * N + n0 + k] - n0;
+        if (r > T) r -= N;
+        else if (r < -P) r += N;
+        rel[k] = r;
+      }
+      int D = 0;
+      for (int k = 0; k < v; k++) D = std::max(D, rel[k] - rel[0] + P - k);
+      for (int k = 0; k < v; k++) {
+        const int lag = k + D - (rel[k] - rel[0]);
+        if (lag < P || lag > L - 1) return false;
+      }
+    }
+  }
+  return true;
+}
+
 }  // namespace sllbm

@@ -178,10 +178,18 @@ struct sllbm_plan_s {
   int device = -1;
   int tile_ok = 0;              // the LDS-tiled kernel applies to this plan
   int tile_tabs = 0;            // 1 + the largest table id of a regular departure point
-  int kernel_choice = 0;        // 0 auto, 1 baseline gather, 2 tiled
+  int kernel_choice = 0;        // 0 auto, 1 baseline gather, 2 tiled, 3 tiled with velocity-split 3D steps
   int tile_auto = 0;            // the automatic choice takes the tile: eligible, and at least
                                 // kTileMinTiles tiles (fewer leave most compute units idle)
-  bool use_tile() const { return tile_ok && (kernel_choice == 2 || (kernel_choice == 0 && tile_auto)); }
+  int col_ok = 0;               // the velocity-split 3D step applies (choice 3; automatic with the tile)
+  int col_zc = 0;               // its z chunk, in cells
+  int col_cpt = 1;              // its output columns per thread (the tile is that many times as long in y)
+  bool use_tile() const {
+    return tile_ok && (kernel_choice == 2 || kernel_choice == 3 || (kernel_choice == 0 && tile_auto));
+  }
+  // plain steps of the plan run the velocity-split 3D step (learned steps keep the tile, whose
+  // streaming launch leaves the node state the correction reads)
+  bool use_col() const { return col_ok && (kernel_choice == 3 || (kernel_choice == 0 && tile_auto)); }
   sllbm::DevTensorPlan tp{};
   sllbm::DevCsrPlan cp{};
   std::vector<void *> dev_allocs;
@@ -233,4 +241,9 @@ constexpr int64_t kTileMinTiles = 256;
 // True if every regular departure stencil of a cell-aligned tile of c[] cells stays in
 // the one-cell halo that the tiled kernel stages.
 bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]);
+// True if the velocity-split 3D step applies with x-y tiles of cx x cy cells and z chunks of
+// zc cells: a 3D plan periodic on every axis, every regular stencil in the one-cell halo of
+// such a tile, and along z every output plane's stencil inside the window of L planes that
+// the kernel holds when it emits that plane.
+bool col_eligible(const Mesh &m, const HostTables &t, int cx, int cy, int zc, int L);
 }  // namespace sllbm

@@ -28,6 +28,24 @@ namespace sllbm {
 #ifndef TILE_WPE
 #define TILE_WPE 4
 #endif
+#ifndef COL_WPE64
+#define COL_WPE64 5
+#endif
+#ifndef COL_WPE32
+#define COL_WPE32 5
+#endif
+#ifndef COL_PADS
+#define COL_PADS 0
+#endif
+#ifndef COL_PADX
+#define COL_PADX 0
+#endif
+#ifndef COL_PD64
+#define COL_PD64 2
+#endif
+#ifndef COL_PD32
+#define COL_PD32 2
+#endif
 
 // 2D plans with this many velocities (D2V25) run the single-pass tile kernel, at 3 waves
 // per SIMD (FP64: 168 VGPRs and a 36-byte spill, which beats 2 waves without one); so do
@@ -983,6 +1001,352 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
   }
 }
 
+// ------------------------------------------------------ velocity-split 3D step
+// A second schedule of the 3D step for plans whose node's 2Q streamed values fit in a lane's
+// registers (D3Q45): velocities are independent until the relaxation, so the streaming
+// launch takes one velocity per workgroup, on a column of output nodes (an x-y tile of
+// TX x TY nodes and a chunk of consecutive z planes).  The workgroup walks the departure
+// region's source planes along z once each: per plane it stages the x-y departure region
+// into LDS, contracts it along x (LDS) and along y (into a register per owned column), and
+// keeps the last L y-contracted planes of its column in registers; each output plane is
+// emitted from that window a fixed number of planes D after its own index (D set per
+// workgroup so that every stencil plane has arrived), so that every iteration issues the
+// same loads and stores.  The stored streamed values are then relaxed by a launch that
+// reads a node's 2Q values into registers, forms the moments and relaxes them: the step
+// reads and writes each population twice, with no node-state array and no re-staging of a
+// departure region per velocity and tile.
+//
+// Along x and y the tile is cell-aligned (24 nodes at p = 2, 3, 4); along z a chunk of
+// whole cells.  The separable contraction (x, then y, then z, each in the order of its
+// stencil) is the tiled kernel's: the streamed values are the same numbers.
+
+struct ColGrid {
+  int nt0, nt1;   // x-y tiles
+  int zc;         // output planes per z chunk (whole cells)
+  int nzc;        // chunks along z
+  int q, r;       // work items (tiles x chunks x velocities) = 8 q + r (XCD remap)
+};
+
+template <typename T, int P, int CPT, int PD, int BS, int WPE>
+__global__ void __launch_bounds__(BS, WPE) k_stream_col3d(const DevTensorPlan pl, const StepArgs sa, const ColGrid cg,
+                                                          const T *__restrict__ pin, T *__restrict__ pout) {
+  // CPT output columns per thread, TY / CPT rows apart
+  constexpr int TX = ColShape<P>::CX * P, TY = CPT * ColShape<P>::CY * P, TYC = TY / CPT;
+  constexpr int RX = TX + P + 1, RY = TY + P + 1;
+  constexpr int SST = RX + COL_PADS;         // LDS row strides of the staged and x-pass planes
+  constexpr int XST = TX + COL_PADX;
+  constexpr int SS = SST * RY;               // staged elements per plane and population (LDS)
+  constexpr int NSE = RX * RY;               // staged elements per plane and population
+  constexpr int NST = (NSE + BS - 1) / BS;
+  constexpr int XS = RY * XST;              // x-pass outputs per plane and population (LDS)
+  constexpr int NXO = RY * TX;               // x-pass outputs per plane and population
+  constexpr int NXI = (NXO + BS - 1) / BS;
+  constexpr int L = kColWin<P>;             // z window (planes held per column)
+  constexpr int ZM = kColZMax;
+  static_assert(BS >= TX * TYC, "CPT output columns per thread");
+  static_assert(BS >= TX + TY + ZM, "the set-up threads");
+  __shared__ T S[2 * SS];                    // the staged plane of f and g
+  __shared__ T X[2 * XS];                    // its x-pass output
+  __shared__ T WX[TX * (P + 1)], WY[TY * (P + 1)];
+  __shared__ int OX[TX], OY[TY];
+  __shared__ T WZ[ZM * L];
+  __shared__ int EMZ[ZM];
+
+  const int tid = threadIdx.x;
+  const int Q = pl.Q;
+  const int64_t N = pl.N;
+  const int Nx = pl.ax[0].N, Ny = pl.ax[1].N, Nz = pl.ax[2].N;
+  // XCD-aware work item: each XCD takes a contiguous range, whose consecutive items are
+  // the neighbouring x-y tiles of one (velocity, z chunk): their departure regions overlap
+  // and meet in that XCD's L2
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, jj = bid >> 3;
+  const int item = xcd * cg.q + min(xcd, cg.r) + jj;
+  const int ntl = cg.nt0 * cg.nt1;
+  const int tl = item % ntl;
+  const int rest = item / ntl;
+  const int zch = rest % cg.nzc;
+  const int i = rest / cg.nzc;
+  const int x0 = (tl % cg.nt0) * TX, y0 = (tl / cg.nt0) * TY, z0 = zch * cg.zc;
+  const int vx = min(TX, Nx - x0), vy = min(TY, Ny - y0), vz = min(cg.zc, Nz - z0);
+  const AxGeo gx = axis_geo<P>(pl.ax[0], pl.tab_reg[i], x0, vx, TX);
+  const AxGeo gy = axis_geo<P>(pl.ax[1], pl.tab_reg[Q + i], y0, vy, TY);
+  const AxGeo gz = axis_geo<P>(pl.ax[2], pl.tab_reg[2 * Q + i], z0, vz, cg.zc);
+
+  // weight rows: x (threads 0..TX-1), y (next TY), z (next ZM); positions past a partial
+  // tile take the last row (their outputs are never stored)
+  int zsr = 0, zlen = 1;
+  T wzr[P + 1];
+#pragma unroll
+  for (int j = 0; j <= P; j++) wzr[j] = T(0);
+  if (tid < TX) {
+    int off, len;
+    T w[P + 1];
+    axis_weights<T, P>(pl.ax[0], gx, x0, min(tid, vx - 1), TX, off, len, w);
+    OX[tid] = gx.ident ? tid : off;
+#pragma unroll
+    for (int j = 0; j <= P; j++) WX[tid * (P + 1) + j] = w[j];
+  } else if (tid < TX + TY) {
+    const int t = tid - TX;
+    int off, len;
+    T w[P + 1];
+    axis_weights<T, P>(pl.ax[1], gy, y0, min(t, vy - 1), TY, off, len, w);
+    OY[t] = gy.ident ? t : off;
+#pragma unroll
+    for (int j = 0; j <= P; j++) WY[t * (P + 1) + j] = w[j];
+  } else if (tid < TX + TY + ZM) {
+    const int oz = tid - TX - TY;
+    int off;
+    axis_weights<T, P>(pl.ax[2], gz, z0, min(oz, vz - 1), cg.zc, off, zlen, wzr);
+    zsr = gz.ident ? oz : off;
+    EMZ[oz] = oz < vz ? zsr + zlen - 1 - oz : 0;
+  }
+  __syncthreads();
+  // D: the largest lag between an output plane and the last plane of its stencil
+  int Dz = 0;
+  for (int oz = 0; oz < vz; oz++) Dz = max(Dz, EMZ[oz]);
+  Dz = __builtin_amdgcn_readfirstlane(Dz);
+  if (tid >= TX + TY && tid < TX + TY + ZM) {
+    // at the emission of plane oz (after source plane oz + Dz), window slot s holds source
+    // plane oz + Dz - (L - 1 - s): stencil plane zsr + j sits in slot L - 1 - lag + j
+    const int oz = tid - TX - TY;
+    const int lag = oz + Dz - zsr;
+#pragma unroll
+    for (int s = 0; s < L; s++) {
+      const int j = s - (L - 1 - lag);
+      T w = T(0);
+#pragma unroll
+      for (int jj2 = 0; jj2 <= P; jj2++)
+        if (jj2 == j && jj2 < zlen) w = wzr[jj2];
+      WZ[oz * L + s] = w;
+    }
+  }
+  __syncthreads();
+
+  const double scale = sa.scale ? *sa.scale : 1.0;
+  const __amdgpu_buffer_rsrc_t rf = buf_rsrc(pin + (size_t)i * N, N);
+  const __amdgpu_buffer_rsrc_t rg = buf_rsrc(pin + ((size_t)Q + i) * N, N);
+  const __amdgpu_buffer_rsrc_t wf = buf_rsrc(pout + (size_t)i * N, N);
+  const __amdgpu_buffer_rsrc_t wg = buf_rsrc(pout + ((size_t)Q + i) * N, N);
+  const int plane = Nx * Ny * (int)sizeof(T);   // bytes per z plane (a population holds < 2^31 bytes)
+  // this thread's staged elements: their x-y byte offset within a plane (or none) and
+  // their place in the LDS plane (-1: none)
+  int xyo[NST], sidx[NST];
+#pragma unroll
+  for (int s = 0; s < NST; s++) {
+    const int e = tid + BS * s;
+    const int rx = e % RX, ry = e / RX;
+    const bool in = e < NSE && rx < gx.R && ry < gy.R;
+    const int gxx = wrap_idx(x0 + gx.rs + rx, Nx), gyy = wrap_idx(y0 + gy.rs + ry, Ny);
+    xyo[s] = in ? (gxx + Nx * gyy) * (int)sizeof(T) : -1;
+    sidx[s] = e < NSE ? ry * SST + rx : -1;
+  }
+  // this thread's output columns and their y weights
+  const int cx = tid % TX, cyb = tid / TX;
+  bool colv[CPT];
+  int oyc[CPT], colb[CPT];
+  T wy[CPT][P + 1];
+#pragma unroll
+  for (int c = 0; c < CPT; c++) {
+    const int cy = cyb + c * TYC;
+    colv[c] = tid < TX * TYC && cx < vx && cy < vy;
+    const int ccy = min(cy, TY - 1);
+    oyc[c] = OY[ccy];
+#pragma unroll
+    for (int j = 0; j <= P; j++) wy[c][j] = WY[ccy * (P + 1) + j];
+    colb[c] = colv[c] ? (x0 + cx + Nx * (y0 + cy)) * (int)sizeof(T) : 0;
+  }
+  const int lenx = gx.ident ? 1 : P + 1, leny = gy.ident ? 1 : P + 1;
+
+  // source plane r of the region into registers (r past the region: every offset out of
+  // range, the loads return 0)
+  auto load_plane = [&](int r, T (&af)[NST], T (&ag)[NST]) __attribute__((always_inline)) {
+    const bool real = r < gz.R;
+    const int zo = wrap_idx(z0 + gz.rs + min(r, gz.R - 1), Nz) * plane;
+#pragma unroll
+    for (int s = 0; s < NST; s++) {
+      const int off = opaque_off(real && xyo[s] >= 0 ? xyo[s] + zo : kBufOutOfRange);
+      af[s] = BufLoad<T>::get(rf, off);
+      ag[s] = BufLoad<T>::get(rg, off);
+    }
+  };
+  T zf[CPT][L], zg[CPT][L];
+#pragma unroll
+  for (int c = 0; c < CPT; c++)
+#pragma unroll
+    for (int s = 0; s < L; s++) zf[c][s] = zg[c][s] = T(0);
+  // one source plane: its staged values (loaded PD planes earlier) into S, the loads of
+  // plane r + PD into the same registers, the x and y passes, the window shift and the
+  // emission of output plane r - D (out of range when there is none).  (A schedule with one
+  // barrier per plane, the x-pass of a plane beside the y-pass of the one before over double
+  // buffers, measured no faster in FP64 and 8 % slower in FP32.)
+  auto step = [&](int r, T (&af)[NST], T (&ag)[NST]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int s = 0; s < NST; s++) {
+      if (sidx[s] >= 0) {
+        S[sidx[s]] = af[s];
+        S[SS + sidx[s]] = ag[s];
+      }
+    }
+    load_plane(r + PD, af, ag);
+    __syncthreads();
+    const int Ry = gy.R;
+#pragma unroll
+    for (int n = 0; n < NXI; n++) {
+      const int it = tid + BS * n;
+      const int ry = it / TX, tx = it - ry * TX;
+      if (it < NXO && ry < Ry && tx < vx) {
+        const T *sf = S + ry * SST + OX[tx];
+        const T *w = WX + tx * (P + 1);
+        T a = 0, c2 = 0;
+#pragma unroll
+        for (int j = 0; j <= P; j++) {
+          if (j >= lenx) break;
+          a += w[j] * sf[j];
+          c2 += w[j] * sf[SS + j];
+        }
+        X[ry * XST + tx] = a;
+        X[XS + ry * XST + tx] = c2;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPT; c++) {
+      T a = 0, c2 = 0;
+      if (colv[c]) {
+        const T *xf = X + oyc[c] * XST + cx;
+#pragma unroll
+        for (int j = 0; j <= P; j++) {
+          if (j >= leny) break;
+          a += wy[c][j] * xf[j * XST];
+          c2 += wy[c][j] * xf[XS + j * XST];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s + 1 < L; s++) {
+        zf[c][s] = zf[c][s + 1];
+        zg[c][s] = zg[c][s + 1];
+      }
+      zf[c][L - 1] = a;
+      zg[c][L - 1] = c2;
+    }
+    const int k = r - Dz;                // (r < 0: the placeholders, k < 0)
+    const bool kv = k >= 0 && k < vz;
+    const T *wz = WZ + min(max(k, 0), ZM - 1) * L;
+    T of[CPT], og[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; c++) of[c] = og[c] = T(0);
+#pragma unroll
+    for (int s = 0; s < L; s++) {
+      const T w = wz[s];
+#pragma unroll
+      for (int c = 0; c < CPT; c++) {
+        of[c] += w * zf[c][s];
+        og[c] += w * zg[c][s];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; c++) {
+      const int off = opaque_off(colv[c] && kv ? colb[c] + (z0 + k) * plane : kBufOutOfRange);
+      BufStore<T>::put(wf, off, (T)(scale * (double)of[c]));
+      BufStore<T>::put(wg, off, (T)(scale * (double)og[c]));
+    }
+  };
+
+  // planes -PD .. -1 are placeholders that only issue the loads of planes 0 .. PD-1 (their
+  // values are zeros, like the window's planes before 0, and they emit nothing), so that
+  // every load is issued inside the loop in the same order: the compiler then waits for a
+  // plane's loads only, not for those of the planes after it
+  T pf[PD][NST], pg[PD][NST];
+#pragma unroll
+  for (int d = 0; d < PD; d++)
+#pragma unroll
+    for (int s = 0; s < NST; s++) pf[d][s] = pg[d][s] = T(0);
+  const int nr = max(gz.R, Dz + vz);   // source planes to walk (the last ones placeholders)
+  for (int r = -PD; r < nr; r += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; d++) step(r + d, pf[d], pg[d]);
+  }
+}
+
+// The moments and the relaxation of the velocity-split step, in place: a node's 2Q
+// streamed values are read into registers (QQ = Q at compile time), the node state formed
+// as the tiled kernel forms it (the same sums in the same order), then BGK, the Prandtl
+// term and Kupershtokh forcing as in k_relax_nodes.  Plans without bounded faces only.
+template <typename T, int QQ, int PR>
+__global__ void __launch_bounds__(kBlock, 2) k_relax_moments(const DevTensorPlan pl, const StepArgs sa,
+                                                          T *__restrict__ pop) {
+  const int64_t N = pl.N;
+  if (sa.relax_mode == 2) return;   // pure streaming: the stored values are final
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t kc = k < N ? k : N - 1;
+  T fs[QQ], gs[QQ];
+#pragma unroll
+  for (int i = 0; i < QQ; i++) {
+    fs[i] = pop[(size_t)i * N + kc];
+    gs[i] = pop[((size_t)QQ + i) * N + kc];
+  }
+  double rho = 0, j0 = 0, j1 = 0, j2 = 0, E = 0;
+#pragma unroll
+  for (int i = 0; i < QQ; i++) {
+    double vi[8];
+    vel_consts(pl.vel, i, vi);
+    const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
+    const double fv = (double)fs[i], gv = (double)gs[i];
+    rho += fv;
+    j0 += vi[0] * fv;
+    j1 += vi[1] * fv;
+    j2 += vi[2] * fv;
+    E += z2 * fv + gv;
+  }
+  // (the values through an empty asm: the compiler would otherwise keep their FP64
+  // conversions from the sums alive into the relaxation, twice the registers in FP32)
+#pragma unroll
+  for (int i = 0; i < QQ; i++) asm volatile("" : "+v"(fs[i]), "+v"(gs[i]));
+  const double r = rho;
+  const double u0 = j0 / r, u1 = j1 / r, u2 = j2 / r;
+  const double Tn = (E - r * (u0 * u0 + u1 * u1 + u2 * u2)) / (2.0 * r * sa.cv);
+  double it = 0.0;
+  if (sa.relax_mode == 0) it = 1.0 / sa.tau_bar;
+  if (sa.relax_mode == 1) {
+    const double mu = sa.mu_ref * pow(Tn / sa.T_ref, sa.mu_exp);
+    it = 1.0 / (mu / (r * Tn * sa.dt) + 0.5);
+  }
+  const EqNode e = eq_prepare(r, u0, u1, u2, Tn, sa, 3);
+  EqNode ef = e;
+  if (sa.has_force) ef = eq_forced(r, u0, u1, u2, Tn, sa, 3);
+  const double gT = Tn * sa.gbase;
+  PrTerm pt;
+  if constexpr (PR) {   // Pr != 1
+    HeatFlux hq = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < QQ; i++) {
+      double vi[8];
+      vel_consts(pl.vel, i, vi);
+      heat_flux_add(hq, vi, u0, u1, u2, (double)fs[i], (double)gs[i]);
+    }
+    pt = pr_term(hq, it, sa, 3);
+  }
+  const int off = opaque_off(k < N ? (int)k * (int)sizeof(T) : kBufOutOfRange);
+#pragma unroll
+  for (int i = 0; i < QQ; i++) {
+    double vi[8];
+    vel_consts(pl.vel, i, vi);
+    const double f = (double)fs[i], g = (double)gs[i];
+    const double fe = eq_f(e, vi);
+    double fo = f - (f - fe) * it;
+    double go = g - (g - gT * fe) * it;
+    if constexpr (PR) pr_add(pt, vi, fo, go);
+    if (sa.has_force) {
+      const double df = eq_f(ef, vi) - fe;
+      fo += df;
+      go += gT * df;
+    }
+    BufStore<T>::put(buf_rsrc(pop + (size_t)i * N, N), off, (T)fo);
+    BufStore<T>::put(buf_rsrc(pop + ((size_t)QQ + i) * N, N), off, (T)go);
+  }
+}
+
 // ------------------------------------------------------------------ launcher
 
 namespace {
@@ -1000,8 +1364,53 @@ void launch_tile2d_single(const DevTensorPlan &tp, const StepArgs &a, const Tile
                        tg, (const T *)pin, (T *)pout, nstate);
 }
 
+// velocity-split 3D step: the streaming launch (one velocity per workgroup, 576 threads: one
+// output column each), then the moments and the relaxation
+template <typename T, int P, int CPT>
+int launch_col_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
+  // a column per thread (FP64, and FP32 on meshes too short in y for two), 5 waves per SIMD:
+  // two workgroups per compute unit (at p = 4 that bound spills: 4 waves, one workgroup)
+  constexpr int TX = ColShape<P>::CX * P, TY = CPT * ColShape<P>::CY * P;
+  constexpr int BS = (TX * TY / CPT + 63) / 64 * 64;
+  constexpr int WPE = P == 4 ? 4 : (sizeof(T) == 8 ? COL_WPE64 : COL_WPE32);
+  constexpr int PD = sizeof(T) == 8 ? COL_PD64 : COL_PD32;   // planes loaded ahead
+  const DevTensorPlan &tp = Pl->tp;
+  ColGrid cg;
+  cg.nt0 = (tp.ax[0].N + TX - 1) / TX;
+  cg.nt1 = (tp.ax[1].N + TY - 1) / TY;
+  cg.zc = Pl->col_zc * P;
+  cg.nzc = (tp.ax[2].N + cg.zc - 1) / cg.zc;
+  const int64_t items = (int64_t)cg.nt0 * cg.nt1 * cg.nzc * tp.Q;
+  if (items <= 0 || items > 0x7fffffff || cg.zc > kColZMax)
+    return fail(SLLBM_EUNSUPPORTED, "velocity-split step: %lld work items, chunk %d", (long long)items, cg.zc);
+  cg.q = (int)(items / 8);
+  cg.r = (int)(items % 8);
+  {
+    ProfScope ps(Pl, "k_stream_col", s);
+    hipLaunchKernelGGL((k_stream_col3d<T, P, CPT, PD, BS, WPE>), dim3((unsigned)items), dim3(BS), 0, s, tp, a, cg,
+                       (const T *)pin, (T *)pout);
+  }
+  {
+    ProfScope ps(Pl, "k_relax_moments", s);
+    const dim3 grid((unsigned)((tp.N + kBlock - 1) / kBlock));
+    if (tp.Q != 45) return fail(SLLBM_EUNSUPPORTED, "velocity-split step: no relaxation launch for Q = %d", tp.Q);
+    if (a.pr_on)
+      hipLaunchKernelGGL((k_relax_moments<T, 45, 1>), grid, dim3(kBlock), 0, s, tp, a, (T *)pout);
+    else
+      hipLaunchKernelGGL((k_relax_moments<T, 45, 0>), grid, dim3(kBlock), 0, s, tp, a, (T *)pout);
+  }
+  return SLLBM_OK;
+}
+
 template <typename T, int D, int P, int CX, int CY, int CZ>
 int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s, bool relax) {
+  if constexpr (D == 3) {
+    if (relax && Pl->use_col()) {
+      if constexpr (sizeof(T) == 4)
+        if (Pl->col_cpt == 2) return launch_col_t<T, P, 2>(Pl, a, pin, pout, s);
+      return launch_col_t<T, P, 1>(Pl, a, pin, pout, s);
+    }
+  }
   constexpr int BS = D == 3 ? 512 : 256;   // threads per workgroup
   // 3D schedule: the skewed two-barrier one except at p = 3 in FP64, where its separate
   // y buffer takes the 12 x 12 x 6 tile to 95 KB of LDS and one workgroup per CU.  Tile

@@ -254,6 +254,35 @@ def test_tiled_kernel_eligibility_follows_the_halo_rule():
     assert S.sllbm_plan_info(S.sllbm_interp_plan(S.sllbm_mesh_build(large), vs, physl.dt))["kernel"] == 2
 
 
+def test_velocity_split_step_eligibility():
+    """The velocity-split 3D step: periodic 3D plans on the 45-velocity set that the tiled
+    kernel takes (the automatic choice from 256 tiles on); not the product set, not bounded
+    meshes, not 2D."""
+    mesh, phys = W.tgv_case(ncell=32, p=3, dt=W.TGV_DT)
+    m = S.sllbm_mesh_build(mesh)
+    q45 = S.sllbm_interp_plan(m, S.sllbm_velset_cubature(3, phys.T0), phys.dt)
+    assert S.sllbm_plan_info(q45)["kernel"] == 3
+    S.sllbm_plan_select_kernel(q45, 2)
+    assert S.sllbm_plan_info(q45)["kernel"] == 2
+    S.sllbm_plan_select_kernel(q45, 3)
+    assert S.sllbm_plan_info(q45)["kernel"] == 3
+    q32 = S.sllbm_interp_plan(m, S.sllbm_velset_cubature(3, phys.T0), phys.dt, S.SLLBM_F32)
+    assert S.sllbm_plan_info(q32)["kernel"] == 3
+    v125 = S.sllbm_interp_plan(m, S.sllbm_velset_gauss_hermite(3), phys.dt)
+    assert S.sllbm_plan_info(v125)["kernel"] == 2
+    cmesh, cphys = W.channel_case(ncell=(6, 8, 6), p=2, box=(2.0, 2.0, 1.5), cfl=0.75, T_wall=0.9, Ma_b=0.5)
+    walls = S.sllbm_interp_plan(S.sllbm_mesh_build(cmesh), S.sllbm_velset_cubature(3, cphys.T0), cphys.dt)
+    smesh, sphys = W.shear_wave_case(ncell=16, p=4)
+    flat = S.sllbm_interp_plan(S.sllbm_mesh_build(smesh), S.sllbm_velset_cubature(2, sphys.T0), sphys.dt)
+    for plan in (v125, walls, flat):
+        with pytest.raises(S.SllbmError) as e:
+            S.sllbm_plan_select_kernel(plan, 3)
+        assert e.value.code == S.SLLBM_EUNSUPPORTED
+    with pytest.raises(S.SllbmError) as e:
+        S.sllbm_plan_select_kernel(q45, 4)
+    assert e.value.code == S.SLLBM_EINVAL
+
+
 def test_profiling_needs_a_device_plan():
     mesh, phys = W.shear_wave_case(ncell=4, p=2)
     plan = S.sllbm_interp_plan(S.sllbm_mesh_build(mesh), S.sllbm_velset_gauss_hermite(2), phys.dt)

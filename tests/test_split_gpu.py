@@ -1,0 +1,165 @@
+"""The velocity-split 3D step (kernel choice 3) on periodic meshes with the reduced set D3Q45:
+one velocity per workgroup on a column of output nodes, the source planes walked once along
+z, then the moments and the relaxation from a node's streamed values held in registers.
+
+It computes the same numbers as the tiled kernel (the separable contraction in the same
+order, the same moment sums): in FP64 the populations after several steps are compared with
+the tiled kernel's bit for bit, and both with the FP64 oracle at the FP64 bar (1e-12); FP32
+storage against the tiled kernel at 1e-6 and the oracle at 1e-5 in rho, u, T.  Meshes with
+ragged x-y tiles and z chunks, mildly stretched cells along z, forcing, Pr != 1 and the
+three relaxation modes.
+"""
+import dataclasses
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from harness import GpuRun, field_errors, oracle_moments, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+TILED, SPLIT = 2, 3
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def box_case(ncell, p, stretch=0.0, **phys_kw):
+    """A periodic 2 pi box of ncell = (nx, ny, nz) cells, its z cells stretched by a factor
+    up to 1 + stretch (smooth, periodic), at the Taylor-Green time step of its smallest cell."""
+    L = 2.0 * math.pi
+    edges = [W.uniform_edges(n, 0.0, L) for n in ncell]
+    if stretch:
+        s = np.arange(ncell[2] + 1) / ncell[2]
+        z = s + stretch / (2 * math.pi) * np.sin(2 * math.pi * s) / (1 + stretch)
+        edges[2] = L * (z - z[0]) / (z[-1] - z[0])
+    mesh = W.TensorMesh(dim=3, p=p, nodes="gll", ncell=tuple(ncell), edges=edges,
+                        face_bc=[[-1, -1], [-1, -1], [-1, -1]])
+    hmin = min(float(np.min(np.diff(e))) for e in edges)
+    _, tgv = W.tgv_case(ncell=8, p=p)
+    phys = dataclasses.replace(tgv, dt=0.5 * hmin / W.ZETA_MAX_GH5, **phys_kw)
+    return mesh, phys
+
+
+def _run_pair(mesh, phys, prec, nsteps, fields=W.tgv_fields):
+    """The same initial state stepped by the tiled kernel and by the velocity-split step."""
+    runs = {}
+    for kernel in (TILED, SPLIT):
+        g = GpuRun(mesh, phys, prec, kernel, vel="cub")
+        assert g.kernel == kernel
+        rho, u, T = fields(g.coords())
+        g.init(rho, u, T)
+        g.run(nsteps)
+        runs[kernel] = g
+    return runs[TILED], runs[SPLIT]
+
+
+CASES = [
+    pytest.param(2, (14, 15, 13), 0.0, id="p2-ragged"),
+    pytest.param(3, (10, 11, 9), 0.0, id="p3-ragged"),
+    pytest.param(3, (10, 10, 12), 0.3, id="p3-stretched-z"),
+    pytest.param(4, (8, 9, 8), 0.0, id="p4-ragged"),
+]
+
+
+@pytest.mark.parametrize("p,ncell,stretch", CASES)
+def test_split_equals_tiled_fp64(p, ncell, stretch):
+    say("split vs tiled fp64", p, ncell, stretch)
+    mesh, phys = box_case(ncell, p, stretch)
+    t, s = _run_pair(mesh, phys, "f64", 6)
+    a, b = t.pop(), s.pop()
+    say("max |split - tiled|", float(np.max(np.abs(a - b))))
+    assert np.array_equal(a, b)
+
+
+# FP32 plans whose y axis holds two tiles' worth of columns run two output columns per thread
+CASES32 = CASES + [
+    pytest.param(2, (14, 26, 13), 0.0, id="p2-two-columns"),
+    pytest.param(3, (10, 18, 9), 0.3, id="p3-two-columns-stretched-z"),
+    pytest.param(4, (8, 14, 8), 0.0, id="p4-two-columns"),
+]
+
+
+@pytest.mark.parametrize("p,ncell,stretch", CASES32)
+def test_split_matches_tiled_fp32(p, ncell, stretch):
+    say("split vs tiled fp32", p, ncell, stretch)
+    mesh, phys = box_case(ncell, p, stretch)
+    t, s = _run_pair(mesh, phys, "f32", 6)
+    e = rel_err(s.pop(), t.pop())
+    say("rel err", e)
+    assert e <= 1e-6
+
+
+@pytest.mark.parametrize("variant", ["mode1", "force_pr", "mode0", "streaming"])
+def test_split_equals_tiled_physics_variants_fp64(variant):
+    """Constant forcing with Pr = 0.71 (the heat-flux term), constant tau_bar, and pure
+    streaming: each term of the relaxation launch, against the tiled kernel's."""
+    kw = {"mode1": {}, "force_pr": {"force": (0.02, -0.01, 0.005), "Pr": 0.71},
+          "mode0": {"relax_mode": 0, "tau_bar": 0.8}, "streaming": {"relax_mode": 2}}[variant]
+    say("split vs tiled fp64", variant)
+    mesh, phys = box_case((10, 11, 9), 3, **kw)
+    t, s = _run_pair(mesh, phys, "f64", 5)
+    assert np.array_equal(t.pop(), s.pop())
+
+
+def _oracle_pair(mesh, phys, prec):
+    o = oracle.TensorOracle(mesh, phys, vel=oracle.cubature_set(3, phys.T0))
+    g = GpuRun(mesh, phys, prec, SPLIT, vel="cub")
+    assert g.kernel == SPLIT
+    return o, g
+
+
+@pytest.mark.parametrize("prec,tol,nsteps,ncell", [("f64", TOL64, 20, (10, 11, 9)), ("f32", TOL32, 20, (10, 11, 9)),
+                                                   ("f32", TOL32, 20, (10, 18, 9))])
+def test_split_oracle_parity(prec, tol, nsteps, ncell):
+    say("split vs oracle", prec, nsteps, ncell)
+    mesh, phys = box_case(ncell, 3, stretch=0.3, force=(0.01, 0.0, -0.01), Pr=0.71)
+    o, g = _oracle_pair(mesh, phys, prec)
+    xyz = o.coords()
+    assert np.max(np.abs(g.coords() - xyz)) < 1e-13
+    rho, u, T = W.tgv_fields(xyz)
+    p0 = o.init(rho, u, T)
+    g.init(rho, u, T)
+    pr = o.run(p0, nsteps)
+    g.run(nsteps)
+    errs = field_errors(g.moments(), oracle_moments(o, pr))
+    say("errors", errs)
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+    if prec == "f64":
+        e = rel_err(g.pop(), pr)
+        say("pop error", e)
+        assert e <= tol
+
+
+def test_split_full_size_taylor_green_sampled():
+    """The headline mesh (96^3 nodes, p = 3, FP64, D3Q45, the 32^3-cell time step), as the
+    benchmark runs it (automatic choice): one step from the oracle's initial state, checked
+    at sampled nodes (tile and z-chunk edges among them) against the oracle node by node."""
+    mesh, phys = W.tgv_case(ncell=32, p=3, dt=W.TGV_DT)
+    o = oracle.TensorOracle(mesh, phys, vel=oracle.cubature_set(3, phys.T0))
+    g = GpuRun(mesh, phys, "f64", 0, vel="cub")
+    assert g.kernel == SPLIT
+    rho, u, T = W.tgv_fields(g.coords())
+    p0 = o.init(rho, u, T)
+    g.load(p0)
+    g.run(1)
+    got = g.pop()
+    rng = np.random.Generator(np.random.PCG64(11))
+    n = 96
+    edges = [0, 23, 24, 47, 48, 71, 72, 95]
+    special = [x + n * (y + n * z) for x in edges[::3] for y in edges[1::3] for z in (0, 47, 48, 95)]
+    nodes = np.unique(np.concatenate([rng.integers(0, o.N, 60), special]))
+    ref = o.step_nodes(p0, nodes)
+    gq = np.stack([got[nodes + q * o.N] for q in range(2 * o.Q)], axis=1)
+    e = rel_err(gq, ref)
+    say("sampled nodes", len(nodes), "pop error", e)
+    assert e <= TOL64
