@@ -775,9 +775,11 @@ bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]) {
 
 bool col_eligible(const Mesh &m, const HostTables &t, int cx, int cy, int zc, int L) {
   const int P = m.p;
-  if (m.dim != 3 || t.nfaces != 0) return false;
-  for (int a = 0; a < 3; a++)
-    if (!m.periodic(a)) return false;
+  if (m.dim != 3 || !m.periodic(2)) return false;
+  // bounded axes: x or y (their boundary layers' nodes are left to the gather kernel, as in
+  // the tiled kernel); z is walked in chunks and must be periodic
+  for (int f = 0; f < t.nfaces; f++)
+    if (t.face_axis[f] == 2) return false;
   const int c[3] = {cx, cy, zc};
   if (!tile_eligible(m, t, c)) return false;
   // along z: the kernel emits output plane k of a chunk after source plane k + D of the

@@ -242,8 +242,8 @@ constexpr int64_t kTileMinTiles = 256;
 // the one-cell halo that the tiled kernel stages.
 bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]);
 // True if the velocity-split 3D step applies with x-y tiles of cx x cy cells and z chunks of
-// zc cells: a 3D plan periodic on every axis, every regular stencil in the one-cell halo of
-// such a tile, and along z every output plane's stencil inside the window of L planes that
-// the kernel holds when it emits that plane.
+// zc cells: a 3D plan periodic along z (bounded faces on x or y only), every regular stencil
+// in the one-cell halo of such a tile, and along z every output plane's stencil inside the
+// window of L planes that the kernel holds when it emits that plane.
 bool col_eligible(const Mesh &m, const HostTables &t, int cx, int cy, int zc, int L);
 }  // namespace sllbm

@@ -1150,6 +1150,13 @@ __global__ void __launch_bounds__(BS, WPE) k_stream_col3d(const DevTensorPlan pl
   for (int c = 0; c < CPT; c++) {
     const int cy = cyb + c * TYC;
     colv[c] = tid < TX * TYC && cx < vx && cy < vy;
+    // columns in the boundary layers of a bounded face (x or y) belong to the gather kernel
+    for (int fc = 0; fc < pl.nfaces; fc++) {
+      const DevFace &F = pl.face[fc];
+      const int n3 = F.axis == 0 ? x0 + cx : y0 + cy;
+      const int l = F.side == 0 ? n3 : (F.axis == 0 ? Nx : Ny) - 1 - n3;
+      if (l < F.depth) colv[c] = false;
+    }
     const int ccy = min(cy, TY - 1);
     oyc[c] = OY[ccy];
 #pragma unroll
@@ -1272,7 +1279,8 @@ __global__ void __launch_bounds__(BS, WPE) k_stream_col3d(const DevTensorPlan pl
 // The moments and the relaxation of the velocity-split step, in place: a node's 2Q
 // streamed values are read into registers (QQ = Q at compile time), the node state formed
 // as the tiled kernel forms it (the same sums in the same order), then BGK, the Prandtl
-// term and Kupershtokh forcing as in k_relax_nodes.  Plans without bounded faces only.
+// term and Kupershtokh forcing as in k_relax_nodes.  Nodes in the boundary layers of a
+// bounded face are left as the gather kernel stored them.
 template <typename T, int QQ, int PR>
 __global__ void __launch_bounds__(kBlock, 2) k_relax_moments(const DevTensorPlan pl, const StepArgs sa,
                                                           T *__restrict__ pop) {
@@ -1291,6 +1299,9 @@ __global__ void __launch_bounds__(kBlock, 2) k_relax_moments(const DevTensorPlan
   for (int i = 0; i < QQ; i++) {
     double vi[8];
     vel_consts(pl.vel, i, vi);
+    // (the velocity's constants tied to the arrival of its values: the compiler would
+    // otherwise compute their products for every velocity ahead of the loads and hold them)
+    asm volatile("" : "+s"(vi[0]), "+s"(vi[1]), "+s"(vi[2]) : "v"(fs[i]), "v"(gs[i]));
     const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
     const double fv = (double)fs[i], gv = (double)gs[i];
     rho += fv;
@@ -1327,7 +1338,19 @@ __global__ void __launch_bounds__(kBlock, 2) k_relax_moments(const DevTensorPlan
     }
     pt = pr_term(hq, it, sa, 3);
   }
-  const int off = opaque_off(k < N ? (int)k * (int)sizeof(T) : kBufOutOfRange);
+  // nodes in the boundary layers of a bounded face (x or y) were relaxed by the gather kernel
+  // (a population plane holds < 2^31 bytes: node indices fit 32 bits)
+  bool act = k < N;
+  if (pl.nfaces > 0) {
+    const int Nx = pl.ax[0].N, Ny = pl.ax[1].N, k32 = (int)kc;
+    for (int fc = 0; fc < pl.nfaces; fc++) {
+      const DevFace &F = pl.face[fc];
+      const int n3 = F.axis == 0 ? k32 % Nx : (k32 / Nx) % Ny;
+      const int l = F.side == 0 ? n3 : (F.axis == 0 ? Nx : Ny) - 1 - n3;
+      if (l < F.depth) act = false;
+    }
+  }
+  const int off = opaque_off(act ? (int)k * (int)sizeof(T) : kBufOutOfRange);
 #pragma unroll
   for (int i = 0; i < QQ; i++) {
     double vi[8];

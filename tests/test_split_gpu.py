@@ -110,6 +110,79 @@ def test_split_equals_tiled_physics_variants_fp64(variant):
     assert np.array_equal(t.pop(), s.pop())
 
 
+# ------------------------------------------------------------------ bounded meshes
+
+def _channel(prec_kw=None):
+    """The channel sub-box long enough in x and z for the 24-node tiles: tanh walls in y,
+    isothermal walls at 0.9, power-law viscosity, Kupershtokh force, Pr 0.7, D3Q45 at a CFL
+    of 0.75 on the product rule's largest abscissa."""
+    mesh, phys = W.channel_case(ncell=(14, 8, 14), p=2, box=(2.0, 2.0, 1.5), cfl=0.75, T_wall=0.9, Ma_b=0.5)
+    return mesh, dataclasses.replace(phys, Pr=0.7)
+
+
+def _channel_fields(x):
+    return W.channel_fields(x, box=(2.0, 2.0, 1.5), Ma_b=0.5, T_wall=1.0)
+
+
+def _mixing():
+    """The mixing layer's moving equilibrium walls in y, 14 x 8 x 14 cells, p = 2."""
+    return W.mixing_layer_case(ncell=(14, 8, 14), p=2, Ma_c=0.7, box=(14 * 2.5 * W.MIX_DTHETA0, 8 * 2.75 * W.MIX_DTHETA0,
+                                                                    14 * 1.5 * W.MIX_DTHETA0))
+
+
+def _mixing_fields(x):
+    return W.mixing_layer_fields(x, Ma_c=0.7, box=(14 * 2.5 * W.MIX_DTHETA0, 8 * 2.75 * W.MIX_DTHETA0,
+                                                  14 * 1.5 * W.MIX_DTHETA0))
+
+
+def _run_pair_fix(mesh, phys, prec, nsteps, fields, fix_every):
+    runs = {}
+    for kernel in (TILED, SPLIT):
+        g = GpuRun(mesh, phys, prec, kernel, vel="cub")
+        assert g.kernel == kernel
+        rho, u, T = fields(g.coords())
+        g.init(rho, u, T)
+        mref = g.moments(totals=True)["totals"][0] if fix_every else None
+        g.run(nsteps, mass_fix_every=fix_every, mass_ref=mref)
+        runs[kernel] = g
+    return runs[TILED], runs[SPLIT]
+
+
+@pytest.mark.parametrize("case", ["channel", "mixing"])
+def test_split_equals_tiled_bounded_fp64(case):
+    """Walls in y (thermal walls and forcing with the mass rescaling; moving equilibrium
+    walls): the boundary layers stay on the gather kernel, the interior on the split step."""
+    say("split vs tiled fp64 bounded", case)
+    mesh, phys = _channel() if case == "channel" else _mixing()
+    fields = _channel_fields if case == "channel" else _mixing_fields
+    t, s = _run_pair_fix(mesh, phys, "f64", 6, fields, 3 if case == "channel" else 0)
+    a, b = t.pop(), s.pop()
+    say("max |split - tiled|", float(np.max(np.abs(a - b))))
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_split_oracle_parity_channel(prec, tol):
+    say("split vs oracle, channel", prec)
+    mesh, phys = _channel()
+    o, g = _oracle_pair(mesh, phys, prec)
+    xyz = o.coords()
+    rho, u, T = _channel_fields(xyz)
+    p0 = o.init(rho, u, T)
+    g.init(rho, u, T)
+    mref = o.totals(p0)[0]
+    pr = o.run(p0, 20, mass_fix_every=5, mass_ref=mref)
+    g.run(20, mass_fix_every=5, mass_ref=mref)
+    errs = field_errors(g.moments(), oracle_moments(o, pr))
+    say("errors", errs)
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+    if prec == "f64":
+        e = rel_err(g.pop(), pr)
+        say("pop error", e)
+        assert e <= tol
+
+
 def _oracle_pair(mesh, phys, prec):
     o = oracle.TensorOracle(mesh, phys, vel=oracle.cubature_set(3, phys.T0))
     g = GpuRun(mesh, phys, prec, SPLIT, vel="cub")
