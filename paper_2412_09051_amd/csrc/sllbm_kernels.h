@@ -69,7 +69,8 @@ template <> struct TileShape<3, 4> { static constexpr int CX = 2, CY = 2, CZ = 2
 // The velocity-split 3D step (one velocity per workgroup on a column of output nodes, then a
 // moments-and-relaxation launch with a node's streamed values in registers): x-y tiles of
 // 24 x 24 nodes, z chunks of whole cells up to kColZMax planes, a window of kColWin<P>
-// y-contracted planes per column; the relaxation launch is compiled for these Q.
+// y-contracted planes per column; the relaxation launch is compiled for these Q (45: a node
+// per lane; 125: a node's velocities over the four waves of a workgroup).
 template <int P> struct ColShape {
   static constexpr int CX = 24 / P, CY = 24 / P;   // cells per tile along x and y
 };
@@ -78,7 +79,7 @@ template <int P> constexpr int kColWin = 3 * P - 1;
 // in y): two in FP32, one in FP64 (where a second column's window would halve the occupancy)
 constexpr int col_cpt(int elem_bytes) { return elem_bytes == 4 ? 2 : 1; }
 constexpr int kColZMax = 96;
-constexpr bool col_q_supported(int Q) { return Q == 45; }
+constexpr bool col_q_supported(int Q) { return Q == 45 || Q == 125; }
 
 int launch_step_csr(sllbm_plan_s *P, const StepArgs &a, const void *pin, void *pout, hipStream_t s);
 // relax = false: 3D plans on the two-launch tile path stop after the streaming launch (the

@@ -1370,6 +1370,139 @@ __global__ void __launch_bounds__(kBlock, 2) k_relax_moments(const DevTensorPlan
   }
 }
 
+// The same for sets whose 2Q streamed values do not fit a lane's registers (D3V125): a
+// workgroup of NPART waves on 64 nodes, wave p holding velocities p QP .. p QP + QP - 1 of
+// them (so that the velocity index stays uniform in a wave: the constants through the scalar
+// cache, the loads coalesced over the 64 nodes); the moment sums and the heat flux of the
+// parts are exchanged through LDS and added in part order.  The sums are the same terms in
+// another order than the tiled kernel's (equal to rounding).
+template <typename T, int QQ, int NPART, int PR>
+__global__ void __launch_bounds__(64 * NPART, 2) k_relax_moments_parts(const DevTensorPlan pl, const StepArgs sa,
+                                                                        T *__restrict__ pop) {
+  constexpr int QP = (QQ + NPART - 1) / NPART;   // velocities per wave
+  __shared__ double MS[NPART][6][64];             // each part's sums (5 moments; 6 heat-flux terms)
+  if (sa.relax_mode == 2) return;   // pure streaming: the stored values are final
+  const int64_t N = pl.N;
+  const int lane = threadIdx.x & 63;
+  const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t kc = k < N ? k : N - 1;
+  const int i0 = part * QP;
+  T fs[QP], gs[QP];
+#pragma unroll
+  for (int j = 0; j < QP; j++) {
+    const int ic = min(i0 + j, QQ - 1);
+    fs[j] = pop[(size_t)ic * N + kc];
+    gs[j] = pop[((size_t)QQ + ic) * N + kc];
+  }
+  double rho = 0, j0 = 0, j1 = 0, j2 = 0, E = 0;
+#pragma unroll
+  for (int j = 0; j < QP; j++) {
+    if (i0 + j >= QQ) break;   // (uniform: the last part holds fewer velocities)
+    double vi[8];
+    vel_consts(pl.vel, i0 + j, vi);
+    asm volatile("" : "+s"(vi[0]), "+s"(vi[1]), "+s"(vi[2]) : "v"(fs[j]), "v"(gs[j]));
+    const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
+    const double fv = (double)fs[j], gv = (double)gs[j];
+    rho += fv;
+    j0 += vi[0] * fv;
+    j1 += vi[1] * fv;
+    j2 += vi[2] * fv;
+    E += z2 * fv + gv;
+  }
+#pragma unroll
+  for (int i = 0; i < QP; i++) asm volatile("" : "+v"(fs[i]), "+v"(gs[i]));
+  MS[part][0][lane] = rho;
+  MS[part][1][lane] = j0;
+  MS[part][2][lane] = j1;
+  MS[part][3][lane] = j2;
+  MS[part][4][lane] = E;
+  __syncthreads();
+  rho = j0 = j1 = j2 = E = 0;
+#pragma unroll
+  for (int q = 0; q < NPART; q++) {
+    rho += MS[q][0][lane];
+    j0 += MS[q][1][lane];
+    j1 += MS[q][2][lane];
+    j2 += MS[q][3][lane];
+    E += MS[q][4][lane];
+  }
+  const double r = rho;
+  const double u0 = j0 / r, u1 = j1 / r, u2 = j2 / r;
+  const double Tn = (E - r * (u0 * u0 + u1 * u1 + u2 * u2)) / (2.0 * r * sa.cv);
+  double it = 0.0;
+  if (sa.relax_mode == 0) it = 1.0 / sa.tau_bar;
+  if (sa.relax_mode == 1) {
+    const double mu = sa.mu_ref * pow(Tn / sa.T_ref, sa.mu_exp);
+    it = 1.0 / (mu / (r * Tn * sa.dt) + 0.5);
+  }
+  const EqNode e = eq_prepare(r, u0, u1, u2, Tn, sa, 3);
+  EqNode ef = e;
+  if (sa.has_force) ef = eq_forced(r, u0, u1, u2, Tn, sa, 3);
+  const double gT = Tn * sa.gbase;
+  PrTerm pt;
+  if constexpr (PR) {   // Pr != 1
+    HeatFlux hq = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < QP; j++) {
+      if (i0 + j >= QQ) break;
+      double vi[8];
+      vel_consts(pl.vel, i0 + j, vi);
+      heat_flux_add(hq, vi, u0, u1, u2, (double)fs[j], (double)gs[j]);
+    }
+    __syncthreads();   // every part has read the moment sums
+    MS[part][0][lane] = hq.f0;
+    MS[part][1][lane] = hq.f1;
+    MS[part][2][lane] = hq.f2;
+    MS[part][3][lane] = hq.g0;
+    MS[part][4][lane] = hq.g1;
+    MS[part][5][lane] = hq.g2;
+    __syncthreads();
+    hq = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < NPART; q++) {
+      hq.f0 += MS[q][0][lane];
+      hq.f1 += MS[q][1][lane];
+      hq.f2 += MS[q][2][lane];
+      hq.g0 += MS[q][3][lane];
+      hq.g1 += MS[q][4][lane];
+      hq.g2 += MS[q][5][lane];
+    }
+    pt = pr_term(hq, it, sa, 3);
+  }
+  // nodes in the boundary layers of a bounded face (x or y) were relaxed by the gather kernel
+  bool act = k < N;
+  if (pl.nfaces > 0) {
+    const int Nx = pl.ax[0].N, Ny = pl.ax[1].N, k32 = (int)kc;
+    for (int fc = 0; fc < pl.nfaces; fc++) {
+      const DevFace &F = pl.face[fc];
+      const int n3 = F.axis == 0 ? k32 % Nx : (k32 / Nx) % Ny;
+      const int l = F.side == 0 ? n3 : (F.axis == 0 ? Nx : Ny) - 1 - n3;
+      if (l < F.depth) act = false;
+    }
+  }
+  const int off = opaque_off(act ? (int)k * (int)sizeof(T) : kBufOutOfRange);
+#pragma unroll
+  for (int j = 0; j < QP; j++) {
+    const int i = i0 + j;
+    if (i >= QQ) break;
+    double vi[8];
+    vel_consts(pl.vel, i, vi);
+    const double f = (double)fs[j], g = (double)gs[j];
+    const double fe = eq_f(e, vi);
+    double fo = f - (f - fe) * it;
+    double go = g - (g - gT * fe) * it;
+    if constexpr (PR) pr_add(pt, vi, fo, go);
+    if (sa.has_force) {
+      const double df = eq_f(ef, vi) - fe;
+      fo += df;
+      go += gT * df;
+    }
+    BufStore<T>::put(buf_rsrc(pop + (size_t)i * N, N), off, (T)fo);
+    BufStore<T>::put(buf_rsrc(pop + ((size_t)QQ + i) * N, N), off, (T)go);
+  }
+}
+
 // ------------------------------------------------------------------ launcher
 
 namespace {
@@ -1415,12 +1548,22 @@ int launch_col_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pou
   }
   {
     ProfScope ps(Pl, "k_relax_moments", s);
-    const dim3 grid((unsigned)((tp.N + kBlock - 1) / kBlock));
-    if (tp.Q != 45) return fail(SLLBM_EUNSUPPORTED, "velocity-split step: no relaxation launch for Q = %d", tp.Q);
-    if (a.pr_on)
-      hipLaunchKernelGGL((k_relax_moments<T, 45, 1>), grid, dim3(kBlock), 0, s, tp, a, (T *)pout);
-    else
-      hipLaunchKernelGGL((k_relax_moments<T, 45, 0>), grid, dim3(kBlock), 0, s, tp, a, (T *)pout);
+    if (tp.Q == 45) {   // a node per lane
+      const dim3 grid((unsigned)((tp.N + kBlock - 1) / kBlock));
+      if (a.pr_on)
+        hipLaunchKernelGGL((k_relax_moments<T, 45, 1>), grid, dim3(kBlock), 0, s, tp, a, (T *)pout);
+      else
+        hipLaunchKernelGGL((k_relax_moments<T, 45, 0>), grid, dim3(kBlock), 0, s, tp, a, (T *)pout);
+    } else if (tp.Q == 125) {   // 64 nodes per workgroup, their velocities over four waves
+      constexpr int NPART = 4;
+      const dim3 grid((unsigned)((tp.N + 63) / 64));
+      if (a.pr_on)
+        hipLaunchKernelGGL((k_relax_moments_parts<T, 125, NPART, 1>), grid, dim3(64 * NPART), 0, s, tp, a, (T *)pout);
+      else
+        hipLaunchKernelGGL((k_relax_moments_parts<T, 125, NPART, 0>), grid, dim3(64 * NPART), 0, s, tp, a, (T *)pout);
+    } else {
+      return fail(SLLBM_EUNSUPPORTED, "velocity-split step: no relaxation launch for Q = %d", tp.Q);
+    }
   }
   return SLLBM_OK;
 }

@@ -250,14 +250,15 @@ def test_tiled_kernel_eligibility_follows_the_halo_rule():
     assert not tiled(S.sllbm_interp_plan(m, vs, big))
     small = W.tgv_case(ncell=5, p=3)[0]       # 15 nodes per axis < tile + halo
     assert not tiled(S.sllbm_interp_plan(S.sllbm_mesh_build(small), vs, phys.dt))
-    large, physl = W.tgv_case(ncell=24, p=3)  # 72^3 nodes: 432 tiles
-    assert S.sllbm_plan_info(S.sllbm_interp_plan(S.sllbm_mesh_build(large), vs, physl.dt))["kernel"] == 2
+    large, physl = W.tgv_case(ncell=24, p=3)  # 72^3 nodes: 432 tiles (periodic: velocity-split steps)
+    assert S.sllbm_plan_info(S.sllbm_interp_plan(S.sllbm_mesh_build(large), vs, physl.dt))["kernel"] == 3
 
 
 def test_velocity_split_step_eligibility():
-    """The velocity-split 3D step: 3D plans on the 45-velocity set that the tiled kernel takes
-    (the automatic choice from 256 tiles on), periodic along z, walls on x or y allowed; not
-    the product set, not meshes shorter than a 24-node tile and its halo, not 2D."""
+    """The velocity-split 3D step: 3D plans that the tiled kernel takes
+    (the automatic choice from 256 tiles on), periodic along z, walls on x or y allowed, on the
+    45- and 125-velocity sets; not D3Q27, not meshes shorter than a 24-node tile and its halo,
+    not 2D."""
     mesh, phys = W.tgv_case(ncell=32, p=3, dt=W.TGV_DT)
     m = S.sllbm_mesh_build(mesh)
     q45 = S.sllbm_interp_plan(m, S.sllbm_velset_cubature(3, phys.T0), phys.dt)
@@ -269,7 +270,9 @@ def test_velocity_split_step_eligibility():
     q32 = S.sllbm_interp_plan(m, S.sllbm_velset_cubature(3, phys.T0), phys.dt, S.SLLBM_F32)
     assert S.sllbm_plan_info(q32)["kernel"] == 3
     v125 = S.sllbm_interp_plan(m, S.sllbm_velset_gauss_hermite(3), phys.dt)
-    assert S.sllbm_plan_info(v125)["kernel"] == 2
+    assert S.sllbm_plan_info(v125)["kernel"] == 3
+    v27 = S.sllbm_interp_plan(m, S.sllbm_velset_gauss_hermite(3, 3), phys.dt)
+    assert S.sllbm_plan_info(v27)["kernel"] == 2
     cmesh, cphys = W.channel_case(ncell=(6, 8, 6), p=2, box=(2.0, 2.0, 1.5), cfl=0.75, T_wall=0.9, Ma_b=0.5)
     walls = S.sllbm_interp_plan(S.sllbm_mesh_build(cmesh), S.sllbm_velset_cubature(3, cphys.T0), cphys.dt)
     smesh, sphys = W.shear_wave_case(ncell=16, p=4)
@@ -278,7 +281,7 @@ def test_velocity_split_step_eligibility():
     long_walls = S.sllbm_interp_plan(S.sllbm_mesh_build(lmesh), S.sllbm_velset_cubature(3, lphys.T0), lphys.dt)
     S.sllbm_plan_select_kernel(long_walls, 3)
     assert S.sllbm_plan_info(long_walls)["kernel"] == 3
-    for plan in (v125, walls, flat):
+    for plan in (v27, walls, flat):
         with pytest.raises(S.SllbmError) as e:
             S.sllbm_plan_select_kernel(plan, 3)
         assert e.value.code == S.SLLBM_EUNSUPPORTED

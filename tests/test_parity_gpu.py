@@ -27,6 +27,7 @@ def say(*a):
 
 
 GATHER, TILED = 1, 2
+SPLIT = 3
 KERNELS = [pytest.param(GATHER, id="gather"), pytest.param(TILED, id="tiled")]
 
 
@@ -262,15 +263,17 @@ def test_tgv_full_size_one_step_sampled(prec, kernel):
 
 
 def test_kernel_selection_reports_the_kernel_in_use():
-    """Automatic choice: the tile from 256 tiles up (one per compute unit), else the gather
-    kernel; an explicit choice of either where the tile applies."""
+    """Automatic choice: the tile from 256 tiles up (one per compute unit), with velocity-split
+    steps on a periodic mesh, else the gather kernel; an explicit choice of either where the
+    tile applies."""
     say("case kernel selection")
     mesh, phys = W.tgv_case(ncell=6, p=3)          # 18^3 nodes: 12 tiles
     assert GpuRun(mesh, phys, "f64").kernel == 0
     assert GpuRun(mesh, phys, "f64", TILED).kernel == TILED
     assert GpuRun(mesh, phys, "f64", GATHER).kernel == 0
     big, physb = W.tgv_case(ncell=24, p=3)         # 72^3 nodes: 6 x 6 x 12 = 432 tiles
-    assert GpuRun(big, physb, "f32").kernel == TILED
+    assert GpuRun(big, physb, "f32").kernel == SPLIT
+    assert GpuRun(big, physb, "f32", TILED).kernel == TILED
     mesh5, phys5 = W.tgv_case(ncell=5, p=3)   # 15 nodes per axis: too few for a tile + halo
     assert GpuRun(mesh5, phys5, "f64").kernel == 0
 

@@ -49,11 +49,11 @@ def box_case(ncell, p, stretch=0.0, **phys_kw):
     return mesh, phys
 
 
-def _run_pair(mesh, phys, prec, nsteps, fields=W.tgv_fields):
+def _run_pair(mesh, phys, prec, nsteps, fields=W.tgv_fields, vel="cub"):
     """The same initial state stepped by the tiled kernel and by the velocity-split step."""
     runs = {}
     for kernel in (TILED, SPLIT):
-        g = GpuRun(mesh, phys, prec, kernel, vel="cub")
+        g = GpuRun(mesh, phys, prec, kernel, vel=vel)
         assert g.kernel == kernel
         rho, u, T = fields(g.coords())
         g.init(rho, u, T)
@@ -135,10 +135,10 @@ def _mixing_fields(x):
                                                   14 * 1.5 * W.MIX_DTHETA0))
 
 
-def _run_pair_fix(mesh, phys, prec, nsteps, fields, fix_every):
+def _run_pair_fix(mesh, phys, prec, nsteps, fields, fix_every, vel="cub"):
     runs = {}
     for kernel in (TILED, SPLIT):
-        g = GpuRun(mesh, phys, prec, kernel, vel="cub")
+        g = GpuRun(mesh, phys, prec, kernel, vel=vel)
         assert g.kernel == kernel
         rho, u, T = fields(g.coords())
         g.init(rho, u, T)
@@ -236,3 +236,51 @@ def test_split_full_size_taylor_green_sampled():
     e = rel_err(gq, ref)
     say("sampled nodes", len(nodes), "pop error", e)
     assert e <= TOL64
+
+
+# ------------------------------------------------------------------ D3V125 (125 velocities)
+# The relaxation launch then spreads a node's velocities over the four waves of a workgroup
+# and adds their moment sums in another order than the tiled kernel: equal to rounding.
+
+@pytest.mark.parametrize("p,ncell,stretch", [pytest.param(2, (14, 15, 13), 0.0, id="p2-ragged"),
+                                             pytest.param(3, (10, 18, 9), 0.3, id="p3-stretched-z")])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-6)])
+def test_split_d3v125_matches_tiled(p, ncell, stretch, prec, tol):
+    say("split vs tiled d3v125", p, ncell, prec)
+    mesh, phys = box_case(ncell, p, stretch, force=(0.01, 0.0, -0.01), Pr=0.71)
+    t, s = _run_pair(mesh, phys, prec, 6, vel="gh")
+    e = rel_err(s.pop(), t.pop())
+    say("rel err", e)
+    assert e <= tol
+
+
+def test_split_d3v125_channel_matches_tiled():
+    say("split vs tiled d3v125 channel fp64")
+    mesh, phys = _channel()
+    t, s = _run_pair_fix(mesh, phys, "f64", 6, _channel_fields, 3, vel="gh")
+    e = rel_err(s.pop(), t.pop())
+    say("rel err", e)
+    assert e <= 1e-13
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_split_d3v125_oracle_parity(prec, tol):
+    say("split vs oracle d3v125", prec)
+    mesh, phys = box_case((10, 11, 9), 3, stretch=0.3, force=(0.01, 0.0, -0.01), Pr=0.71)
+    o = oracle.TensorOracle(mesh, phys)
+    g = GpuRun(mesh, phys, prec, SPLIT)
+    assert g.kernel == SPLIT and g.Q == 125
+    xyz = o.coords()
+    rho, u, T = W.tgv_fields(xyz)
+    p0 = o.init(rho, u, T)
+    g.init(rho, u, T)
+    pr = o.run(p0, 20)
+    g.run(20)
+    errs = field_errors(g.moments(), oracle_moments(o, pr))
+    say("errors", errs)
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+    if prec == "f64":
+        e = rel_err(g.pop(), pr)
+        say("pop error", e)
+        assert e <= tol
