@@ -102,28 +102,25 @@ int require_device(const sllbm_plan_s *P) {
   return SLLBM_OK;
 }
 
-// z chunk (cells) of the velocity-split 3D step: the work items (x-y tiles x chunks x
-// velocities) should fill whole rounds of two workgroups per compute unit, and each chunk
-// re-reads about half a cell of departure planes beyond its own; the chunk with the best
-// product of the two
+// z chunk (cells) of the velocity-split 3D step: the axis is cut into nzc equal chunks, as
+// few as give at least two rounds of work items (x-y tiles x chunks x velocities) over two
+// workgroups per compute unit: longer chunks re-read fewer departure planes beyond their own
+// and fill and drain their pipelines less often.  (Measured on the 96^3 Taylor-Green mesh
+// and the 128 x 96 x 64 channel: chunks of a smaller count than this, or chunks much shorter,
+// were slower; a tiny last chunk beside long ones too.)
 int col_chunk_cells(const Mesh &m, int Q, int cpt) {
   const int P = m.p, ncz = m.N[2] / P;
   const int64_t tiles = (int64_t)((m.N[0] + 23) / 24) * ((m.N[1] + 24 * cpt - 1) / (24 * cpt));
-  const double slots = 256.0 * 2.0;
-  int best = 0;
-  double best_eff = -1.0;
-  // (a periodic axis must be longer than a chunk and its halo)
-  for (int zc = 1; zc <= ncz - 2 && zc * P <= kColZMax; zc++) {
-    const int nzc = (ncz + zc - 1) / zc;
-    const double rounds = (double)(tiles * Q * nzc) / slots;
-    const double planes = zc * P;
-    const double eff = rounds / std::ceil(rounds) * planes / (planes + 0.5 * (P + 1));
-    if (eff > best_eff + 1e-9) {
-      best_eff = eff;
-      best = zc;
-    }
+  const int64_t slots = 256 * 2;
+  int last = 0;
+  for (int nzc = 1; nzc <= ncz; nzc++) {
+    const int zc = (ncz + nzc - 1) / nzc;
+    // (a periodic axis must be longer than a chunk and its halo)
+    if (zc > ncz - 2 || zc * P > kColZMax || (ncz + zc - 1) / zc != nzc) continue;
+    last = zc;
+    if (tiles * Q * nzc >= 2 * slots) return zc;
   }
-  return best;
+  return last;
 }
 
 }  // namespace

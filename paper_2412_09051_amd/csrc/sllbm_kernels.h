@@ -69,8 +69,8 @@ template <> struct TileShape<3, 4> { static constexpr int CX = 2, CY = 2, CZ = 2
 // The velocity-split 3D step (one velocity per workgroup on a column of output nodes, then a
 // moments-and-relaxation launch with a node's streamed values in registers): x-y tiles of
 // 24 x 24 nodes, z chunks of whole cells up to kColZMax planes, a window of kColWin<P>
-// y-contracted planes per column; the relaxation launch is compiled for these Q (45: a node
-// per lane; 125: a node's velocities over the four waves of a workgroup).
+// y-contracted planes per column; the relaxation launch (a node's velocities over the waves
+// of a workgroup) is compiled for these Q.
 template <int P> struct ColShape {
   static constexpr int CX = 24 / P, CY = 24 / P;   // cells per tile along x and y
 };

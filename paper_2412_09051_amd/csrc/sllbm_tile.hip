@@ -1012,9 +1012,9 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
 // emitted from that window a fixed number of planes D after its own index (D set per
 // workgroup so that every stencil plane has arrived), so that every iteration issues the
 // same loads and stores.  The stored streamed values are then relaxed by a launch that
-// reads a node's 2Q values into registers, forms the moments and relaxes them: the step
-// reads and writes each population twice, with no node-state array and no re-staging of a
-// departure region per velocity and tile.
+// reads a node's 2Q values into the registers of a few waves, forms the moments and relaxes
+// them: the step reads and writes each population twice, with no node-state array and no
+// re-staging of a departure region per velocity and tile.
 //
 // Along x and y the tile is cell-aligned (24 nodes at p = 2, 3, 4); along z a chunk of
 // whole cells.  The separable contraction (x, then y, then z, each in the order of its
@@ -1276,108 +1276,16 @@ __global__ void __launch_bounds__(BS, WPE) k_stream_col3d(const DevTensorPlan pl
   }
 }
 
-// The moments and the relaxation of the velocity-split step, in place: a node's 2Q
-// streamed values are read into registers (QQ = Q at compile time), the node state formed
-// as the tiled kernel forms it (the same sums in the same order), then BGK, the Prandtl
-// term and Kupershtokh forcing as in k_relax_nodes.  Nodes in the boundary layers of a
-// bounded face are left as the gather kernel stored them.
-template <typename T, int QQ, int PR>
-__global__ void __launch_bounds__(kBlock, 2) k_relax_moments(const DevTensorPlan pl, const StepArgs sa,
-                                                          T *__restrict__ pop) {
-  const int64_t N = pl.N;
-  if (sa.relax_mode == 2) return;   // pure streaming: the stored values are final
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t kc = k < N ? k : N - 1;
-  T fs[QQ], gs[QQ];
-#pragma unroll
-  for (int i = 0; i < QQ; i++) {
-    fs[i] = pop[(size_t)i * N + kc];
-    gs[i] = pop[((size_t)QQ + i) * N + kc];
-  }
-  double rho = 0, j0 = 0, j1 = 0, j2 = 0, E = 0;
-#pragma unroll
-  for (int i = 0; i < QQ; i++) {
-    double vi[8];
-    vel_consts(pl.vel, i, vi);
-    // (the velocity's constants tied to the arrival of its values: the compiler would
-    // otherwise compute their products for every velocity ahead of the loads and hold them)
-    asm volatile("" : "+s"(vi[0]), "+s"(vi[1]), "+s"(vi[2]) : "v"(fs[i]), "v"(gs[i]));
-    const double z2 = vi[0] * vi[0] + vi[1] * vi[1] + vi[2] * vi[2];
-    const double fv = (double)fs[i], gv = (double)gs[i];
-    rho += fv;
-    j0 += vi[0] * fv;
-    j1 += vi[1] * fv;
-    j2 += vi[2] * fv;
-    E += z2 * fv + gv;
-  }
-  // (the values through an empty asm: the compiler would otherwise keep their FP64
-  // conversions from the sums alive into the relaxation, twice the registers in FP32)
-#pragma unroll
-  for (int i = 0; i < QQ; i++) asm volatile("" : "+v"(fs[i]), "+v"(gs[i]));
-  const double r = rho;
-  const double u0 = j0 / r, u1 = j1 / r, u2 = j2 / r;
-  const double Tn = (E - r * (u0 * u0 + u1 * u1 + u2 * u2)) / (2.0 * r * sa.cv);
-  double it = 0.0;
-  if (sa.relax_mode == 0) it = 1.0 / sa.tau_bar;
-  if (sa.relax_mode == 1) {
-    const double mu = sa.mu_ref * pow(Tn / sa.T_ref, sa.mu_exp);
-    it = 1.0 / (mu / (r * Tn * sa.dt) + 0.5);
-  }
-  const EqNode e = eq_prepare(r, u0, u1, u2, Tn, sa, 3);
-  EqNode ef = e;
-  if (sa.has_force) ef = eq_forced(r, u0, u1, u2, Tn, sa, 3);
-  const double gT = Tn * sa.gbase;
-  PrTerm pt;
-  if constexpr (PR) {   // Pr != 1
-    HeatFlux hq = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int i = 0; i < QQ; i++) {
-      double vi[8];
-      vel_consts(pl.vel, i, vi);
-      heat_flux_add(hq, vi, u0, u1, u2, (double)fs[i], (double)gs[i]);
-    }
-    pt = pr_term(hq, it, sa, 3);
-  }
-  // nodes in the boundary layers of a bounded face (x or y) were relaxed by the gather kernel
-  // (a population plane holds < 2^31 bytes: node indices fit 32 bits)
-  bool act = k < N;
-  if (pl.nfaces > 0) {
-    const int Nx = pl.ax[0].N, Ny = pl.ax[1].N, k32 = (int)kc;
-    for (int fc = 0; fc < pl.nfaces; fc++) {
-      const DevFace &F = pl.face[fc];
-      const int n3 = F.axis == 0 ? k32 % Nx : (k32 / Nx) % Ny;
-      const int l = F.side == 0 ? n3 : (F.axis == 0 ? Nx : Ny) - 1 - n3;
-      if (l < F.depth) act = false;
-    }
-  }
-  const int off = opaque_off(act ? (int)k * (int)sizeof(T) : kBufOutOfRange);
-#pragma unroll
-  for (int i = 0; i < QQ; i++) {
-    double vi[8];
-    vel_consts(pl.vel, i, vi);
-    const double f = (double)fs[i], g = (double)gs[i];
-    const double fe = eq_f(e, vi);
-    double fo = f - (f - fe) * it;
-    double go = g - (g - gT * fe) * it;
-    if constexpr (PR) pr_add(pt, vi, fo, go);
-    if (sa.has_force) {
-      const double df = eq_f(ef, vi) - fe;
-      fo += df;
-      go += gT * df;
-    }
-    BufStore<T>::put(buf_rsrc(pop + (size_t)i * N, N), off, (T)fo);
-    BufStore<T>::put(buf_rsrc(pop + ((size_t)QQ + i) * N, N), off, (T)go);
-  }
-}
-
-// The same for sets whose 2Q streamed values do not fit a lane's registers (D3V125): a
-// workgroup of NPART waves on 64 nodes, wave p holding velocities p QP .. p QP + QP - 1 of
-// them (so that the velocity index stays uniform in a wave: the constants through the scalar
-// cache, the loads coalesced over the 64 nodes); the moment sums and the heat flux of the
-// parts are exchanged through LDS and added in part order.  The sums are the same terms in
-// another order than the tiled kernel's (equal to rounding).
+// The moments and the relaxation of the velocity-split step, in place: a workgroup of NPART
+// waves on 64 nodes, wave p holding the streamed values of velocities p QP .. p QP + QP - 1 of
+// them in registers (so that the velocity index stays uniform in a wave: the constants
+// through the scalar cache, the loads coalesced over the 64 nodes); the moment sums and the
+// heat flux of the parts are exchanged through LDS and added in part order, then each wave
+// relaxes its velocities (BGK, the Prandtl term and Kupershtokh forcing as in k_relax_nodes).
+// The sums are the tiled kernel's terms, added in another order (equal to rounding).  Nodes
+// in the boundary layers of a bounded face are left as the gather kernel stored them.
 template <typename T, int QQ, int NPART, int PR>
-__global__ void __launch_bounds__(64 * NPART, 2) k_relax_moments_parts(const DevTensorPlan pl, const StepArgs sa,
+__global__ void __launch_bounds__(64 * NPART, 2) k_relax_moments(const DevTensorPlan pl, const StepArgs sa,
                                                                         T *__restrict__ pop) {
   constexpr int QP = (QQ + NPART - 1) / NPART;   // velocities per wave
   __shared__ double MS[NPART][6][64];             // each part's sums (5 moments; 6 heat-flux terms)
@@ -1548,19 +1456,23 @@ int launch_col_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pou
   }
   {
     ProfScope ps(Pl, "k_relax_moments", s);
-    if (tp.Q == 45) {   // a node per lane
-      const dim3 grid((unsigned)((tp.N + kBlock - 1) / kBlock));
+    // 64 nodes per workgroup, their velocities over the waves (FP64: 4, FP32: 2 at Q = 45;
+    // 4 at Q = 125).  Measured on the 96^3 Taylor-Green mesh against a node per lane: FP64
+    // D3Q45 0.268 -> 0.250 ms, FP32 0.152 -> 0.119 ms; the channel's D3Q45 set-up at Pr 0.7,
+    // where a node per lane spilled, 1.51 -> 1.17 ms
+    const dim3 grid((unsigned)((tp.N + 63) / 64));
+    if (tp.Q == 45) {
+      constexpr int NPART = sizeof(T) == 8 ? 4 : 2;
       if (a.pr_on)
-        hipLaunchKernelGGL((k_relax_moments<T, 45, 1>), grid, dim3(kBlock), 0, s, tp, a, (T *)pout);
+        hipLaunchKernelGGL((k_relax_moments<T, 45, NPART, 1>), grid, dim3(64 * NPART), 0, s, tp, a, (T *)pout);
       else
-        hipLaunchKernelGGL((k_relax_moments<T, 45, 0>), grid, dim3(kBlock), 0, s, tp, a, (T *)pout);
-    } else if (tp.Q == 125) {   // 64 nodes per workgroup, their velocities over four waves
+        hipLaunchKernelGGL((k_relax_moments<T, 45, NPART, 0>), grid, dim3(64 * NPART), 0, s, tp, a, (T *)pout);
+    } else if (tp.Q == 125) {
       constexpr int NPART = 4;
-      const dim3 grid((unsigned)((tp.N + 63) / 64));
       if (a.pr_on)
-        hipLaunchKernelGGL((k_relax_moments_parts<T, 125, NPART, 1>), grid, dim3(64 * NPART), 0, s, tp, a, (T *)pout);
+        hipLaunchKernelGGL((k_relax_moments<T, 125, NPART, 1>), grid, dim3(64 * NPART), 0, s, tp, a, (T *)pout);
       else
-        hipLaunchKernelGGL((k_relax_moments_parts<T, 125, NPART, 0>), grid, dim3(64 * NPART), 0, s, tp, a, (T *)pout);
+        hipLaunchKernelGGL((k_relax_moments<T, 125, NPART, 0>), grid, dim3(64 * NPART), 0, s, tp, a, (T *)pout);
     } else {
       return fail(SLLBM_EUNSUPPORTED, "velocity-split step: no relaxation launch for Q = %d", tp.Q);
     }

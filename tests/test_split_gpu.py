@@ -1,13 +1,13 @@
-"""The velocity-split 3D step (kernel choice 3) on periodic meshes with the reduced set D3Q45:
-one velocity per workgroup on a column of output nodes, the source planes walked once along
-z, then the moments and the relaxation from a node's streamed values held in registers.
+"""The velocity-split 3D step (kernel choice 3): one velocity per workgroup on a column of
+output nodes, the source planes walked once along z, then the moments and the relaxation from
+a node's streamed values held in the registers of the waves of a workgroup.
 
-It computes the same numbers as the tiled kernel (the separable contraction in the same
-order, the same moment sums): in FP64 the populations after several steps are compared with
-the tiled kernel's bit for bit, and both with the FP64 oracle at the FP64 bar (1e-12); FP32
-storage against the tiled kernel at 1e-6 and the oracle at 1e-5 in rho, u, T.  Meshes with
-ragged x-y tiles and z chunks, mildly stretched cells along z, forcing, Pr != 1 and the
-three relaxation modes.
+It computes the tiled kernel's numbers up to the order of the moment sums (the relaxation
+adds the sums of the waves' parts): FP64 populations after several steps agree with the tiled
+kernel's to 1e-13 and with the FP64 oracle at the FP64 bar (1e-12); FP32 storage with the tiled
+kernel to 1e-6 and with the oracle to 1e-5 in rho, u, T.  Meshes with ragged x-y tiles and z
+chunks, mildly stretched cells along z, forcing, Pr != 1, the three relaxation modes, and
+walls in y (the boundary layers stay on the gather kernel), on D3Q45 and D3V125.
 """
 import dataclasses
 import math
@@ -71,13 +71,13 @@ CASES = [
 
 
 @pytest.mark.parametrize("p,ncell,stretch", CASES)
-def test_split_equals_tiled_fp64(p, ncell, stretch):
+def test_split_matches_tiled_fp64(p, ncell, stretch):
     say("split vs tiled fp64", p, ncell, stretch)
     mesh, phys = box_case(ncell, p, stretch)
     t, s = _run_pair(mesh, phys, "f64", 6)
-    a, b = t.pop(), s.pop()
-    say("max |split - tiled|", float(np.max(np.abs(a - b))))
-    assert np.array_equal(a, b)
+    e = rel_err(s.pop(), t.pop())
+    say("rel err", e)
+    assert e <= 1e-13
 
 
 # FP32 plans whose y axis holds two tiles' worth of columns run two output columns per thread
@@ -99,7 +99,7 @@ def test_split_matches_tiled_fp32(p, ncell, stretch):
 
 
 @pytest.mark.parametrize("variant", ["mode1", "force_pr", "mode0", "streaming"])
-def test_split_equals_tiled_physics_variants_fp64(variant):
+def test_split_matches_tiled_physics_variants_fp64(variant):
     """Constant forcing with Pr = 0.71 (the heat-flux term), constant tau_bar, and pure
     streaming: each term of the relaxation launch, against the tiled kernel's."""
     kw = {"mode1": {}, "force_pr": {"force": (0.02, -0.01, 0.005), "Pr": 0.71},
@@ -107,7 +107,9 @@ def test_split_equals_tiled_physics_variants_fp64(variant):
     say("split vs tiled fp64", variant)
     mesh, phys = box_case((10, 11, 9), 3, **kw)
     t, s = _run_pair(mesh, phys, "f64", 5)
-    assert np.array_equal(t.pop(), s.pop())
+    e = rel_err(s.pop(), t.pop())
+    say("rel err", e)
+    assert e <= (0.0 if variant == "streaming" else 1e-13)
 
 
 # ------------------------------------------------------------------ bounded meshes
@@ -149,16 +151,16 @@ def _run_pair_fix(mesh, phys, prec, nsteps, fields, fix_every, vel="cub"):
 
 
 @pytest.mark.parametrize("case", ["channel", "mixing"])
-def test_split_equals_tiled_bounded_fp64(case):
+def test_split_matches_tiled_bounded_fp64(case):
     """Walls in y (thermal walls and forcing with the mass rescaling; moving equilibrium
     walls): the boundary layers stay on the gather kernel, the interior on the split step."""
     say("split vs tiled fp64 bounded", case)
     mesh, phys = _channel() if case == "channel" else _mixing()
     fields = _channel_fields if case == "channel" else _mixing_fields
     t, s = _run_pair_fix(mesh, phys, "f64", 6, fields, 3 if case == "channel" else 0)
-    a, b = t.pop(), s.pop()
-    say("max |split - tiled|", float(np.max(np.abs(a - b))))
-    assert np.array_equal(a, b)
+    e = rel_err(s.pop(), t.pop())
+    say("rel err", e)
+    assert e <= 1e-13
 
 
 @pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
@@ -239,8 +241,6 @@ def test_split_full_size_taylor_green_sampled():
 
 
 # ------------------------------------------------------------------ D3V125 (125 velocities)
-# The relaxation launch then spreads a node's velocities over the four waves of a workgroup
-# and adds their moment sums in another order than the tiled kernel: equal to rounding.
 
 @pytest.mark.parametrize("p,ncell,stretch", [pytest.param(2, (14, 15, 13), 0.0, id="p2-ragged"),
                                              pytest.param(3, (10, 18, 9), 0.3, id="p3-stretched-z")])
