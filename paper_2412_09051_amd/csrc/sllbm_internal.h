@@ -187,8 +187,8 @@ struct sllbm_plan_s {
   bool use_tile() const {
     return tile_ok && (kernel_choice == 2 || kernel_choice == 3 || (kernel_choice == 0 && tile_auto));
   }
-  // plain steps of the plan run the velocity-split 3D step (learned steps keep the tile, whose
-  // streaming launch leaves the node state the correction reads)
+  // steps of the plan run the velocity-split 3D step (a learned step: its streaming launch and
+  // a launch that stores the node state the correction reads)
   bool use_col() const { return col_ok && (kernel_choice == 3 || (kernel_choice == 0 && tile_auto)); }
   sllbm::DevTensorPlan tp{};
   sllbm::DevCsrPlan cp{};

@@ -1284,12 +1284,15 @@ __global__ void __launch_bounds__(BS, WPE) k_stream_col3d(const DevTensorPlan pl
 // relaxes its velocities (BGK, the Prandtl term and Kupershtokh forcing as in k_relax_nodes).
 // The sums are the tiled kernel's terms, added in another order (equal to rounding).  Nodes
 // in the boundary layers of a bounded face are left as the gather kernel stored them.
-template <typename T, int QQ, int NPART, int PR>
+// STATE = 1: no relaxation; the node state (rho, u, T, 1/tau_bar as [6][N] doubles) of the
+// nodes outside the boundary layers is stored instead, for a relaxation that the learned
+// correction does in its own pass.
+template <typename T, int QQ, int NPART, int PR, int STATE>
 __global__ void __launch_bounds__(64 * NPART, 2) k_relax_moments(const DevTensorPlan pl, const StepArgs sa,
-                                                                        T *__restrict__ pop) {
+                                                                        T *__restrict__ pop, double *__restrict__ nstate) {
   constexpr int QP = (QQ + NPART - 1) / NPART;   // velocities per wave
   __shared__ double MS[NPART][6][64];             // each part's sums (5 moments; 6 heat-flux terms)
-  if (sa.relax_mode == 2) return;   // pure streaming: the stored values are final
+  if (!STATE && sa.relax_mode == 2) return;   // pure streaming: the stored values are final
   const int64_t N = pl.N;
   const int lane = threadIdx.x & 63;
   const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1344,6 +1347,28 @@ __global__ void __launch_bounds__(64 * NPART, 2) k_relax_moments(const DevTensor
     const double mu = sa.mu_ref * pow(Tn / sa.T_ref, sa.mu_exp);
     it = 1.0 / (mu / (r * Tn * sa.dt) + 0.5);
   }
+  // nodes in the boundary layers of a bounded face (x or y) were relaxed by the gather kernel
+  bool act = k < N;
+  if (pl.nfaces > 0) {
+    const int Nx = pl.ax[0].N, Ny = pl.ax[1].N, k32 = (int)kc;
+    for (int fc = 0; fc < pl.nfaces; fc++) {
+      const DevFace &F = pl.face[fc];
+      const int n3 = F.axis == 0 ? k32 % Nx : (k32 / Nx) % Ny;
+      const int l = F.side == 0 ? n3 : (F.axis == 0 ? Nx : Ny) - 1 - n3;
+      if (l < F.depth) act = false;
+    }
+  }
+  if constexpr (STATE) {
+    if (part == 0 && act) {
+      nstate[k] = r;
+      nstate[N + k] = u0;
+      nstate[2 * N + k] = u1;
+      nstate[3 * N + k] = u2;
+      nstate[4 * N + k] = Tn;
+      nstate[5 * N + k] = it;
+    }
+    return;
+  }
   const EqNode e = eq_prepare(r, u0, u1, u2, Tn, sa, 3);
   EqNode ef = e;
   if (sa.has_force) ef = eq_forced(r, u0, u1, u2, Tn, sa, 3);
@@ -1377,17 +1402,6 @@ __global__ void __launch_bounds__(64 * NPART, 2) k_relax_moments(const DevTensor
       hq.g2 += MS[q][5][lane];
     }
     pt = pr_term(hq, it, sa, 3);
-  }
-  // nodes in the boundary layers of a bounded face (x or y) were relaxed by the gather kernel
-  bool act = k < N;
-  if (pl.nfaces > 0) {
-    const int Nx = pl.ax[0].N, Ny = pl.ax[1].N, k32 = (int)kc;
-    for (int fc = 0; fc < pl.nfaces; fc++) {
-      const DevFace &F = pl.face[fc];
-      const int n3 = F.axis == 0 ? k32 % Nx : (k32 / Nx) % Ny;
-      const int l = F.side == 0 ? n3 : (F.axis == 0 ? Nx : Ny) - 1 - n3;
-      if (l < F.depth) act = false;
-    }
   }
   const int off = opaque_off(act ? (int)k * (int)sizeof(T) : kBufOutOfRange);
 #pragma unroll
@@ -1431,7 +1445,7 @@ void launch_tile2d_single(const DevTensorPlan &tp, const StepArgs &a, const Tile
 // velocity-split 3D step: the streaming launch (one velocity per workgroup, 576 threads: one
 // output column each), then the moments and the relaxation
 template <typename T, int P, int CPT>
-int launch_col_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
+int launch_col_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s, bool relax) {
   // a column per thread (FP64, and FP32 on meshes too short in y for two), 5 waves per SIMD:
   // two workgroups per compute unit (at p = 4 that bound spills: 4 waves, one workgroup)
   constexpr int TX = ColShape<P>::CX * P, TY = CPT * ColShape<P>::CY * P;
@@ -1455,24 +1469,29 @@ int launch_col_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pou
                        (const T *)pin, (T *)pout);
   }
   {
-    ProfScope ps(Pl, "k_relax_moments", s);
+    // relax = false: the node state instead of the relaxation (the learned step's
+    // correction then relaxes and corrects in one pass)
+    ProfScope ps(Pl, relax ? "k_relax_moments" : "k_node_state", s);
     // 64 nodes per workgroup, their velocities over the waves (FP64: 4, FP32: 2 at Q = 45;
     // 4 at Q = 125).  Measured on the 96^3 Taylor-Green mesh against a node per lane: FP64
     // D3Q45 0.268 -> 0.250 ms, FP32 0.152 -> 0.119 ms; the channel's D3Q45 set-up at Pr 0.7,
     // where a node per lane spilled, 1.51 -> 1.17 ms
     const dim3 grid((unsigned)((tp.N + 63) / 64));
+    double *ns = Pl->nstate;
+#define RM_LAUNCH(QV, NP)                                                                                   \
+  {                                                                                                         \
+    if (!relax)                                                                                             \
+      hipLaunchKernelGGL((k_relax_moments<T, QV, NP, 0, 1>), grid, dim3(64 * NP), 0, s, tp, a, (T *)pout, ns); \
+    else if (a.pr_on)                                                                                       \
+      hipLaunchKernelGGL((k_relax_moments<T, QV, NP, 1, 0>), grid, dim3(64 * NP), 0, s, tp, a, (T *)pout, ns); \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_relax_moments<T, QV, NP, 0, 0>), grid, dim3(64 * NP), 0, s, tp, a, (T *)pout, ns); \
+  }
     if (tp.Q == 45) {
-      constexpr int NPART = sizeof(T) == 8 ? 4 : 2;
-      if (a.pr_on)
-        hipLaunchKernelGGL((k_relax_moments<T, 45, NPART, 1>), grid, dim3(64 * NPART), 0, s, tp, a, (T *)pout);
-      else
-        hipLaunchKernelGGL((k_relax_moments<T, 45, NPART, 0>), grid, dim3(64 * NPART), 0, s, tp, a, (T *)pout);
+      RM_LAUNCH(45, (sizeof(T) == 8 ? 4 : 2))
     } else if (tp.Q == 125) {
-      constexpr int NPART = 4;
-      if (a.pr_on)
-        hipLaunchKernelGGL((k_relax_moments<T, 125, NPART, 1>), grid, dim3(64 * NPART), 0, s, tp, a, (T *)pout);
-      else
-        hipLaunchKernelGGL((k_relax_moments<T, 125, NPART, 0>), grid, dim3(64 * NPART), 0, s, tp, a, (T *)pout);
+      RM_LAUNCH(125, 4)
+#undef RM_LAUNCH
     } else {
       return fail(SLLBM_EUNSUPPORTED, "velocity-split step: no relaxation launch for Q = %d", tp.Q);
     }
@@ -1483,10 +1502,10 @@ int launch_col_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pou
 template <typename T, int D, int P, int CX, int CY, int CZ>
 int launch_tile_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s, bool relax) {
   if constexpr (D == 3) {
-    if (relax && Pl->use_col()) {
+    if (Pl->use_col()) {
       if constexpr (sizeof(T) == 4)
-        if (Pl->col_cpt == 2) return launch_col_t<T, P, 2>(Pl, a, pin, pout, s);
-      return launch_col_t<T, P, 1>(Pl, a, pin, pout, s);
+        if (Pl->col_cpt == 2) return launch_col_t<T, P, 2>(Pl, a, pin, pout, s, relax);
+      return launch_col_t<T, P, 1>(Pl, a, pin, pout, s, relax);
     }
   }
   constexpr int BS = D == 3 ? 512 : 256;   // threads per workgroup

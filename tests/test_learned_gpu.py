@@ -345,23 +345,35 @@ def _learned_case(case):
     if case == "mixing_d3q45_pr071":
         mesh, phys = W.mixing_layer_case(ncell=(6, 6, 6), box=BOX)
         return mesh, dataclasses.replace(phys, Pr=0.71), lambda x: W.mixing_layer_fields(x, box=BOX, amp=0.2), "cub"
+    if case.startswith("mixing_split"):
+        # long enough in x and z for the velocity-split step's 24-node tiles
+        box = (14 * 2.5 * W.MIX_DTHETA0, 8 * 2.75 * W.MIX_DTHETA0, 14 * 1.5 * W.MIX_DTHETA0)
+        mesh, phys = W.mixing_layer_case(ncell=(14, 8, 14), box=box)
+        vel = "cub" if case.endswith("d3q45") else None
+        if vel:
+            phys = dataclasses.replace(phys, Pr=0.71)
+        return mesh, phys, lambda x: W.mixing_layer_fields(x, box=box, amp=0.2), vel
     mesh, phys = W.channel_case(ncell=(6, 8, 6), p=2, box=(2.0, 2.0, 1.5), cfl=0.9, T_wall=0.9, Ma_b=0.5)
     return mesh, phys, lambda x: W.channel_fields(x, box=(2.0, 2.0, 1.5), Ma_b=0.5, T_wall=1.0), None
 
 
-@pytest.mark.parametrize("case", ["mixing", "mixing_d3q45_pr071", "channel_force"])
+@pytest.mark.parametrize("case", ["mixing", "mixing_d3q45_pr071", "channel_force", "mixing_split",
+                                  "mixing_split_d3q45"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_learned_step_fused_matches_oracle(case, prec):
     """sllbm_step_learned on the 3D tile path (the relaxation and the correction in one pass)
     against the oracle's step followed by its correction (features of the post-collision
-    state), from the same input; and against the library's own step + correction calls."""
+    state), from the same input; and against the library's own step + correction calls.  The
+    mixing_split cases run the velocity-split step (its streaming launch, then a launch that
+    stores the node state) ahead of the correction's pass."""
     torch, S = _torch(), _S()
     mesh, phys, fields, vel = _learned_case(case)
     vs = oracle.cubature_set(3, phys.T0) if vel == "cub" else None
     o = oracle.TensorOracle(mesh, phys, vel=vs)
     _, plan = _plan(mesh, phys, prec, vel=vel or "gh")
-    S.sllbm_plan_select_kernel(plan, 2)                     # the tile (and its relaxation launch)
-    assert S.sllbm_plan_info(plan)["kernel"] == 2
+    kernel = 3 if case.startswith("mixing_split") else 2   # the tile (and its relaxation launch)
+    S.sllbm_plan_select_kernel(plan, kernel)
+    assert S.sllbm_plan_info(plan)["kernel"] == kernel
     net = S.sllbm_mlp_create(20, 2 * o.Q, seed=31)
     theta = S.sllbm_mlp_get_params(net)
     th = theta.copy()
