@@ -173,7 +173,7 @@ int sllbm_plan_info(sllbm_plan p, sllbm_plan_info_t *info);
  * the moments from a node's streamed values held in registers and relaxes them
  * (SLLBM_EUNSUPPORTED unless the plan is 3D, periodic along z (bounded faces on x or y, whose
  * boundary layers stay on the gather kernel), on a 45-velocity set and tiled-eligible with
- * 24-node x-y tiles).  All compute the same step; the
+ * its x-y tiles of 48 x 12 nodes and a halo).  All compute the same step; the
  * choice exists for testing and measurement. */
 int sllbm_plan_select_kernel(sllbm_plan p, int kernel);
 /* Per-kernel timing of a plan's launches (for measurement, not part of the method).

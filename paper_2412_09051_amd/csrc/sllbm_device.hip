@@ -108,9 +108,9 @@ int require_device(const sllbm_plan_s *P) {
 // and fill and drain their pipelines less often.  (Measured on the 96^3 Taylor-Green mesh
 // and the 128 x 96 x 64 channel: chunks of a smaller count than this, or chunks much shorter,
 // were slower; a tiny last chunk beside long ones too.)
-int col_chunk_cells(const Mesh &m, int Q, int cpt) {
+int col_chunk_cells(const Mesh &m, int Q, int tx, int ty) {
   const int P = m.p, ncz = m.N[2] / P;
-  const int64_t tiles = (int64_t)((m.N[0] + 23) / 24) * ((m.N[1] + 24 * cpt - 1) / (24 * cpt));
+  const int64_t tiles = (int64_t)((m.N[0] + tx - 1) / tx) * ((m.N[1] + ty - 1) / ty);
   const int64_t slots = 256 * 2;
   int last = 0;
   for (int nzc = 1; nzc <= ncz; nzc++) {
@@ -201,11 +201,11 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
     if (P->tile_ok && m.dim == 3 && col_q_supported(V.Q)) {
       // the widest tile that applies (FP32: two columns per thread, else one)
       for (int cpt = col_cpt(prec == SLLBM_F32 ? 4 : 8); cpt >= 1 && !P->col_ok; cpt--) {
-        const int zc = col_chunk_cells(m, V.Q, cpt);
         int cx = 0, cy = 0, L = 0;
         if (m.p == 2) cx = ColShape<2>::CX, cy = cpt * ColShape<2>::CY, L = kColWin<2>;
         if (m.p == 3) cx = ColShape<3>::CX, cy = cpt * ColShape<3>::CY, L = kColWin<3>;
         if (m.p == 4) cx = ColShape<4>::CX, cy = cpt * ColShape<4>::CY, L = kColWin<4>;
+        const int zc = cx > 0 ? col_chunk_cells(m, V.Q, cx * m.p, cy * m.p) : 0;
         if (zc > 0 && L > 0 && col_eligible(m, t, cx, cy, zc, L)) {
           P->col_ok = 1;
           P->col_zc = zc;

@@ -68,11 +68,20 @@ template <> struct TileShape<3, 4> { static constexpr int CX = 2, CY = 2, CZ = 2
 
 // The velocity-split 3D step (one velocity per workgroup on a column of output nodes, then a
 // moments-and-relaxation launch with a node's streamed values in registers): x-y tiles of
-// 24 x 24 nodes, z chunks of whole cells up to kColZMax planes, a window of kColWin<P>
+// 48 x 12 nodes, z chunks of whole cells up to kColZMax planes, a window of kColWin<P>
 // y-contracted planes per column; the relaxation launch (a node's velocities over the waves
 // of a workgroup) is compiled for these Q.
+// (48 x 12 against 24 x 24 on the 96^3 Taylor-Green mesh: the same within 2 % on D3Q45 and
+// D3V125; on the 256 x 193 x 128-node channel's D3Q45 set-up 1.60 -> 1.25 ms per streaming
+// launch, its longer rows meeting in L2; 36 x 12: no better)
+#ifndef COL_TX
+#define COL_TX 48
+#endif
+#ifndef COL_TY
+#define COL_TY 12
+#endif
 template <int P> struct ColShape {
-  static constexpr int CX = 24 / P, CY = 24 / P;   // cells per tile along x and y
+  static constexpr int CX = COL_TX / P, CY = COL_TY / P;   // cells per tile along x and y
 };
 template <int P> constexpr int kColWin = 3 * P - 1;
 // most output columns per thread of the streaming launch (the tile is that many times as long

@@ -1016,7 +1016,7 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
 // them: the step reads and writes each population twice, with no node-state array and no
 // re-staging of a departure region per velocity and tile.
 //
-// Along x and y the tile is cell-aligned (24 nodes at p = 2, 3, 4); along z a chunk of
+// Along x and y the tile is cell-aligned (48 x 12 nodes at p = 2, 3, 4); along z a chunk of
 // whole cells.  The separable contraction (x, then y, then z, each in the order of its
 // stencil) is the tiled kernel's: the streamed values are the same numbers.
 
@@ -1443,7 +1443,7 @@ void launch_tile2d_single(const DevTensorPlan &tp, const StepArgs &a, const Tile
 }
 
 // velocity-split 3D step: the streaming launch (one velocity per workgroup, 576 threads: one
-// output column each), then the moments and the relaxation
+// output column each, two in FP32), then the moments and the relaxation
 template <typename T, int P, int CPT>
 int launch_col_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pout, hipStream_t s, bool relax) {
   // a column per thread (FP64, and FP32 on meshes too short in y for two), 5 waves per SIMD:

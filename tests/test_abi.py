@@ -257,7 +257,7 @@ def test_tiled_kernel_eligibility_follows_the_halo_rule():
 def test_velocity_split_step_eligibility():
     """The velocity-split 3D step: 3D plans that the tiled kernel takes
     (the automatic choice from 256 tiles on), periodic along z, walls on x or y allowed, on the
-    45- and 125-velocity sets; not D3Q27, not meshes shorter than a 24-node tile and its halo,
+    45- and 125-velocity sets; not D3Q27, not meshes shorter than a 48 x 12-node tile and its halo,
     not 2D."""
     mesh, phys = W.tgv_case(ncell=32, p=3, dt=W.TGV_DT)
     m = S.sllbm_mesh_build(mesh)
@@ -277,7 +277,7 @@ def test_velocity_split_step_eligibility():
     walls = S.sllbm_interp_plan(S.sllbm_mesh_build(cmesh), S.sllbm_velset_cubature(3, cphys.T0), cphys.dt)
     smesh, sphys = W.shear_wave_case(ncell=16, p=4)
     flat = S.sllbm_interp_plan(S.sllbm_mesh_build(smesh), S.sllbm_velset_cubature(2, sphys.T0), sphys.dt)
-    lmesh, lphys = W.channel_case(ncell=(14, 8, 14), p=2, box=(2.0, 2.0, 1.5), cfl=0.75, T_wall=0.9, Ma_b=0.5)
+    lmesh, lphys = W.channel_case(ncell=(26, 8, 14), p=2, box=(4.0, 2.0, 1.5), cfl=0.75, T_wall=0.9, Ma_b=0.5)
     long_walls = S.sllbm_interp_plan(S.sllbm_mesh_build(lmesh), S.sllbm_velset_cubature(3, lphys.T0), lphys.dt)
     S.sllbm_plan_select_kernel(long_walls, 3)
     assert S.sllbm_plan_info(long_walls)["kernel"] == 3

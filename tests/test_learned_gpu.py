@@ -346,9 +346,9 @@ def _learned_case(case):
         mesh, phys = W.mixing_layer_case(ncell=(6, 6, 6), box=BOX)
         return mesh, dataclasses.replace(phys, Pr=0.71), lambda x: W.mixing_layer_fields(x, box=BOX, amp=0.2), "cub"
     if case.startswith("mixing_split"):
-        # long enough in x and z for the velocity-split step's 24-node tiles
-        box = (14 * 2.5 * W.MIX_DTHETA0, 8 * 2.75 * W.MIX_DTHETA0, 14 * 1.5 * W.MIX_DTHETA0)
-        mesh, phys = W.mixing_layer_case(ncell=(14, 8, 14), box=box)
+        # long enough in x and z for the velocity-split step's 48 x 12-node tiles
+        box = (26 * 2.5 * W.MIX_DTHETA0, 8 * 2.75 * W.MIX_DTHETA0, 14 * 1.5 * W.MIX_DTHETA0)
+        mesh, phys = W.mixing_layer_case(ncell=(26, 8, 14), box=box)
         vel = "cub" if case.endswith("d3q45") else None
         if vel:
             phys = dataclasses.replace(phys, Pr=0.71)

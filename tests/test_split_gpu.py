@@ -63,10 +63,10 @@ def _run_pair(mesh, phys, prec, nsteps, fields=W.tgv_fields, vel="cub"):
 
 
 CASES = [
-    pytest.param(2, (14, 15, 13), 0.0, id="p2-ragged"),
-    pytest.param(3, (10, 11, 9), 0.0, id="p3-ragged"),
-    pytest.param(3, (10, 10, 12), 0.3, id="p3-stretched-z"),
-    pytest.param(4, (8, 9, 8), 0.0, id="p4-ragged"),
+    pytest.param(2, (26, 15, 13), 0.0, id="p2-ragged"),
+    pytest.param(3, (18, 11, 9), 0.0, id="p3-ragged"),
+    pytest.param(3, (18, 10, 12), 0.3, id="p3-stretched-z"),
+    pytest.param(4, (14, 9, 8), 0.0, id="p4-ragged"),
 ]
 
 
@@ -80,11 +80,13 @@ def test_split_matches_tiled_fp64(p, ncell, stretch):
     assert e <= 1e-13
 
 
-# FP32 plans whose y axis holds two tiles' worth of columns run two output columns per thread
+# FP32 plans whose y axis is long enough run two output columns per thread (24-node tiles in y);
+# shorter ones one
 CASES32 = CASES + [
-    pytest.param(2, (14, 26, 13), 0.0, id="p2-two-columns"),
-    pytest.param(3, (10, 18, 9), 0.3, id="p3-two-columns-stretched-z"),
-    pytest.param(4, (8, 14, 8), 0.0, id="p4-two-columns"),
+    pytest.param(3, (18, 7, 9), 0.0, id="p3-one-column"),
+    pytest.param(2, (26, 14, 13), 0.0, id="p2-two-columns"),
+    pytest.param(3, (18, 10, 9), 0.3, id="p3-two-columns-stretched-z"),
+    pytest.param(4, (14, 8, 8), 0.0, id="p4-two-columns"),
 ]
 
 
@@ -105,7 +107,7 @@ def test_split_matches_tiled_physics_variants_fp64(variant):
     kw = {"mode1": {}, "force_pr": {"force": (0.02, -0.01, 0.005), "Pr": 0.71},
           "mode0": {"relax_mode": 0, "tau_bar": 0.8}, "streaming": {"relax_mode": 2}}[variant]
     say("split vs tiled fp64", variant)
-    mesh, phys = box_case((10, 11, 9), 3, **kw)
+    mesh, phys = box_case((18, 11, 9), 3, **kw)
     t, s = _run_pair(mesh, phys, "f64", 5)
     e = rel_err(s.pop(), t.pop())
     say("rel err", e)
@@ -115,25 +117,25 @@ def test_split_matches_tiled_physics_variants_fp64(variant):
 # ------------------------------------------------------------------ bounded meshes
 
 def _channel(prec_kw=None):
-    """The channel sub-box long enough in x and z for the 24-node tiles: tanh walls in y,
+    """The channel sub-box long enough in x for the 48-node tiles: tanh walls in y,
     isothermal walls at 0.9, power-law viscosity, Kupershtokh force, Pr 0.7, D3Q45 at a CFL
     of 0.75 on the product rule's largest abscissa."""
-    mesh, phys = W.channel_case(ncell=(14, 8, 14), p=2, box=(2.0, 2.0, 1.5), cfl=0.75, T_wall=0.9, Ma_b=0.5)
+    mesh, phys = W.channel_case(ncell=(26, 8, 14), p=2, box=(4.0, 2.0, 1.5), cfl=0.75, T_wall=0.9, Ma_b=0.5)
     return mesh, dataclasses.replace(phys, Pr=0.7)
 
 
 def _channel_fields(x):
-    return W.channel_fields(x, box=(2.0, 2.0, 1.5), Ma_b=0.5, T_wall=1.0)
+    return W.channel_fields(x, box=(4.0, 2.0, 1.5), Ma_b=0.5, T_wall=1.0)
 
 
 def _mixing():
-    """The mixing layer's moving equilibrium walls in y, 14 x 8 x 14 cells, p = 2."""
-    return W.mixing_layer_case(ncell=(14, 8, 14), p=2, Ma_c=0.7, box=(14 * 2.5 * W.MIX_DTHETA0, 8 * 2.75 * W.MIX_DTHETA0,
+    """The mixing layer's moving equilibrium walls in y, 26 x 8 x 14 cells, p = 2."""
+    return W.mixing_layer_case(ncell=(26, 8, 14), p=2, Ma_c=0.7, box=(26 * 2.5 * W.MIX_DTHETA0, 8 * 2.75 * W.MIX_DTHETA0,
                                                                     14 * 1.5 * W.MIX_DTHETA0))
 
 
 def _mixing_fields(x):
-    return W.mixing_layer_fields(x, Ma_c=0.7, box=(14 * 2.5 * W.MIX_DTHETA0, 8 * 2.75 * W.MIX_DTHETA0,
+    return W.mixing_layer_fields(x, Ma_c=0.7, box=(26 * 2.5 * W.MIX_DTHETA0, 8 * 2.75 * W.MIX_DTHETA0,
                                                   14 * 1.5 * W.MIX_DTHETA0))
 
 
@@ -192,8 +194,8 @@ def _oracle_pair(mesh, phys, prec):
     return o, g
 
 
-@pytest.mark.parametrize("prec,tol,nsteps,ncell", [("f64", TOL64, 20, (10, 11, 9)), ("f32", TOL32, 20, (10, 11, 9)),
-                                                   ("f32", TOL32, 20, (10, 18, 9))])
+@pytest.mark.parametrize("prec,tol,nsteps,ncell", [("f64", TOL64, 20, (18, 11, 9)), ("f32", TOL32, 20, (18, 7, 9)),
+                                                   ("f32", TOL32, 20, (18, 11, 9))])
 def test_split_oracle_parity(prec, tol, nsteps, ncell):
     say("split vs oracle", prec, nsteps, ncell)
     mesh, phys = box_case(ncell, 3, stretch=0.3, force=(0.01, 0.0, -0.01), Pr=0.71)
@@ -242,8 +244,8 @@ def test_split_full_size_taylor_green_sampled():
 
 # ------------------------------------------------------------------ D3V125 (125 velocities)
 
-@pytest.mark.parametrize("p,ncell,stretch", [pytest.param(2, (14, 15, 13), 0.0, id="p2-ragged"),
-                                             pytest.param(3, (10, 18, 9), 0.3, id="p3-stretched-z")])
+@pytest.mark.parametrize("p,ncell,stretch", [pytest.param(2, (26, 15, 13), 0.0, id="p2-ragged"),
+                                             pytest.param(3, (18, 10, 9), 0.3, id="p3-stretched-z")])
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-6)])
 def test_split_d3v125_matches_tiled(p, ncell, stretch, prec, tol):
     say("split vs tiled d3v125", p, ncell, prec)
@@ -266,7 +268,7 @@ def test_split_d3v125_channel_matches_tiled():
 @pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
 def test_split_d3v125_oracle_parity(prec, tol):
     say("split vs oracle d3v125", prec)
-    mesh, phys = box_case((10, 11, 9), 3, stretch=0.3, force=(0.01, 0.0, -0.01), Pr=0.71)
+    mesh, phys = box_case((18, 11, 9), 3, stretch=0.3, force=(0.01, 0.0, -0.01), Pr=0.71)
     o = oracle.TensorOracle(mesh, phys)
     g = GpuRun(mesh, phys, prec, SPLIT)
     assert g.kernel == SPLIT and g.Q == 125
