@@ -30,6 +30,25 @@ __device__ __forceinline__ void basis_at(const DevCsrPlan &pl, double t, double 
   }
 }
 
+// The reference coordinates (xi, eta) of row (i, k): FP64 plans store them as two FP64
+// planes per velocity, FP32 plans as one interleaved FP32 pair per row (8 B per row
+// instead of 16; the coordinate's rounding moves the interpolated value by at most about 1e-7
+// of its change across the cell, far below the FP32 storage rounding).
+template <typename T> struct RowXi;
+template <> struct RowXi<double> {
+  __device__ static void get(const DevCsrPlan &pl, int i, int64_t k, double &x, double &y) {
+    x = pl.row_xi[(size_t)(2 * i) * pl.N + k];
+    y = pl.row_xi[(size_t)(2 * i + 1) * pl.N + k];
+  }
+};
+template <> struct RowXi<float> {
+  __device__ static void get(const DevCsrPlan &pl, int i, int64_t k, double &x, double &y) {
+    const float2 r = ((const float2 *)pl.row_xf)[(size_t)i * pl.N + k];
+    x = r.x;
+    y = r.y;
+  }
+};
+
 template <typename T, int P>
 __device__ __forceinline__ void stream_csr(const DevCsrPlan &pl, const StepArgs &sa, const T *__restrict__ pin,
                                            int64_t k, int i, double scale, double &fv, double &gv) {
@@ -45,11 +64,12 @@ __device__ __forceinline__ void stream_csr(const DevCsrPlan &pl, const StepArgs 
     return;
   }
   // the (p+1)^2 weights are products of the 1D bases at the departure point's reference
-  // coordinates, evaluated here instead of being read from the plan (16 B per row
-  // instead of 8 (p+1)^2)
+  // coordinates, evaluated here instead of being read from the plan
+  double xi, eta;
+  RowXi<T>::get(pl, i, k, xi, eta);
   double lx[P + 1], ly[P + 1];
-  basis_at<P>(pl, pl.row_xi[(size_t)(2 * i) * N + k], lx);
-  basis_at<P>(pl, pl.row_xi[(size_t)(2 * i + 1) * N + k], ly);
+  basis_at<P>(pl, xi, lx);
+  basis_at<P>(pl, eta, ly);
   const int32_t *cn = pl.cell_nodes + (size_t)c * NPC;
   const T *F = pin + (size_t)src * N;
   const T *G = pin + ((size_t)pl.Q + src) * N;

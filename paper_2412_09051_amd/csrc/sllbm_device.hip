@@ -199,8 +199,8 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
     }
     for (int id : t.tab_reg) P->tile_tabs = std::max(P->tile_tabs, id + 1);
     if (P->tile_ok && m.dim == 3 && col_q_supported(V.Q)) {
-      // the widest tile that applies (FP32: two columns per thread, else one)
-      for (int cpt = col_cpt(prec == SLLBM_F32 ? 4 : 8); cpt >= 1 && !P->col_ok; cpt--) {
+      // the widest tile that applies (two columns per thread where that pays, else one)
+      for (int cpt = col_cpt(prec == SLLBM_F32 ? 4 : 8, m.p, V.Q); cpt >= 1 && !P->col_ok; cpt--) {
         int cx = 0, cy = 0, L = 0;
         if (m.p == 2) cx = ColShape<2>::CX, cy = cpt * ColShape<2>::CY, L = kColWin<2>;
         if (m.p == 3) cx = ColShape<3>::CX, cy = cpt * ColShape<3>::CY, L = kColWin<3>;
@@ -298,7 +298,20 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
     UP(cn32, cp.cell_nodes);
     UP(t.row_cell, cp.row_cell);
     UP(t.row_src, cp.row_src);
-    UP(t.row_xi, cp.row_xi);
+    cp.row_xi = nullptr;
+    cp.row_xf = nullptr;
+    if (P->prec == SLLBM_F32) {
+      std::vector<float> xf(t.row_xi.size());
+      const size_t N = (size_t)m.n_nodes;
+      for (size_t i = 0; i < (size_t)V.Q; i++)
+        for (size_t k = 0; k < N; k++) {
+          xf[2 * (i * N + k)] = (float)t.row_xi[(2 * i) * N + k];
+          xf[2 * (i * N + k) + 1] = (float)t.row_xi[(2 * i + 1) * N + k];
+        }
+      UP(xf, cp.row_xf);
+    } else {
+      UP(t.row_xi, cp.row_xi);
+    }
     for (int a = 0; a <= m.p; a++) {
       cp.xref[a] = m.xref[a];
       double l = 1.0;

@@ -111,7 +111,8 @@ struct DevCsrPlan {
   const int32_t *cell_nodes;// [n_cells][npc]
   const int32_t *row_cell;  // [Q][N] cell of the departure point, -1 inlet
   const int32_t *row_src;   // [Q][N] source velocity, or bc index for inlet rows
-  const double *row_xi;     // [Q][2][N] reference coordinates (xi, eta) of the departure point in its cell
+  const double *row_xi;     // FP64 plans: [Q][2][N] reference coordinates (xi, eta) of the departure point in its cell
+  const float *row_xf;      // FP32 plans: [Q][N][2] the same coordinates rounded to FP32
   double xref[kMaxP + 1];   // support points on [-1, 1]
   double lam[kMaxP + 1];    // 1 / prod_{b != a} (xref_a - xref_b)
   const double *node_Tw;    // [N] thermal-wall temperature, NaN = none

@@ -85,8 +85,10 @@ template <int P> struct ColShape {
 };
 template <int P> constexpr int kColWin = 3 * P - 1;
 // most output columns per thread of the streaming launch (the tile is that many times as long
-// in y): two in FP32, one in FP64 (where a second column's window would halve the occupancy)
-constexpr int col_cpt(int elem_bytes) { return elem_bytes == 4 ? 2 : 1; }
+// in y): two in FP32, one in FP64 (where a second column's window would halve the occupancy).
+// FP32 D3Q45 at p = 3 also takes one (96^3 Taylor-Green: 0.267 -> 0.244 ms per streaming
+// launch), while D3V125 and the p = 2 channel lose 4-6 % per step with it.
+constexpr int col_cpt(int elem_bytes, int p, int Q) { return elem_bytes == 4 && !(p == 3 && Q == 45) ? 2 : 1; }
 constexpr int kColZMax = 96;
 constexpr bool col_q_supported(int Q) { return Q == 45 || Q == 125; }
 

@@ -80,12 +80,13 @@ def test_split_matches_tiled_fp64(p, ncell, stretch):
     assert e <= 1e-13
 
 
-# FP32 plans whose y axis is long enough run two output columns per thread (24-node tiles in y);
-# shorter ones one
+# FP32 plans whose y axis is long enough run two output columns per thread (24-node tiles in y),
+# shorter ones one; D3Q45 at p = 3 always runs one (the p = 3 two-column kernel is covered by
+# the D3V125 cases below)
 CASES32 = CASES + [
-    pytest.param(3, (18, 7, 9), 0.0, id="p3-one-column"),
+    pytest.param(3, (18, 7, 9), 0.0, id="p3-short-y"),
     pytest.param(2, (26, 14, 13), 0.0, id="p2-two-columns"),
-    pytest.param(3, (18, 10, 9), 0.3, id="p3-two-columns-stretched-z"),
+    pytest.param(3, (18, 10, 9), 0.3, id="p3-long-y-stretched-z"),
     pytest.param(4, (14, 8, 8), 0.0, id="p4-two-columns"),
 ]
 
