@@ -49,13 +49,27 @@ template <> struct RowXi<float> {
   }
 };
 
+// The plan row of (velocity i, node k): the cell holding the departure point (-1: inlet),
+// the source population (or the inlet's bc index) and the reference coordinates.
+struct CsrRow {
+  int c, src;
+  double xi, eta;
+};
+template <typename T>
+__device__ __forceinline__ CsrRow load_row(const DevCsrPlan &pl, int64_t k, int i) {
+  CsrRow r;
+  r.c = pl.row_cell[(size_t)i * pl.N + k];
+  r.src = pl.row_src[(size_t)i * pl.N + k];
+  RowXi<T>::get(pl, i, k, r.xi, r.eta);
+  return r;
+}
+
 template <typename T, int P>
-__device__ __forceinline__ void stream_csr(const DevCsrPlan &pl, const StepArgs &sa, const T *__restrict__ pin,
-                                           int64_t k, int i, double scale, double &fv, double &gv) {
+__device__ __forceinline__ void stream_row(const DevCsrPlan &pl, const StepArgs &sa, const T *__restrict__ pin,
+                                           int i, const CsrRow &r, double scale, double &fv, double &gv) {
   constexpr int NPC = (P + 1) * (P + 1);
   const int64_t N = pl.N;
-  const int c = pl.row_cell[(size_t)i * N + k];
-  const int src = pl.row_src[(size_t)i * N + k];
+  const int c = r.c, src = r.src;
   if (c < 0) {  // equilibrium inlet (Sec. 3.3.1)
     const double *st = sa.inlet + 5 * src;
     EqNode e = eq_prepare(st[0], st[1], st[2], st[3], st[4], sa, 2);
@@ -65,11 +79,9 @@ __device__ __forceinline__ void stream_csr(const DevCsrPlan &pl, const StepArgs 
   }
   // the (p+1)^2 weights are products of the 1D bases at the departure point's reference
   // coordinates, evaluated here instead of being read from the plan
-  double xi, eta;
-  RowXi<T>::get(pl, i, k, xi, eta);
   double lx[P + 1], ly[P + 1];
-  basis_at<P>(pl, xi, lx);
-  basis_at<P>(pl, eta, ly);
+  basis_at<P>(pl, r.xi, lx);
+  basis_at<P>(pl, r.eta, ly);
   const int32_t *cn = pl.cell_nodes + (size_t)c * NPC;
   const T *F = pin + (size_t)src * N;
   const T *G = pin + ((size_t)pl.Q + src) * N;
@@ -88,6 +100,12 @@ __device__ __forceinline__ void stream_csr(const DevCsrPlan &pl, const StepArgs 
   }
   fv = scale * a;
   gv = scale * b;
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void stream_csr(const DevCsrPlan &pl, const StepArgs &sa, const T *__restrict__ pin,
+                                           int64_t k, int i, double scale, double &fv, double &gv) {
+  stream_row<T, P>(pl, sa, pin, i, load_row<T>(pl, k, i), scale, fv, gv);
 }
 
 // relaxation of one node given its streamed populations (thermal wall, BGK, force)
@@ -152,9 +170,14 @@ __global__ void __launch_bounds__(kBlock) k_step_csr(const DevCsrPlan pl, const 
   double rho = 0, j0 = 0, j1 = 0, E = 0;
   if constexpr (QS > 0) {
     double fs[QS], gs[QS];
+    // the plan row of the next velocity is loaded while this one's gathers are in flight
+    // (its cell, source and coordinates then start the next velocity's chain of loads)
+    CsrRow nx = load_row<T>(pl, k, 0);
 #pragma unroll
     for (int i = 0; i < QS; i++) {
-      stream_csr<T, P>(pl, sa, pin, k, i, scale, fs[i], gs[i]);
+      const CsrRow cur = nx;
+      if (i + 1 < QS) nx = load_row<T>(pl, k, i + 1);
+      stream_row<T, P>(pl, sa, pin, i, cur, scale, fs[i], gs[i]);
       const double *vi = pl.vel + 8 * i;
       rho += fs[i];
       j0 += vi[0] * fs[i];

@@ -343,14 +343,13 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
 
   // x-pass: S[rz][ry][*] -> X[rz][ry][tx]; each thread keeps one tx (and its weights)
   // and walks the rows of the committed region
-  auto xpass = [&]() __attribute__((always_inline)) {
+  auto xpass = [&](int off) __attribute__((always_inline)) {
     constexpr int NRX = BS / TX;          // rows in flight per sweep of the workgroup
     const int Ry = cg[1].R;   // one plane in 2D: the row counter is ry itself
     const int len = cg[0].ident ? 1 : P + 1;
     const int tx = tid % TX, r0 = tid / TX;
     if (r0 < NRX && tx < vx) {
       const int row = cg[0].tb * NW + tx;
-      const int off = OT[row];
       T w[P + 1];
 #pragma unroll
       for (int j = 0; j <= P; j++) w[j] = WT[row * (P + 1) + j];
@@ -375,14 +374,15 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
   };
 
   // y contraction for the owned nodes straight out of X
-  auto ypass_nodes = [&](int tby, int leny, double (&fv)[NPT], double (&gv)[NPT]) __attribute__((always_inline)) {
+  auto ypass_nodes = [&](int tby, int leny, const int (&yo)[NPT], double (&fv)[NPT], double (&gv)[NPT])
+                         __attribute__((always_inline)) {
 #pragma unroll
     for (int m = 0; m < NPT; m++) {
       fv[m] = gv[m] = 0.0;
       if (!own[m]) continue;
       const int ry = tby * NW + TX + oty[m];
       const T *wy = WT + ry * (P + 1);
-      const T *xr = X + OT[ry] * TX + otx[m];
+      const T *xr = X + yo[m] * TX + otx[m];
       T a = 0, b = 0;
 #pragma unroll
       for (int jy = 0; jy <= P; jy++) {
@@ -400,13 +400,19 @@ __global__ void __launch_bounds__(BS, WPE) k_step_tile2d(const DevTensorPlan pl,
   for (int m = 0; m < NPT; m++) rho[m] = j0[m] = j1[m] = j2[m] = E[m] = 0.0;
   // one velocity: x-pass, commit of the next one, y contraction, moments
   auto velocity = [&](int i, double (&fv)[NPT], double (&gv)[NPT]) __attribute__((always_inline)) {
+    // the stencil starts of this thread's x-pass row and y-pass nodes (the tables are
+    // constant): read before the barrier, they take an LDS round trip off each pass
+    const int xo = OT[cg[0].tb * NW + tid % TX];
+    int yo[NPT];
+#pragma unroll
+    for (int m = 0; m < NPT; m++) yo[m] = OT[cg[1].tb * NW + TX + oty[m]];
     __syncthreads();   // velocity i is in S; X is free
-    xpass();
+    xpass(xo);
     __syncthreads();   // X holds velocity i; S is free
     const int tby = cg[1].tb, leny = cg[1].ident ? 1 : P + 1;
     if (i + 1 < Q) commit();
     prefetch(i + 2);
-    ypass_nodes(tby, leny, fv, gv);
+    ypass_nodes(tby, leny, yo, fv, gv);
     // the velocity table is never written by the step: read through the scalar cache
     const double __attribute__((address_space(4))) *vi =
         (const double __attribute__((address_space(4))) *)(pl.vel + 8 * i);
@@ -1164,6 +1170,14 @@ __global__ void __launch_bounds__(BS, WPE) k_stream_col3d(const DevTensorPlan pl
     colb[c] = colv[c] ? (x0 + cx + Nx * (y0 + cy)) * (int)sizeof(T) : 0;
   }
   const int lenx = gx.ident ? 1 : P + 1, leny = gy.ident ? 1 : P + 1;
+  // this thread's x-pass position is the same in every sweep (BS is a multiple of TX): its
+  // stencil start and weights stay in registers, off the LDS path between the barriers
+  static_assert(BS % TX == 0, "one x-pass position per thread");
+  const int xt = tid % TX;
+  const int oxt = OX[xt];
+  T wxt[P + 1];
+#pragma unroll
+  for (int j = 0; j <= P; j++) wxt[j] = WX[xt * (P + 1) + j];
 
   // source plane r of the region into registers (r past the region: every offset out of
   // range, the loads return 0)
@@ -1201,33 +1215,32 @@ __global__ void __launch_bounds__(BS, WPE) k_stream_col3d(const DevTensorPlan pl
 #pragma unroll
     for (int n = 0; n < NXI; n++) {
       const int it = tid + BS * n;
-      const int ry = it / TX, tx = it - ry * TX;
-      if (it < NXO && ry < Ry && tx < vx) {
-        const T *sf = S + ry * SST + OX[tx];
-        const T *w = WX + tx * (P + 1);
+      const int ry = it / TX;
+      if (it < NXO && ry < Ry && xt < vx) {
+        const T *sf = S + ry * SST + oxt;
         T a = 0, c2 = 0;
 #pragma unroll
         for (int j = 0; j <= P; j++) {
           if (j >= lenx) break;
-          a += w[j] * sf[j];
-          c2 += w[j] * sf[SS + j];
+          a += wxt[j] * sf[j];
+          c2 += wxt[j] * sf[SS + j];
         }
-        X[ry * XST + tx] = a;
-        X[XS + ry * XST + tx] = c2;
+        X[ry * XST + xt] = a;
+        X[XS + ry * XST + xt] = c2;
       }
     }
     __syncthreads();
+    // (every column reads rows of X inside the plane, valid or not, and a column without a
+    // node discards its result: no divergent branch around these reads)
 #pragma unroll
     for (int c = 0; c < CPT; c++) {
       T a = 0, c2 = 0;
-      if (colv[c]) {
-        const T *xf = X + oyc[c] * XST + cx;
+      const T *xf = X + oyc[c] * XST + cx;
 #pragma unroll
-        for (int j = 0; j <= P; j++) {
-          if (j >= leny) break;
-          a += wy[c][j] * xf[j * XST];
-          c2 += wy[c][j] * xf[XS + j * XST];
-        }
+      for (int j = 0; j <= P; j++) {
+        if (j >= leny) break;
+        a += wy[c][j] * xf[j * XST];
+        c2 += wy[c][j] * xf[XS + j * XST];
       }
 #pragma unroll
       for (int s = 0; s + 1 < L; s++) {
