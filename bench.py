@@ -36,9 +36,9 @@ BYTES_PER_UPDATE = {"f64": 32, "f32": 16}
 
 def curv_bytes_per_update(prec):
     """f and g read and written, plus the plan row of the (node, velocity) pair: its cell
-    and source (two int32) and the departure point's reference coordinates (two values of
+    and source (one int32) and the departure point's reference coordinates (two values of
     the plan's precision)."""
-    return BYTES_PER_UPDATE[prec] + 8 + (8 if prec == "f32" else 16)
+    return BYTES_PER_UPDATE[prec] + 4 + (8 if prec == "f32" else 16)
 
 
 def parse():

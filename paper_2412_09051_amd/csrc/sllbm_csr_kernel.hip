@@ -1,8 +1,8 @@
 // CSR step kernel for curvilinear meshes (gfx950): one node per lane; every
-// (velocity, node) row names the cell holding the departure point, the source
-// population (bounce-back: the opposite one) and the departure point's reference
-// coordinates in that cell, from which the kernel evaluates the (p+1)^2 weights of
-// eq:intf, or an inlet state (Sec. 3.3.1).  Interpolation accumulates in FP64 for both
+// (velocity, node) row names the cell holding the departure point and the source
+// population (bounce-back: the opposite one) in one word, and the departure point's
+// reference coordinates in that cell, from which the kernel evaluates the (p+1)^2 weights
+// of eq:intf; or an inlet state (Sec. 3.3.1).  Interpolation accumulates in FP64 for both
 // storage precisions.  For Q = 25 (D2V25) the 50 streamed values stay in registers
 // between the moments and the relaxation, so every row is read once per step.
 #include <hip/hip_runtime.h>
@@ -58,8 +58,11 @@ struct CsrRow {
 template <typename T>
 __device__ __forceinline__ CsrRow load_row(const DevCsrPlan &pl, int64_t k, int i) {
   CsrRow r;
-  r.c = pl.row_cell[(size_t)i * pl.N + k];
-  r.src = pl.row_src[(size_t)i * pl.N + k];
+  const int code = pl.row_code[(size_t)i * pl.N + k];
+  // the opposite velocity through the scalar cache (i is the same for the whole wave)
+  const int op = ((const int32_t __attribute__((address_space(4))) *)pl.opp)[i];
+  r.c = code < 0 ? -1 : (code & (kCsrOpp - 1));
+  r.src = code < 0 ? -1 - code : ((code & kCsrOpp) ? op : i);
   RowXi<T>::get(pl, i, k, r.xi, r.eta);
   return r;
 }

@@ -296,8 +296,24 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
     for (int d = 0; d < m.dim; d++) cp.npc *= (m.p + 1);
     std::vector<int32_t> cn32(m.cell_nodes.begin(), m.cell_nodes.end());
     UP(cn32, cp.cell_nodes);
-    UP(t.row_cell, cp.row_cell);
-    UP(t.row_src, cp.row_src);
+    if (m.n_cells >= kCsrOpp) {
+      sllbm_plan_destroy(P);
+      return fail(SLLBM_EUNSUPPORTED, "curvilinear plans hold at most %d cells", (int)kCsrOpp - 1);
+    }
+    std::vector<int32_t> code(t.row_cell.size());
+    for (size_t i = 0; i < (size_t)V.Q; i++)
+      for (size_t k = 0; k < (size_t)m.n_nodes; k++) {
+        const size_t r = i * (size_t)m.n_nodes + k;
+        const int32_t c = t.row_cell[r], src = t.row_src[r];
+        if (c >= 0 && src != (int32_t)i && src != V.opp[i]) {
+          sllbm_plan_destroy(P);
+          return fail(SLLBM_EGEOM, "curvilinear row (%zu, %zu): source %d is neither the velocity nor its opposite", i,
+                      k, (int)src);
+        }
+        code[r] = c < 0 ? -1 - src : (c | (src != (int32_t)i ? kCsrOpp : 0));
+      }
+    UP(code, cp.row_code);
+    UP(V.opp, cp.opp);
     cp.row_xi = nullptr;
     cp.row_xf = nullptr;
     if (P->prec == SLLBM_F32) {

@@ -109,8 +109,9 @@ struct DevCsrPlan {
   int64_t N;
   int npc;                  // support points per cell, (p+1)^dim
   const int32_t *cell_nodes;// [n_cells][npc]
-  const int32_t *row_cell;  // [Q][N] cell of the departure point, -1 inlet
-  const int32_t *row_src;   // [Q][N] source velocity, or bc index for inlet rows
+  const int32_t *row_code;  // [Q][N] the cell of the departure point, | kCsrOpp when the source
+                            // is the opposite population (bounce-back); an inlet row: -1 - bc
+  const int32_t *opp;       // [Q] opposite velocity
   const double *row_xi;     // FP64 plans: [Q][2][N] reference coordinates (xi, eta) of the departure point in its cell
   const float *row_xf;      // FP32 plans: [Q][N][2] the same coordinates rounded to FP32
   double xref[kMaxP + 1];   // support points on [-1, 1]

@@ -43,6 +43,11 @@ constexpr int kTileTabsMax = 16;
 // 32-bit byte offsets: its plans hold at most this many bytes per plane.
 constexpr int64_t kBufMaxBytes = 0x7ffffff0;
 
+// A curvilinear plan row holds its cell and its source in one word (4 B per row): the cell
+// (below 2^30), with this bit set when the source is the opposite population; an inlet row
+// holds -1 - bc.
+constexpr int32_t kCsrOpp = 1 << 30;
+
 // Cell-aligned tile (cells per axis) of the LDS-tiled step kernel for (dim, order).
 template <int D, int P> struct TileShape;
 // 2D tiles hold at most 256 nodes: one node per lane of a 256-thread workgroup, so that the
