@@ -147,7 +147,9 @@ int sllbm_velset_cubature(int dim, double T0, int *Q, double *zeta, double *w, i
  * (Sec. 3.1 interpolation display, Sec. 3.3).  Built on the host and uploaded to the
  * GPU once; SLLBM_EGEOM names the offending node and velocity in the error message.
  * Without a GPU the host part is still built (sllbm_plan_info works) and every launch
- * returns SLLBM_EHIP.  GPU kernels exist for dim 2 and 3, p = 2..4, Q <= 128. */
+ * returns SLLBM_EHIP.  GPU kernels exist for dim 2 and 3, p = 2..4, Q <= 128.  A curvilinear
+ * plan holds each row's cell and source in one 32-bit word: meshes of 2^30 cells or more
+ * return SLLBM_EUNSUPPORTED. */
 int sllbm_interp_plan(sllbm_mesh m, const sllbm_velset *v, double dt, int prec, sllbm_plan *out);
 
 typedef struct {
@@ -172,8 +174,8 @@ int sllbm_plan_info(sllbm_plan p, sllbm_plan_info_t *info);
  * velocity per workgroup, walking each departure plane once along z, and a launch that forms
  * the moments from a node's streamed values held in registers and relaxes them
  * (SLLBM_EUNSUPPORTED unless the plan is 3D, periodic along z (bounded faces on x or y, whose
- * boundary layers stay on the gather kernel), on a 45-velocity set and tiled-eligible with
- * its x-y tiles of 48 x 12 nodes and a halo).  All compute the same step; the
+ * boundary layers stay on the gather kernel), on a 45- or 125-velocity set and tiled-eligible
+ * with its x-y tiles of 48 x 12 nodes and a halo).  All compute the same step; the
  * choice exists for testing and measurement. */
 int sllbm_plan_select_kernel(sllbm_plan p, int kernel);
 /* Per-kernel timing of a plan's launches (for measurement, not part of the method).

@@ -284,7 +284,7 @@ def sllbm_interp_plan(m: Mesh, velset: dict, dt: float, prec: int = SLLBM_F64) -
 
 def sllbm_plan_select_kernel(plan: Plan, kernel: int) -> None:
     """0 automatic, 1 per-node gather kernel, 2 LDS-tiled kernel, 3 LDS-tiled kernel with
-    velocity-split 3D steps (3D plans periodic along z on a 45-velocity set)."""
+    velocity-split 3D steps (3D plans periodic along z on a 45- or 125-velocity set)."""
     _check(_lib.sllbm_plan_select_kernel(plan.handle, ctypes.c_int(kernel)), "sllbm_plan_select_kernel")
 
 
