@@ -108,9 +108,9 @@ int require_device(const sllbm_plan_s *P) {
 // and fill and drain their pipelines less often.  (Measured on the 96^3 Taylor-Green mesh
 // and the 128 x 96 x 64 channel: chunks of a smaller count than this, or chunks much shorter,
 // were slower; a tiny last chunk beside long ones too.)
-int col_chunk_cells(const Mesh &m, int Q, int tx, int ty) {
+int col_chunk_cells(const Mesh &m, int Q, int tx, int ty, const int org[2], const int end[2]) {
   const int P = m.p, ncz = m.N[2] / P;
-  const int64_t tiles = (int64_t)((m.N[0] + tx - 1) / tx) * ((m.N[1] + ty - 1) / ty);
+  const int64_t tiles = (int64_t)((end[0] - org[0] + tx - 1) / tx) * ((end[1] - org[1] + ty - 1) / ty);
   const int64_t slots = 256 * 2;
   int last = 0;
   for (int nzc = 1; nzc <= ncz; nzc++) {
@@ -199,17 +199,31 @@ extern "C" int sllbm_interp_plan(sllbm_mesh ms, const sllbm_velset *v, double dt
     }
     for (int id : t.tab_reg) P->tile_tabs = std::max(P->tile_tabs, id + 1);
     if (P->tile_ok && m.dim == 3 && col_q_supported(V.Q)) {
+      // the x-y tiles cover the nodes between the bounded faces' boundary layers (which the
+      // gather kernel steps), from and to the nearest cell boundaries outside them
+      int org[2] = {0, 0}, end[2] = {(int)m.N[0], (int)m.N[1]};
+      for (int f = 0; f < t.nfaces; f++) {
+        const int a = t.face_axis[f];
+        if (a > 1) continue;
+        const int whole = t.face_depth[f] / m.p * m.p;   // whole cells inside the layers
+        if (t.face_side[f] == 0) org[a] = whole;
+        else end[a] = (int)m.N[a] - whole;
+      }
       // the widest tile that applies (two columns per thread where that pays, else one)
       for (int cpt = col_cpt(prec == SLLBM_F32 ? 4 : 8, m.p, V.Q); cpt >= 1 && !P->col_ok; cpt--) {
         int cx = 0, cy = 0, L = 0;
         if (m.p == 2) cx = ColShape<2>::CX, cy = cpt * ColShape<2>::CY, L = kColWin<2>;
         if (m.p == 3) cx = ColShape<3>::CX, cy = cpt * ColShape<3>::CY, L = kColWin<3>;
         if (m.p == 4) cx = ColShape<4>::CX, cy = cpt * ColShape<4>::CY, L = kColWin<4>;
-        const int zc = cx > 0 ? col_chunk_cells(m, V.Q, cx * m.p, cy * m.p) : 0;
-        if (zc > 0 && L > 0 && col_eligible(m, t, cx, cy, zc, L)) {
+        const int zc = cx > 0 && end[0] > org[0] && end[1] > org[1] ? col_chunk_cells(m, V.Q, cx * m.p, cy * m.p, org, end) : 0;
+        if (zc > 0 && L > 0 && col_eligible(m, t, cx, cy, zc, L, org, end)) {
           P->col_ok = 1;
           P->col_zc = zc;
           P->col_cpt = cpt;
+          for (int a = 0; a < 2; a++) {
+            P->col_org[a] = org[a];
+            P->col_end[a] = end[a];
+          }
         }
       }
     }

@@ -734,7 +734,7 @@ bool tile_cells(int D, int P, int c[3]) {
   return true;
 }
 
-bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]) {
+bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3], const int *org, const int *end) {
   int P = m.p;
   // the kernel holds byte offsets within a staged region's span of a population in 32 bits
   const int64_t span = m.dim == 3 ? (int64_t)m.N[0] * m.N[1] * (c[2] * P + P + 1)
@@ -751,10 +751,11 @@ bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]) {
     if (m.periodic(a) && N <= T + P) return false;
     std::vector<char> used(t.ntab[a], 0);
     for (size_t q = 0; q < t.tab_reg.size() / 3; q++) used[t.tab_reg[a * (t.tab_reg.size() / 3) + q]] = 1;
+    const int o = org ? org[a] : 0, e = end ? end[a] : N;
     for (int tb = 0; tb < t.ntab[a]; tb++) {
       if (!used[tb] || t.ident[a][tb]) continue;
-      for (int n0 = 0; n0 < N; n0 += T) {
-        int v = std::min(T, N - n0);
+      for (int n0 = o; n0 < e; n0 += T) {
+        int v = std::min(T, e - n0);
         int lo = 1 << 30, hi = -(1 << 30), first = 0, last = 0;
         for (int k = 0; k < v; k++) {
           int r = t.start[a][(size_t)tb * N + n0 + k] - n0;
@@ -773,7 +774,7 @@ bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]) {
   return true;
 }
 
-bool col_eligible(const Mesh &m, const HostTables &t, int cx, int cy, int zc, int L) {
+bool col_eligible(const Mesh &m, const HostTables &t, int cx, int cy, int zc, int L, const int org[2], const int end[2]) {
   const int P = m.p;
   if (m.dim != 3 || !m.periodic(2)) return false;
   // bounded axes: x or y (their boundary layers' nodes are left to the gather kernel, as in
@@ -781,7 +782,8 @@ bool col_eligible(const Mesh &m, const HostTables &t, int cx, int cy, int zc, in
   for (int f = 0; f < t.nfaces; f++)
     if (t.face_axis[f] == 2) return false;
   const int c[3] = {cx, cy, zc};
-  if (!tile_eligible(m, t, c)) return false;
+  const int o3[3] = {org[0], org[1], 0}, e3[3] = {end[0], end[1], m.N[2]};
+  if (!tile_eligible(m, t, c, o3, e3)) return false;
   // along z: the kernel emits output plane k of a chunk after source plane k + D of the
   // chunk's departure region, D the largest lag of a stencil's last plane behind its output
   // plane; stencil plane j of k then sits lag = k + D - (its first plane) planes back

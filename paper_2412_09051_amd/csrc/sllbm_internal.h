@@ -186,6 +186,8 @@ struct sllbm_plan_s {
   int col_ok = 0;               // the velocity-split 3D step applies (choice 3; automatic with the tile)
   int col_zc = 0;               // its z chunk, in cells
   int col_cpt = 1;              // its output columns per thread (the tile is that many times as long in y)
+  int col_org[2] = {0, 0};      // its x-y tiles start here (a cell boundary past a bounded face's layers)
+  int col_end[2] = {0, 0};      // and cover the nodes below this (the last interior cell boundary)
   bool use_tile() const {
     return tile_ok && (kernel_choice == 2 || kernel_choice == 3 || (kernel_choice == 0 && tile_auto));
   }
@@ -242,10 +244,13 @@ bool tile_cells(int D, int P, int c[3]);
 constexpr int64_t kTileMinTiles = 256;
 // True if every regular departure stencil of a cell-aligned tile of c[] cells stays in
 // the one-cell halo that the tiled kernel stages.
-bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3]);
+// org / end (optional): the tiles of axis a start at org[a] and cover the nodes below end[a]
+// (default: 0 and the axis length)
+bool tile_eligible(const Mesh &m, const HostTables &t, const int c[3], const int *org = nullptr,
+                   const int *end = nullptr);
 // True if the velocity-split 3D step applies with x-y tiles of cx x cy cells and z chunks of
 // zc cells: a 3D plan periodic along z (bounded faces on x or y only), every regular stencil
 // in the one-cell halo of such a tile, and along z every output plane's stencil inside the
 // window of L planes that the kernel holds when it emits that plane.
-bool col_eligible(const Mesh &m, const HostTables &t, int cx, int cy, int zc, int L);
+bool col_eligible(const Mesh &m, const HostTables &t, int cx, int cy, int zc, int L, const int org[2], const int end[2]);
 }  // namespace sllbm

@@ -1028,6 +1028,8 @@ __global__ void __launch_bounds__(kBlock) k_relax_nodes(const DevTensorPlan pl, 
 
 struct ColGrid {
   int nt0, nt1;   // x-y tiles
+  int ox, oy;     // the first tile's origin (a cell boundary; 0 unless a bounded face's layers come first)
+  int ex, ey;     // the tiles cover the nodes below these
   int zc;         // output planes per z chunk (whole cells)
   int nzc;        // chunks along z
   int q, r;       // work items (tiles x chunks x velocities) = 8 q + r (XCD remap)
@@ -1074,8 +1076,8 @@ __global__ void __launch_bounds__(BS, WPE) k_stream_col3d(const DevTensorPlan pl
   const int rest = item / ntl;
   const int zch = rest % cg.nzc;
   const int i = rest / cg.nzc;
-  const int x0 = (tl % cg.nt0) * TX, y0 = (tl / cg.nt0) * TY, z0 = zch * cg.zc;
-  const int vx = min(TX, Nx - x0), vy = min(TY, Ny - y0), vz = min(cg.zc, Nz - z0);
+  const int x0 = cg.ox + (tl % cg.nt0) * TX, y0 = cg.oy + (tl / cg.nt0) * TY, z0 = zch * cg.zc;
+  const int vx = min(TX, cg.ex - x0), vy = min(TY, cg.ey - y0), vz = min(cg.zc, Nz - z0);
   const AxGeo gx = axis_geo<P>(pl.ax[0], pl.tab_reg[i], x0, vx, TX);
   const AxGeo gy = axis_geo<P>(pl.ax[1], pl.tab_reg[Q + i], y0, vy, TY);
   const AxGeo gz = axis_geo<P>(pl.ax[2], pl.tab_reg[2 * Q + i], z0, vz, cg.zc);
@@ -1476,8 +1478,12 @@ int launch_col_t(sllbm_plan_s *Pl, const StepArgs &a, const void *pin, void *pou
   constexpr int PD = sizeof(T) == 8 ? COL_PD64 : COL_PD32;   // planes loaded ahead
   const DevTensorPlan &tp = Pl->tp;
   ColGrid cg;
-  cg.nt0 = (tp.ax[0].N + TX - 1) / TX;
-  cg.nt1 = (tp.ax[1].N + TY - 1) / TY;
+  cg.ox = Pl->col_org[0];
+  cg.oy = Pl->col_org[1];
+  cg.ex = Pl->col_end[0];
+  cg.ey = Pl->col_end[1];
+  cg.nt0 = (cg.ex - cg.ox + TX - 1) / TX;
+  cg.nt1 = (cg.ey - cg.oy + TY - 1) / TY;
   cg.zc = Pl->col_zc * P;
   cg.nzc = (tp.ax[2].N + cg.zc - 1) / cg.zc;
   const int64_t items = (int64_t)cg.nt0 * cg.nt1 * cg.nzc * tp.Q;
