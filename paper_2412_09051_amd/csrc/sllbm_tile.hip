@@ -1,23 +1,23 @@
 // LDS-tiled fused SLLBM step on tensor-product meshes (gfx950, wave64).
 //
-// One workgroup owns a cell-aligned tile of TX x TY (x TZ) nodes.  For every velocity i
-// it stages the departure region of f_i and g_i (the tile shifted by the velocity's
-// displacement, at most one cell of halo on one side per axis) from HBM into LDS, then
-// applies the separable interpolant of eq:intf as 1D passes: (p+1) multiply-adds per
-// pass and streamed value instead of (p+1)^d gathers.
-// Two launches per step: the first streams every velocity, stores the streamed f_i, g_i
-// and reduces their conserved moments per node into a small node-state array (6 doubles
-// per node); the second relaxes the stored populations in place, one node per lane.
-// Nodes in the boundary layers of a bounded face (where some departure point leaves the
-// domain, and where the isothermal-wall correction acts) are left to the per-node gather
-// kernel, launched on those slabs.
-//
-// The 2D and 3D stream kernels differ in their schedule (measured on MI355X: each is the
-// faster of the two designs for its dimension): in 2D the weight rows of every table sit
-// in LDS for the whole tile, staging uses buffer loads, and the y contraction runs per
-// node straight out of the x-pass buffer (two barriers per velocity); in 3D the x, y and
-// z passes each go through LDS and the weight rows of each velocity travel with its
-// staged region (four barriers per velocity).
+// One workgroup owns a cell-aligned tile of nodes.  For a velocity i it stages the
+// departure region of f_i and g_i (the tile shifted by the velocity's displacement, at most
+// one cell of halo on one side per axis) from HBM into LDS, then applies the separable
+// interpolant of eq:intf as 1D passes: (p+1) multiply-adds per pass and streamed value
+// instead of (p+1)^d gathers.  Nodes in the boundary layers of a bounded face (where some
+// departure point leaves the domain, and where the isothermal-wall correction acts) are left
+// to the per-node gather kernel, launched on those slabs.  Three schedules, each measured on
+// MI355X as the faster one where it applies:
+//  * 2D (k_step_tile2d): every velocity of a tile of at most 256 nodes, the weight rows of
+//    every table in LDS for the whole tile, buffer-load staging, the y contraction per node
+//    straight out of the x-pass buffer (two barriers per velocity).  With Q = 25 or 19 a
+//    node's streamed values stay in registers and the node is relaxed in the same launch.
+//  * 3D tile (k_step_tile3d): every velocity of a 3D tile, x, y and z passes through LDS
+//    (four barriers per velocity, or two with the passes of consecutive velocities skewed);
+//    it stores the streamed values and the node state, and a second launch relaxes.
+//  * velocity-split 3D (k_stream_col3d, then k_relax_moments): one velocity per workgroup
+//    on a column of output nodes walked once along z (one barrier per source plane), then a
+//    launch that forms each node's moments from its stored streamed values and relaxes them.
 #include <hip/hip_runtime.h>
 
 #include "sllbm_device_common.h"
